@@ -1,0 +1,165 @@
+"""Python entry to the FP64 CPU oracle (``sw_oracle.c``).
+
+Test infrastructure only: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark use it; the product library never does.  It shares no
+code with the GPU path.  Arrays are numpy; the C library is built with gcc on
+first use if it is not there yet.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sw_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+LEVELS_MIDPOINT = 0
+LEVELS_LEFT = 1
+MODE_ROT_TRANS = 0
+MODE_ROT_ONLY = 1
+STATUS_OK = 0
+STATUS_ZERO_MASS = 1
+STATUS_NONFINITE = 2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc -O2 -fopenmp (no SIMD intrinsics)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        lib.oracle_project.argtypes = [P, i64, i32, i32, P, P]
+        lib.oracle_project.restype = None
+        lib.oracle_quantiles.argtypes = [P, i64, i32, i32, i32, i32, P, P, P]
+        lib.oracle_quantiles.restype = None
+        lib.oracle_align.argtypes = [P, P, i64, P, P, i64, P, i64, i32, i32, i32, i32,
+                                     P, P, P, P, P]
+        lib.oracle_align.restype = None
+        lib.oracle_objective_at.argtypes = [P, P, i32, i32, i32, dbl, dbl]
+        lib.oracle_objective_at.restype = dbl
+        lib.oracle_angle_table.argtypes = [i32, P, P]
+        lib.oracle_angle_table.restype = None
+        lib.oracle_num_threads.argtypes = []
+        lib.oracle_num_threads.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def angle_table(n: int):
+    cs = np.zeros(n, np.float64)
+    sn = np.zeros(n, np.float64)
+    _load().oracle_angle_table(n, _ptr(cs), _ptr(sn))
+    return cs, sn
+
+
+def project(img: np.ndarray, n: int):
+    """Hat-weighted line projections.  img [N, L, L] float32 -> pmf [N, n, L]
+    float64 and a per-image non-finite flag [N] int32."""
+    img = np.ascontiguousarray(img, dtype=np.float32)
+    if img.ndim == 2:
+        img = img[None]
+    N, L, L2 = img.shape
+    assert L == L2
+    pmf = np.zeros((N, n, L), np.float64)
+    bad = np.zeros(N, np.int32)
+    _load().oracle_project(_ptr(img), N, L, n, _ptr(pmf), _ptr(bad))
+    return pmf, bad
+
+
+def quantiles(pmf: np.ndarray, Q: int, levels: int = LEVELS_MIDPOINT, nonfinite=None):
+    """pmf [N, n, L] -> quantile tables [N, Q, n] and aux [N, 4]
+    (mass, E, Re a, Im a)."""
+    pmf = np.ascontiguousarray(pmf, dtype=np.float64)
+    if pmf.ndim == 2:
+        pmf = pmf[None]
+    N, n, L = pmf.shape
+    qt = np.zeros((N, Q, n), np.float64)
+    aux = np.zeros((N, 4), np.float64)
+    nf = None if nonfinite is None else np.ascontiguousarray(nonfinite, dtype=np.int32)
+    _load().oracle_quantiles(_ptr(pmf), N, L, n, Q, levels, _ptr(nf), _ptr(qt), _ptr(aux))
+    return qt, aux
+
+
+def tables(img: np.ndarray, n: int, Q: int, levels: int = LEVELS_MIDPOINT):
+    """Image stack -> (qt, aux): projection followed by quantiles."""
+    pmf, bad = project(img, n)
+    return quantiles(pmf, Q, levels, bad)
+
+
+def align(ref_qt, ref_aux, img_qt, img_aux, L: int, pairs=None, mode: int = MODE_ROT_TRANS,
+          want_curve: bool = False):
+    """Exhaustive rotation scan with the closed-form translation.
+
+    Returns a dict with rot_index [P], shift_px [P, 2], sw2sq [P], status [P],
+    and curve [P, n] when requested.  Pairs default to all ref x img in
+    row-major order."""
+    ref_qt = np.ascontiguousarray(ref_qt, dtype=np.float64)
+    img_qt = np.ascontiguousarray(img_qt, dtype=np.float64)
+    ref_aux = np.ascontiguousarray(ref_aux, dtype=np.float64)
+    img_aux = np.ascontiguousarray(img_aux, dtype=np.float64)
+    if ref_qt.ndim == 2:
+        ref_qt, ref_aux = ref_qt[None], ref_aux[None]
+    if img_qt.ndim == 2:
+        img_qt, img_aux = img_qt[None], img_aux[None]
+    nr, Q, n = ref_qt.shape
+    ni = img_qt.shape[0]
+    if pairs is not None:
+        pairs = np.ascontiguousarray(pairs, dtype=np.int64).reshape(-1, 2)
+        P = pairs.shape[0]
+    else:
+        P = nr * ni
+    out_l = np.zeros(P, np.int32)
+    out_s = np.zeros((P, 2), np.float64)
+    out_d = np.zeros(P, np.float64)
+    st = np.zeros(P, np.int32)
+    curve = np.zeros((P, n), np.float64) if want_curve else None
+    _load().oracle_align(_ptr(ref_qt), _ptr(ref_aux), nr, _ptr(img_qt), _ptr(img_aux), ni,
+                         _ptr(pairs), P, L, n, Q, mode, _ptr(out_l), _ptr(out_s), _ptr(out_d),
+                         _ptr(st), _ptr(curve))
+    res = {"rot_index": out_l, "shift_px": out_s, "sw2sq": out_d, "status": st,
+           "theta_rad": 2.0 * np.pi * out_l / n}
+    if want_curve:
+        res["curve"] = curve
+    return res
+
+
+def objective_at(U, V, l: int, sx: float, sy: float) -> float:
+    """D(l, s) for one pair of tables (s in unit-disk coordinates)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    Q, n = U.shape
+    return _load().oracle_objective_at(_ptr(U), _ptr(V), n, Q, l, sx, sy)
+
+
+def align_images(ref_img, imgs, n: int, Q: int, levels: int = LEVELS_MIDPOINT,
+                 mode: int = MODE_ROT_TRANS, want_curve: bool = False):
+    """Whole path from images: one reference image against a stack."""
+    L = imgs.shape[-1]
+    rq, ra = tables(ref_img, n, Q, levels)
+    iq, ia = tables(imgs, n, Q, levels)
+    return align(rq, ra, iq, ia, L, mode=mode, want_curve=want_curve)

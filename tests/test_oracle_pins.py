@@ -1,0 +1,376 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle
+itself: closed forms stated in the paper, textbook results (Radon transform of
+a Gaussian, 1-D W2 between Gaussians), exact invariances of the discretisation
+(rotation by 90 degrees, theta + pi reversal, first moments), and brute force
+on tiny inputs.  Each test names the plausible mistake it would catch."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import erf
+from scipy.optimize import minimize
+
+import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "theorem_constants.json")))
+
+
+def blob_img(L, seed=5, K=4, spread=0.45):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = synth.blob_params(rng, K, L, spread=spread, sig_px=(2.0, 4.0))
+    return synth.finish(synth.render(*params, L), L)
+
+
+# ---------------------------------------------------------------- angle table
+def test_angle_table_values_and_symmetry(oracle):
+    for n in (8, 12, 64, 96, 128):
+        cs, sn = oracle.angle_table(n)
+        th = 2 * np.pi * np.arange(n) / n
+        assert np.max(np.abs(cs - np.cos(th))) < 1e-15
+        assert np.max(np.abs(sn - np.sin(th))) < 1e-15
+        q = n // 4
+        # quarter turn and half turn are exact
+        assert np.array_equal(cs[q:], -sn[: n - q]) and np.array_equal(sn[q:], cs[: n - q])
+        assert np.array_equal(cs[n // 2:], -cs[: n // 2]) and np.array_equal(sn[n // 2:], -sn[: n // 2])
+
+
+# ---------------------------------------------------------------- projection
+def test_projection_mass_and_first_moment(oracle):
+    """Every column carries the image mass, and its first moment is the
+    centroid projected on d_k = (cos, -sin) (hat deposits conserve both).
+    Catches a wrong sign of the detector direction, a bin-centre offset, or
+    weights that do not sum to one."""
+    L, n = 48, 24
+    img = blob_img(L)
+    pmf, _ = oracle.project(img, n)
+    h = 2.0 / L
+    ax = (np.arange(L) - 0.5 * (L - 1)) * h
+    X, Y = np.meshgrid(ax, ax)  # X varies along columns, Y along rows
+    keep = synth.disk_keep(L)
+    F = np.where(keep, img.astype(np.float64), 0.0)
+    mass = F.sum()
+    cx, cy = (F * X).sum() / mass, (F * Y).sum() / mass
+    s_b = -1.0 + (np.arange(L) + 0.5) * h
+    for k in range(n):
+        th = 2 * np.pi * k / n
+        col = pmf[0, k]
+        assert abs(col.sum() - mass) < 1e-13
+        m1 = (col * s_b).sum() / col.sum()
+        assert abs(m1 - (cx * np.cos(th) - cy * np.sin(th))) < 1e-13
+
+
+def test_projection_of_gaussian_is_gaussian(oracle):
+    """The Radon transform of an isotropic Gaussian N(c, s^2 I) is the 1-D
+    Gaussian N(c.d, s^2) at every angle (textbook).  A hat deposit is a
+    one-bin box smoothing followed by cell integration, so the cumulative sums
+    of a column must follow the Gaussian CDF with s^2 + h^2/12 at the bin edges.
+    (The density itself carries the known moire of pixel-driven projection at
+    oblique angles; the CDF, which is what W2 uses, integrates it out.)
+    Catches a transposed image axis or a wrong angle direction."""
+    n = 16
+    c = np.array([0.21, -0.13])
+    s = 0.12
+    worst = []
+    for L in (64, 128, 256):
+        img = synth.gaussian_image(L, c, s)
+        pmf, _ = oracle.project(img, n)
+        h = 2.0 / L
+        edges = -1.0 + (np.arange(L) + 1) * h
+        se = math.sqrt(s * s + h * h / 12)
+        errs = []
+        for k in range(n):
+            th = 2 * np.pi * k / n
+            mu = c[0] * np.cos(th) - c[1] * np.sin(th)
+            cdf = 0.5 * (1 + erf((edges - mu) / (math.sqrt(2) * se)))
+            got = np.cumsum(pmf[0, k]) / pmf[0, k].sum()
+            errs.append(np.max(np.abs(got - cdf)))
+        # worst at 45 degrees, where the moire makes the error first order in h
+        assert max(errs) < 0.25 * h
+        worst.append(max(errs))
+    assert worst[2] < worst[0] / 3
+
+
+def test_projection_half_turn_reversal(oracle):
+    """theta + pi reverses the detector axis: P[k + n/2][b] = P[k][L-1-b]."""
+    L, n = 40, 32
+    pmf, _ = oracle.project(blob_img(L, seed=9), n)
+    P = pmf[0]
+    assert np.max(np.abs(P[n // 2:] - P[: n // 2, ::-1])) < 1e-14
+
+
+def test_projection_quarter_turn_is_column_shift(oracle):
+    """np.rot90 of the array is the rotation R_{-pi/2} of the image in
+    (x = column, y = row) coordinates, so its projection at angle k equals the
+    original's at k - n/4.  Explicit re-projection, brute force on a tiny grid."""
+    for L, n in ((8, 8), (12, 16), (16, 12)):
+        img = blob_img(L, seed=L)
+        for m in range(1, 4):
+            P0, _ = oracle.project(img, n)
+            Pm, _ = oracle.project(np.ascontiguousarray(np.rot90(img, m)), n)
+            assert np.max(np.abs(Pm[0] - np.roll(P0[0], m * n // 4, axis=0))) < 1e-14
+
+
+def test_projection_single_pixel_centre_odd_grid(oracle):
+    """For odd L the centre pixel sits at the origin: tau = L/2 - 1/2 is an
+    integer bin at every angle, so all its mass lands in that one bin."""
+    L, n = 9, 16
+    img = np.zeros((L, L), np.float32)
+    img[L // 2, L // 2] = 2.5
+    pmf, _ = oracle.project(img, n)
+    for k in range(n):
+        assert abs(pmf[0, k, L // 2] - 2.5) < 1e-13
+        assert abs(pmf[0, k].sum() - 2.5) < 1e-13
+
+
+def test_projection_clips_and_masks(oracle):
+    """Negative pixels and pixels outside the disk of radius 1 - h are ignored;
+    a non-finite pixel is flagged."""
+    L, n = 16, 8
+    img = np.zeros((L, L), np.float32)
+    img[0, 0] = 5.0          # corner: outside the disk
+    img[8, 8] = -3.0         # negative: clipped
+    img[7, 9] = 1.0
+    pmf, bad = oracle.project(img, n)
+    assert abs(pmf[0].sum(axis=1) - 1.0).max() < 1e-14 and bad[0] == 0
+    img[3, 3] = np.nan
+    _, bad = oracle.project(img, n)
+    assert bad[0] == 1
+
+
+# ---------------------------------------------------------------- quantiles
+def test_quantiles_uniform_pmf(oracle):
+    """A uniform PMF has a linear CDF, so the quantile function is -1 + 2 z."""
+    L, n, Q = 32, 1, 20
+    pmf = np.ones((1, n, L))
+    for levels, z in ((0, (np.arange(Q) + 0.5) / Q), (1, np.arange(Q) / Q)):
+        qt, _ = oracle.quantiles(pmf, Q, levels)
+        assert np.max(np.abs(qt[0, :, 0] - (-1 + 2 * z))) < 1e-14
+
+
+def test_quantiles_point_mass_and_left_continuity(oracle):
+    """All mass in bin b: U(z) = t_b + h z.  Two separated bins with masses
+    p and 1 - p: left-continuous inverse, so U(p) is the right edge of the first
+    bin (the generalised inverse inf{t : F(t) >= z})."""
+    L, Q = 16, 8
+    h = 2.0 / L
+    pmf = np.zeros((1, 1, L))
+    pmf[0, 0, 5] = 3.0
+    qt, _ = oracle.quantiles(pmf, Q)
+    z = (np.arange(Q) + 0.5) / Q
+    assert np.max(np.abs(qt[0, :, 0] - (-1 + 5 * h + h * z))) < 1e-14
+    pmf = np.zeros((1, 1, L))
+    pmf[0, 0, 3] = 0.25
+    pmf[0, 0, 10] = 0.75
+    qt, _ = oracle.quantiles(pmf, 4, levels=1)  # z = 0, .25, .5, .75
+    t = lambda b: -1 + b * h
+    # z = 0: inf{t in [-1, 1] : F(t) >= 0} is the left end of the interval
+    exp = [-1.0, t(4), t(10) + h * (0.5 - 0.25) / 0.75, t(10) + h * (0.75 - 0.25) / 0.75]
+    assert np.max(np.abs(qt[0, :, 0] - np.array(exp))) < 1e-14
+
+
+def gauss_cells(L, m, s):
+    h = 2.0 / L
+    t = -1 + np.arange(L + 1) * h
+    cdf = 0.5 * (1 + erf((t - m) / (math.sqrt(2) * s)))
+    return np.diff(cdf)
+
+
+def test_quantiles_1d_gaussian_w2_closed_form(oracle):
+    """Textbook W2 between 1-D Gaussians: (m1 - m2)^2 + (s1 - s2)^2.  Cell
+    averages add h^2/12 to each variance.  The error must stay within the
+    paper's E3 bound (32/L) and fall faster than first order in h.
+    Catches a wrong level rule, a misplaced bin edge or a missing clamp."""
+    m1, s1, m2, s2 = -0.11, 0.09, 0.17, 0.14
+    errs = []
+    for L in (64, 128, 256):
+        h = 2.0 / L
+        pmf = np.stack([gauss_cells(L, m1, s1), gauss_cells(L, m2, s2)])[:, None, :]
+        qt, _ = oracle.quantiles(pmf, L)
+        w2 = np.mean((qt[0, :, 0] - qt[1, :, 0]) ** 2)
+        a1, a2 = math.sqrt(s1 ** 2 + h * h / 12), math.sqrt(s2 ** 2 + h * h / 12)
+        ref = (m1 - m2) ** 2 + (a1 - a2) ** 2
+        err = abs(w2 - ref)
+        assert err < GOLD["e3_bound_factor"]["value"] / L
+        errs.append(err)
+    assert errs[0] < 2e-4
+    # observed order ~1.5 (Gaussian tails make the quantile function steep)
+    assert errs[1] < errs[0] / 1.8 and errs[2] < errs[1] / 1.8
+
+
+def test_quantile_table_invariants(oracle):
+    """Nondecreasing in z, inside [-1, 1], and the half-turn symmetry
+    U[j][k + n/2] = -U[Q-1-j][k] of midpoint levels."""
+    L, n, Q = 48, 16, 24
+    qt, aux = oracle.tables(blob_img(L, seed=3), n, Q)
+    U = qt[0]
+    assert np.all(np.diff(U, axis=0) >= 0)
+    assert U.min() >= -1 and U.max() <= 1
+    assert np.max(np.abs(U[:, n // 2:] + U[::-1, : n // 2])) < 1e-12
+    assert abs(aux[0, 1] - (U ** 2).sum()) < 1e-12
+
+
+def test_translation_moment_is_half_centroid(oracle):
+    """a = (1/n) sum_k ubar_k d_k and ubar_k is the mean of column k, i.e. the
+    centroid projected on d_k; with sum_k d_k d_k^T = (n/2) I this gives
+    a = centroid / 2.  Catches a sign or factor error in the translation term."""
+    L, n, Q = 96, 32, 96
+    img = blob_img(L, seed=21)
+    _, aux = oracle.tables(img, n, Q)
+    h = 2.0 / L
+    ax = (np.arange(L) - 0.5 * (L - 1)) * h
+    F = np.where(synth.disk_keep(L), img.astype(np.float64), 0)
+    cx = (F.sum(axis=0) * ax).sum() / F.sum()
+    cy = (F.sum(axis=1) * ax).sum() / F.sum()
+    assert abs(aux[0, 2] - cx / 2) < 2e-4 and abs(aux[0, 3] - cy / 2) < 2e-4
+
+
+# ---------------------------------------------------------------- alignment
+def test_self_distance_is_zero(oracle):
+    """SW2(f, f) = 0 at l = 0 with zero translation."""
+    L, n = 32, 32
+    img = blob_img(L, seed=7)
+    r = oracle.align_images(img, img[None], n, n, want_curve=True)
+    assert r["rot_index"][0] == 0 and r["sw2sq"][0] == 0.0
+    assert np.all(r["shift_px"][0] == 0.0)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_quarter_turns_recovered_exactly(oracle, m):
+    """g = np.rot90(f, m) = R_{-m pi/2} f, hence f = R_{m pi/2} g: the scan must
+    return l* = m n / 4 with a vanishing distance and no translation."""
+    L, n = 40, 40
+    f = blob_img(L, seed=11)
+    g = np.ascontiguousarray(np.rot90(f, m))
+    r = oracle.align_images(f, g[None], n, n)
+    assert r["rot_index"][0] == (m * n // 4) % n
+    assert r["sw2sq"][0] < 1e-12 and np.all(np.abs(r["shift_px"][0]) < 1e-9)
+
+
+@pytest.mark.parametrize("di,dj", [(3, -2), (-4, 0), (1, 5)])
+def test_integer_shifts_recovered(oracle, di, dj):
+    """g[i][j] = f[i - di][j - dj] means g = T_t f with t = (dj, di) pixels, so
+    f = T_{-t} g: l* = 0 and the rounded shift is (-dj, -di)."""
+    L, n = 64, 64
+    f = blob_img(L, seed=13, spread=0.3)
+    g = np.zeros_like(f)
+    src = f[max(0, -di): L - max(0, di), max(0, -dj): L - max(0, dj)]
+    g[max(0, di): max(0, di) + src.shape[0], max(0, dj): max(0, dj) + src.shape[1]] = src
+    r = oracle.align_images(f, g[None], n, n)
+    assert r["rot_index"][0] == 0
+    assert tuple(np.round(r["shift_px"][0]).astype(int)) == (-dj, -di)
+    assert r["sw2sq"][0] < 0.02 * (2.0 / L) ** 2
+
+
+def test_two_gaussians_closed_form(oracle):
+    """f = N(c1, s1^2 I), g = N(c2, s2^2 I): every projection is a 1-D Gaussian,
+    so SW2^2 = |c1 - c2|^2 / 2 + (s1 - s2)^2 (Thm 3.2 at p = 2 plus the 1-D
+    formula).  The best translation removes the first term, and every rotation
+    ties (the designated several-correct-answers case)."""
+    L, n = 128, 64
+    c1, s1, c2, s2 = np.array([0.1, -0.05]), 0.10, np.array([-0.08, 0.12]), 0.15
+    f = synth.gaussian_image(L, c1, s1)
+    g = synth.gaussian_image(L, c2, s2)
+    rq, ra = oracle.tables(f, n, n)
+    iq, ia = oracle.tables(g, n, n)
+    r1 = oracle.align(rq, ra, iq, ia, L, mode=oracle.MODE_ROT_ONLY, want_curve=True)
+    d0 = r1["curve"][0, 0]
+    k = GOLD["sw2_translation_constant_p2"]["value"]
+    cont = k * np.sum((c1 - c2) ** 2) + (s1 - s2) ** 2
+    assert abs(d0 - cont) < 2e-4
+    # Thm 2.1 budget (App. A): angular 8 pi / n (loose) + E3 32 / L
+    assert abs(d0 - cont) < 8 * np.pi / n + 32.0 / L
+    r = oracle.align(rq, ra, iq, ia, L, want_curve=True)
+    h = 2.0 / L
+    # rotating g by theta_l about the origin moves its centre to R_l c2, so the
+    # best shift at that lag is c1 - R_l c2 (this pins the rotation direction)
+    th = r["theta_rad"][0]
+    Rc2 = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]]) @ c2
+    assert np.max(np.abs(r["shift_px"][0] * h - (c1 - Rc2))) < 2e-3
+    assert np.max(np.abs(r["curve"][0] - (s1 - s2) ** 2)) < 1e-4
+    assert np.ptp(r["curve"][0]) < 1e-5
+
+
+def test_translation_theorem_uncorrected(oracle):
+    """Thm 3.2: SW2^2(f, T_t f) = |t|^2 / 2.  Re-render a blob image with all
+    centres moved by t and read D0(0) in rotation-only mode; the discretisation
+    error shrinks with L."""
+    errs = []
+    t = np.array([0.09, -0.05])
+    for L in (32, 64, 128):
+        rng = np.random.Generator(np.random.PCG64(4))
+        cen, sig, amp = synth.blob_params(rng, 3, L, spread=0.35, sig_px=(2, 4))
+        sig = np.full(3, 0.08)
+        f = synth.finish(synth.render(cen, sig, amp, L), L)
+        g = synth.finish(synth.render(cen + t, sig, amp, L), L)
+        r = oracle.align_images(f, g[None], L, L, mode=oracle.MODE_ROT_ONLY, want_curve=True)
+        errs.append(abs(r["curve"][0, 0] - GOLD["sw2_translation_constant_p2"]["value"] * t @ t))
+    assert errs[-1] < 1e-5 and errs[-1] < errs[0]
+
+
+def test_closed_form_translation_is_the_minimiser(oracle):
+    """Brute force: minimise D(l, s) over s numerically for every l of a tiny
+    problem and compare with the closed form s* = 2 b(l), D* = D(l, s*)."""
+    L, n = 12, 12
+    f = blob_img(L, seed=31, K=3, spread=0.4)
+    g = np.ascontiguousarray(np.rot90(blob_img(L, seed=32, K=3, spread=0.4)))
+    rq, ra = oracle.tables(f, n, n)
+    iq, ia = oracle.tables(g, n, n)
+    r = oracle.align(rq, ra, iq, ia, L, want_curve=True)
+    best = None
+    for l in range(n):
+        fun = lambda s: oracle.objective_at(rq[0], iq[0], l, s[0], s[1])
+        res = minimize(fun, np.zeros(2), method="Nelder-Mead",
+                       options=dict(xatol=1e-12, fatol=1e-16, maxiter=4000))
+        assert abs(res.fun - r["curve"][0, l]) < 1e-12
+        if best is None or res.fun < best[0] - 1e-14:
+            best = (res.fun, l, res.x)
+    assert best[1] == r["rot_index"][0]
+    assert np.max(np.abs(best[2] / (2.0 / L) - r["shift_px"][0])) < 1e-5
+
+
+def test_swap_symmetry_and_scale_invariance(oracle):
+    """D*_{f,g}(l) = D*_{g,f}(-l mod n), and scaling an image changes nothing."""
+    L, n = 32, 24
+    f, g = blob_img(L, seed=41), blob_img(L, seed=42)
+    a = oracle.align_images(f, g[None], n, n, want_curve=True)["curve"][0]
+    b = oracle.align_images(g, f[None], n, n, want_curve=True)["curve"][0]
+    assert np.max(np.abs(a - b[(-np.arange(n)) % n])) < 1e-14
+    # a power-of-two scale is exact in float32, so the tables must agree to
+    # FP64 rounding; a general scale perturbs the float32 input by ~1e-7
+    c = oracle.align_images(f, (4.0 * g)[None], n, n, want_curve=True)["curve"][0]
+    assert np.max(np.abs(a - c)) < 1e-14
+    c = oracle.align_images(f, (3.7 * g)[None], n, n, want_curve=True)["curve"][0]
+    assert np.max(np.abs(a - c) / a) < 1e-6
+
+
+def test_rotated_blob_copies_recovered(oracle):
+    """Planted rotation and shift on the blob workload (no noise): the scan
+    finds the grid angle nearest the truth (within one step) and the shift to a
+    pixel."""
+    ref, imgs, th, sh = synth.make_stack(77, 64, 6, K=6, shift_px=4.0, jitter_px=0.0, snr=None)
+    n = 64
+    r = oracle.align_images(ref, imgs, n, n)
+    step = 2 * np.pi / n
+    for g in range(6):
+        dth = (r["theta_rad"][g] - th[g] + np.pi) % (2 * np.pi) - np.pi
+        assert abs(dth) <= 1.01 * step
+        assert np.max(np.abs(r["shift_px"][g] - sh[g])) < 1.0
+
+
+def test_status_codes(oracle):
+    L, n = 16, 8
+    good = blob_img(L)
+    zero = np.zeros((L, L), np.float32)
+    nan = good.copy()
+    nan[5, 5] = np.nan
+    rq, ra = oracle.tables(good, n, n)
+    iq, ia = oracle.tables(np.stack([good, zero, nan]), n, n)
+    r = oracle.align(rq, ra, iq, ia, L)
+    assert list(r["status"]) == [oracle.STATUS_OK, oracle.STATUS_ZERO_MASS, oracle.STATUS_NONFINITE]
+
+
+def test_view_stability_constant():
+    """The golden constant of Thm 3.1 at p = 2 is 1 - 4/(3 pi)."""
+    assert abs(GOLD["view_stability_constant_p2"]["value"] - (1 - 4 / (3 * math.pi))) < 1e-9
