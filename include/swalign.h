@@ -1,0 +1,169 @@
+/*
+ * swalign.h -- C ABI of the MI355X (gfx950) library for rigid alignment of
+ * images in sliced 2-Wasserstein distance.
+ *
+ * The method (Shi, Singer, Verbeke, "Fast rigid alignment of heterogeneous
+ * images in sliced Wasserstein distance"):
+ *   1. project every image onto n angles                        (Sec. 2.2-2.3)
+ *   2. turn every projection into a CDF and a table of Q quantiles  (Sec. 2.3)
+ *   3. cross-correlate two quantile tables along the angle axis by FFT, one
+ *      correlation per quantile row summed over rows               (Sec. 2.3,
+ *      fast computation over rotations)
+ *   4. correct each rotation lag with the least-squares translation, which
+ *      follows from the translation equivariance of SW2           (Thm 3.2)
+ *   5. take the argmin over the rotation grid.
+ * The problem solved for a reference f and a target g is
+ *   argmin over (s, theta) of d(f, T_s R_theta g)              (Sec. 1.1)
+ * with theta restricted to the grid 2 pi l / n.
+ *
+ * Conventions used throughout:
+ *   - images are row-major L x L float32; pixel (i, j) sits at
+ *     x = (j - (L-1)/2) h, y = (i - (L-1)/2) h, h = 2/L (x along +column,
+ *     y along +row); only pixels with x^2 + y^2 <= (1-h)^2 are used and
+ *     negative values count as 0;
+ *   - angle k is theta_k = 2 pi k / n; detector bin b has centre
+ *     -1 + (b + 1/2) h; quantile level j is (j + 1/2)/Q (or j/Q);
+ *   - a result (rot_index = l, shift_px = s) means f ~ T_s R_theta g with
+ *     theta = 2 pi l / n; sw2sq is the squared distance (1/(nQ)) times the
+ *     squared Frobenius norm of the table difference (Sec. 2.3).
+ *
+ * Memory: every array argument is a DEVICE pointer unless marked "host".  The
+ * caller owns all arrays it passes; the library never frees them.  The
+ * library owns its scratch (angle spectra, tables), released by
+ * sw_ctx_destroy.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * Compute calls are asynchronous on that stream.  One context's scratch is
+ * shared by its calls: calls on one context must be issued on one stream (or
+ * otherwise ordered); use one context per concurrent stream.
+ *
+ * Errors: every call returns sw_status; no C++ exception crosses the ABI.
+ * sw_last_error() returns a thread-local message for the last failure.
+ * Whole-call errors (bad geometry, null pointers, device failures) fail the
+ * call; per-image problems (zero mass after clipping and masking, a
+ * non-finite pixel) are reported in sw_result.status and the call succeeds.
+ */
+#ifndef SWALIGN_H
+#define SWALIGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SW_OK = 0,
+    SW_NOT_READY = 1,      /* serving: result not finished yet */
+    SW_E_INVALID = -1,     /* bad argument or geometry */
+    SW_E_NOMEM = -2,       /* allocation failed, or a request exceeds the budget */
+    SW_E_DEVICE = -3,      /* HIP runtime error */
+    SW_E_UNSUPPORTED = -4, /* valid but not implemented combination */
+    SW_E_BUSY = -5         /* serving queue full (back-pressure) */
+} sw_status;
+
+/* Quantile levels z_j: midpoint (j + 1/2)/Q (default) or left j/Q, the
+   left Riemann sum of the paper's error analysis (App. A, E3). */
+typedef enum { SW_LEVELS_MIDPOINT = 0, SW_LEVELS_LEFT = 1 } sw_levels;
+
+/* Rotation + closed-form translation (default), or rotation only, which is
+   the paper's own objective (Sec. 2.3, discrete SW2 over rotations). */
+typedef enum { SW_MODE_ROT_TRANS = 0, SW_MODE_ROT_ONLY = 1 } sw_mode;
+
+/* FP32 everywhere, or FP32 tables with a BF16 correlation (FP32 accumulate)
+   and an FP32 rescore of the top_k lags. */
+typedef enum { SW_PREC_FP32 = 0, SW_PREC_BF16_SPLIT = 1 } sw_precision;
+
+/* Per-result status: zero mass after clipping and masking, a non-finite
+   input value, or a pair index outside the table sets. */
+enum { SW_RESULT_OK = 0, SW_RESULT_ZERO_MASS = 1, SW_RESULT_NONFINITE = 2, SW_RESULT_BAD_PAIR = 3 };
+
+/* Geometry.  Valid: 8 <= L <= 256; n_angles a multiple of 8, at most 512,
+   whose only prime factors are 2 and 3; n_quantiles a multiple of 4 in
+   [8, 512]. */
+typedef struct {
+    int32_t L;
+    int32_t n_angles;
+    int32_t n_quantiles;
+    int32_t levels; /* sw_levels */
+} sw_geom;
+
+/* One alignment result (24 bytes). */
+typedef struct {
+    int32_t rot_index;  /* l* in [0, n) */
+    float theta_rad;    /* 2 pi l* / n */
+    float shift_px[2];  /* s* in pixels: [0] along +column (x), [1] along +row (y) */
+    float sw2sq;        /* squared SW2 at (l*, s*), unit-disk coordinates */
+    int32_t status;     /* SW_RESULT_* */
+} sw_result;
+
+/* Context: binds a device and owns scratch.  tune_json (host, nullable) is a
+   path to a tile table written by the autotuner. */
+sw_status sw_ctx_create(void **ctx, int device, const char *tune_json);
+sw_status sw_ctx_destroy(void *ctx);
+const char *sw_last_error(void);
+const char *sw_version(void);
+
+/* Step 1, line projection (Sec. 2.2 Radon transform, Sec. 2.3 columns of U).
+   pmf[g][k][b] = sum over masked pixels of max(F,0) * max(0, 1 - |p.d_k - c_b|/h)
+   with d_k = (cos theta_k, -sin theta_k) and c_b the centre of bin b: each
+   pixel deposits its value into the two bins around its projected position
+   by linear interpolation.  Unnormalised (column sums equal the image mass).
+   img: [N][L][L] float32, pmf: [N][n][L] float32 (caller-allocated).
+   An image holding a non-finite value yields an all-NaN projection. */
+sw_status sw_project(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/,
+                     float *pmf, void *stream);
+
+/* Step 2, CDF and quantile table (Sec. 2.3: cumulative sums, then ICDF by
+   linear interpolation; generalised inverse inf{t : F(t) >= z}, App. A).
+   Per column k: C[b] = (sum_{b'<=b} pmf[k][b'])/m_k accumulated in FP64,
+   b* = min{b : C[b] >= z_j}, qt[j][k] = t_{b*} + h (z_j - C[b*-1]) /
+   (C[b*] - C[b*-1]) clamped to the bin, t_b = -1 + b h.
+   pmf: [N][n][L] float32, qt: [N][Q][n] float32.
+   aux (nullable): [N][4] float64 = { mass (NaN if non-finite), E = sum qt^2,
+   Re a, Im a } with a = (1/n) sum_k qbar_k (cos theta_k, -sin theta_k),
+   qbar_k the mean of column k (the translation moment). */
+sw_status sw_quantiles(void *ctx, const float *pmf, int64_t N, const sw_geom *g /*host*/,
+                       float *qt, double *aux, void *stream);
+
+/* Steps 1 and 2 fused: images straight to quantile tables, the projection
+   never leaving the chip.  Same outputs as sw_project followed by
+   sw_quantiles. */
+sw_status sw_tables(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/, float *qt,
+                    double *aux, void *stream);
+
+/* Steps 3-5: alignment of table pairs.
+   For each pair (r, g): the angle spectra of both tables, the correlation
+   C(l) = sum_{j,k} U[j][k] V[j][(k+l) mod n] for all l by FFT along the angle
+   axis, D0(l) = (E_U + E_V - 2 C(l))/(nQ), b(l) = a_U - e^{i theta_l} a_V,
+   s*(l) = 2 b(l), D*(l) = D0(l) - 2|b(l)|^2 (ROT_TRANS) or D0(l)
+   (ROT_ONLY), l* = argmin D*(l) (ties to the smallest l), then sw2sq
+   recomputed at (l*, s*) as a direct FP32 residual sum.  With top_k > 1
+   the top_k lags are rescored and the smallest rescored value wins.
+   pairs: [n_pairs][2] int64 (ref index, img index) or NULL for all
+   ref x img in row-major order (pair p = r * n_img + g).
+   out: [P] sw_result; curve (nullable): [P][n] float32, D*(l). */
+typedef struct {
+    const float *ref_qt;   /* [n_ref][Q][n] */
+    const double *ref_aux; /* [n_ref][4] */
+    int64_t n_ref;
+    const float *img_qt;   /* [n_img][Q][n] */
+    const double *img_aux; /* [n_img][4] */
+    int64_t n_img;
+    const int64_t *pairs;  /* [n_pairs][2] or NULL */
+    int64_t n_pairs;
+    sw_geom geom;
+    int32_t mode;          /* sw_mode */
+    int32_t prec;          /* sw_precision */
+    int32_t top_k;         /* 1..8; 0 means 1 for FP32 and 4 for BF16_SPLIT */
+} sw_batch;
+
+sw_status sw_align_batch(void *ctx, const sw_batch *b /*host*/, sw_result *out, float *curve,
+                         void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWALIGN_H */

@@ -1,0 +1,86 @@
+"""ctypes declarations of libswalign's C ABI (include/swalign.h).
+
+Argument marshalling only: every computation runs in the HIP kernels of the
+library.  Loading fails loudly when the library has not been built."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswalign.so")
+
+SW_OK, SW_NOT_READY, SW_E_INVALID, SW_E_NOMEM, SW_E_DEVICE, SW_E_UNSUPPORTED, SW_E_BUSY = (
+    0, 1, -1, -2, -3, -4, -5)
+LEVELS_MIDPOINT, LEVELS_LEFT = 0, 1
+MODE_ROT_TRANS, MODE_ROT_ONLY = 0, 1
+PREC_FP32, PREC_BF16_SPLIT = 0, 1
+RESULT_OK, RESULT_ZERO_MASS, RESULT_NONFINITE = 0, 1, 2
+
+STATUS_NAMES = {0: "SW_OK", 1: "SW_NOT_READY", -1: "SW_E_INVALID", -2: "SW_E_NOMEM",
+                -3: "SW_E_DEVICE", -4: "SW_E_UNSUPPORTED", -5: "SW_E_BUSY"}
+
+
+class sw_geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("n_angles", ctypes.c_int32),
+                ("n_quantiles", ctypes.c_int32), ("levels", ctypes.c_int32)]
+
+
+class sw_result(ctypes.Structure):
+    _fields_ = [("rot_index", ctypes.c_int32), ("theta_rad", ctypes.c_float),
+                ("shift_px", ctypes.c_float * 2), ("sw2sq", ctypes.c_float),
+                ("status", ctypes.c_int32)]
+
+
+class sw_batch(ctypes.Structure):
+    _fields_ = [("ref_qt", ctypes.c_void_p), ("ref_aux", ctypes.c_void_p),
+                ("n_ref", ctypes.c_int64), ("img_qt", ctypes.c_void_p),
+                ("img_aux", ctypes.c_void_p), ("n_img", ctypes.c_int64),
+                ("pairs", ctypes.c_void_p), ("n_pairs", ctypes.c_int64),
+                ("geom", sw_geom), ("mode", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("top_k", ctypes.c_int32)]
+
+
+class SwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+# (name, restype, argtypes) of every exported entry point
+P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+SIGNATURES = [
+    ("sw_ctx_create", I32, [ctypes.POINTER(ctypes.c_void_p), I32, ctypes.c_char_p]),
+    ("sw_ctx_destroy", I32, [P]),
+    ("sw_last_error", ctypes.c_char_p, []),
+    ("sw_version", ctypes.c_char_p, []),
+    ("sw_project", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P]),
+    ("sw_quantiles", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
+    ("sw_tables", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
+    ("sw_align_batch", I32, [P, ctypes.POINTER(sw_batch), P, P, P]),
+]
+
+_lib = None
+
+
+def load():
+    """Load libswalign.so (built in-tree by paper_2503_13756_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2503_13756_amd.build` "
+                "(there is no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(status):
+    if status != SW_OK:
+        raise SwError(status, load().sw_last_error().decode(errors="replace"))
+    return status

@@ -1,0 +1,54 @@
+// Kernel and launcher of the stand-alone line projection (images -> PMF
+// tables); the device routines are in proj_dev.h.
+#include "proj_dev.h"
+
+namespace sw {
+
+template <int NT, int TPW>
+__global__ __launch_bounds__(NT) void k_project(const float *__restrict__ img, int64_t N,
+                                                ProjShape P, const float2 *__restrict__ dtab,
+                                                float *__restrict__ pmf) {
+    extern __shared__ float lds[];
+    const int64_t g = blockIdx.x;
+    if (g >= N) return;
+    const float *F = img + g * (int64_t)P.L * P.L;
+    float *out = pmf + g * (int64_t)P.n * P.L;
+    int bad = 0;
+    project_image<NT, TPW>(F, P, dtab, lds, bad,
+                           [&](int k, int b, float v) { out[k * P.L + b] = v; });
+    if (bad) {
+        // an image with a non-finite value gets an all-NaN projection
+        __syncthreads();
+        for (int t = threadIdx.x; t < P.n * P.L; t += NT) out[t] = __int_as_float(0x7fc00000);
+    }
+}
+
+template <int NT, int TPW>
+static hipError_t launch_project_t(const float *img, int64_t N, const ProjShape &P,
+                                   const float2 *dtab, float *pmf, hipStream_t s) {
+    const size_t lds = sizeof(float) * 2 * P.R * P.S;
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_project<NT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    (void)attr;
+    hipLaunchKernelGGL((k_project<NT, TPW>), dim3((unsigned)N), dim3(NT), lds, s, img, N, P, dtab,
+                       pmf);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &t, float *pmf,
+                          hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    constexpr int kLdsFloats = 16384;  // 64 KiB: two blocks per CU
+    ProjShape P = proj_shape(g.L, g.n, kLdsFloats);
+    const int tpw256 = tasks_per_wave(P.items, 256);
+    if (tpw256 <= 4) return launch_project_t<256, 4>(img, N, P, t.d32, pmf, s);
+    if (tpw256 <= 8) return launch_project_t<256, 8>(img, N, P, t.d32, pmf, s);
+    if (tpw256 <= 12) return launch_project_t<256, 12>(img, N, P, t.d32, pmf, s);
+    const int tpw512 = tasks_per_wave(P.items, 512);
+    if (tpw512 <= 12) return launch_project_t<512, 12>(img, N, P, t.d32, pmf, s);
+    const int tpw1024 = tasks_per_wave(P.items, 1024);
+    if (tpw1024 <= 12) return launch_project_t<1024, 12>(img, N, P, t.d32, pmf, s);
+    return launch_project_t<1024, 20>(img, N, P, t.d32, pmf, s);
+}
+
+}  // namespace sw

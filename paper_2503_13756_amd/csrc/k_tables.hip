@@ -1,0 +1,137 @@
+// Fused projection + CDF/quantile stage: one block turns one image into its
+// quantile table without the projection leaving the chip.  The projection
+// accumulates in registers across LDS image strips (proj_dev.h); after the
+// last strip the block writes the PMF table into the same LDS region and
+// inverts its columns there (quant_dev.h).  Results are identical in form to
+// the stand-alone projection followed by the stand-alone quantile stage.
+#include "proj_dev.h"
+#include "quant_dev.h"
+
+namespace sw {
+
+struct TablesShape {
+    ProjShape P;
+    int Q, levels, TC;
+    int region_floats;  // max(strip buffers, PMF table), a multiple of 2
+};
+
+template <int NT, int TPW>
+__global__ __launch_bounds__(NT) void k_tables(const float *__restrict__ img, int64_t N,
+                                               TablesShape T, const float2 *__restrict__ d32,
+                                               const double2 *__restrict__ d64,
+                                               float *__restrict__ qt, double *__restrict__ aux) {
+    constexpr int NW = NT / 64;
+    extern __shared__ double ldsd[];
+    __shared__ double red[NW][4];
+    const int64_t g = blockIdx.x;
+    if (g >= N) return;
+    const ProjShape &P = T.P;
+    const int L = P.L, n = P.n, Q = T.Q, TC = T.TC;
+    float *region = (float *)ldsd;
+    double *C0 = ldsd + T.region_floats / 2;
+    float *Ut = (float *)(C0 + NW * (L + 1));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    const float *F = img + g * (int64_t)L * L;
+    int bad = 0;
+    project_image<NT, TPW>(F, P, d32, region, bad,
+                           [&](int k, int b, float v) { region[k * L + b] = v; });
+    if (bad)
+        for (int t = threadIdx.x; t < n * L; t += NT) region[t] = __int_as_float(0x7fc00000);
+    __syncthreads();
+
+    double *C = C0 + wave * (L + 1);
+    const int ldt = TC + 1;
+    float *U = qt + g * (int64_t)Q * n;
+    double E = 0.0, ar = 0.0, ai = 0.0, mass0 = 0.0;
+    for (int k0 = 0; k0 < n; k0 += TC) {
+        for (int kl = wave; kl < TC; kl += NW) {
+            const int k = k0 + kl;
+            const float *colp = region + k * L;
+            double su, sq;
+            const double mass = invert_column([&](int b) { return colp[b]; }, L, Q, T.levels, C, Ut,
+                                              ldt, kl, lane, &su, &sq);
+            if (k == 0) mass0 = mass;
+            su = wave_sum_d(su);
+            sq = wave_sum_d(sq);
+            const double qbar = su / (double)Q;
+            const double2 d = d64[k];
+            E += sq;
+            ar += qbar * d.x;
+            ai += qbar * d.y;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < Q * TC; idx += NT) {
+            const int j = idx / TC, kl = idx - j * TC;
+            U[(int64_t)j * n + k0 + kl] = Ut[j * ldt + kl];
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        red[wave][0] = E;
+        red[wave][1] = ar;
+        red[wave][2] = ai;
+        red[wave][3] = mass0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && aux) {
+        double e = 0, x = 0, y = 0;
+        for (int w = 0; w < NW; ++w) {
+            e += red[w][0];
+            x += red[w][1];
+            y += red[w][2];
+        }
+        double *A = aux + 4 * g;
+        A[0] = red[0][3];
+        A[1] = e;
+        A[2] = x / (double)n;
+        A[3] = y / (double)n;
+    }
+}
+
+// Bytes of LDS the fused kernel needs for a geometry (0 when it cannot run).
+size_t tables_lds_bytes(Geo g, int nt, TablesShape *out) {
+    constexpr int kStripFloats = 16384;
+    TablesShape T;
+    T.P = proj_shape(g.L, g.n, kStripFloats);
+    T.Q = g.Q;
+    T.levels = g.levels;
+    int region = 2 * T.P.R * T.P.S;
+    if (region < g.n * g.L) region = g.n * g.L;
+    region = (region + 1) & ~1;
+    T.region_floats = region;
+    const size_t fixed = sizeof(float) * region + sizeof(double) * (nt / 64) * (g.L + 1);
+    const size_t budget = 150 * 1024;
+    if (fixed + sizeof(float) * g.Q * 9 > budget) return 0;
+    T.TC = pick_tc(g.n, g.Q, budget - fixed);
+    if (out) *out = T;
+    return fixed + sizeof(float) * g.Q * (T.TC + 1);
+}
+
+bool tables_fused_fits(Geo g) { return tables_lds_bytes(g, 256, nullptr) != 0; }
+
+template <int NT, int TPW>
+static hipError_t launch_tables_t(const float *img, int64_t N, const TablesShape &T, size_t lds,
+                                  const AngleTable &t, float *qt, double *aux, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_tables<NT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
+    (void)attr;
+    hipLaunchKernelGGL((k_tables<NT, TPW>), dim3((unsigned)N), dim3(NT), lds, s, img, N, T, t.d32,
+                       t.d64, qt, aux);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t, float *qt,
+                         double *aux, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    TablesShape T;
+    const size_t lds = tables_lds_bytes(g, 256, &T);
+    if (lds == 0) return hipErrorInvalidValue;  // caller checks tables_lds_bytes first
+    const int tpw = tasks_per_wave(T.P.items, 256);
+    if (tpw <= 4) return launch_tables_t<256, 4>(img, N, T, lds, t, qt, aux, s);
+    if (tpw <= 8) return launch_tables_t<256, 8>(img, N, T, lds, t, qt, aux, s);
+    if (tpw <= 12) return launch_tables_t<256, 12>(img, N, T, lds, t, qt, aux, s);
+    return launch_tables_t<256, 20>(img, N, T, lds, t, qt, aux, s);
+}
+
+}  // namespace sw

@@ -1,0 +1,213 @@
+// Line projection of images (the Radon transform of Sec. 2.2, discretised
+// as a hat-weighted line sum, i.e. pixel-driven linear interpolation onto the
+// detector bins).
+//
+// Formulation on the GPU: gather, atomic-free.  A lane owns one output bin b
+// of one "slot" angle theta in [0, pi/4] and walks the image rows.  In row i
+// the line of bin b crosses the row at column u = (b - c0 + s (i - c0))/c + c0
+// (c = cos theta >= s = sin theta), and the pixels with non-zero weight are
+// the four columns floor(u) - 1 .. floor(u) + 2 (at most three of them are
+// non-zero because the pixel spacing along the detector is c >= 1/sqrt 2
+// bins).  The four hat weights are shared by four angles of the same orbit
+// under the symmetries of the square pixel grid:
+//   theta        : F[i][j]            -> bin b
+//   pi/2 - theta : F[j][i]            -> bin L-1-b
+//   pi - theta   : F[i][L-1-j]        -> bin b
+//   pi/2 + theta : F[L-1-j][i]        -> bin b
+// and theta + pi is the reversed projection of theta.  So one set of weights
+// per (slot, bin, row) feeds up to eight output columns; the angle table is
+// built with these symmetries exact.
+//
+// The image is staged through LDS in strips of R rows together with the same
+// R columns transposed, so that all four variants read along LDS rows (lanes
+// take consecutive bins, hence near-consecutive columns: conflict-light with
+// an odd row stride).  Accumulators live in registers across strips.
+#pragma once
+#include "sw_internal.h"
+
+namespace sw {
+
+__device__ __forceinline__ bool in_disk(int L, int i, int j) {
+    // x^2 + y^2 <= (1 - h)^2 in exact integer form
+    const int a = 2 * j - L + 1, b = 2 * i - L + 1, r = L - 2;
+    return a * a + b * b <= r * r;
+}
+
+struct ProjShape {
+    int L, n, S, R, slots, items;
+};
+
+__host__ inline ProjShape proj_shape(int L, int n, int lds_floats) {
+    ProjShape p;
+    p.L = L;
+    p.n = n;
+    p.S = strip_stride(L);
+    p.R = lds_floats / (2 * p.S);
+    if (p.R > L) p.R = L;
+    p.slots = n / 8 + 1;
+    p.items = p.slots * L;
+    return p;
+}
+
+// Stage image rows [i0, i0 + rows) into Srow[r][S] and image columns
+// [i0, i0 + rows) transposed into Tcol[r][S]; masked, clipped, zero padded.
+template <int NT>
+__device__ void stage_strip(const float *__restrict__ F, const ProjShape &P, int i0, int rows,
+                            float *Srow, float *Tcol, int &bad) {
+    const int L = P.L, S = P.S;
+    for (int r = 0; r < rows; ++r) {
+        const int i = i0 + r;
+        for (int jj = threadIdx.x; jj < S; jj += NT) {
+            const int j = jj - kPadLeft;
+            float v = 0.f;
+            if (j >= 0 && j < L) {
+                const float x = F[(size_t)i * L + j];
+                if (!isfinite(x)) bad = 1;
+                if (in_disk(L, i, j) && x > 0.f) v = x;
+            }
+            Srow[r * S + jj] = v;
+        }
+    }
+    // threads as (column block, row): consecutive threads read consecutive
+    // image columns of one image row
+    const int per = NT / rows;  // rows <= NT is guaranteed by the launcher
+    const int r = threadIdx.x % rows;
+    const int jb = threadIdx.x / rows;
+    if (jb < per) {
+        for (int jj = jb; jj < S; jj += per) {
+            const int j = jj - kPadLeft;
+            float v = 0.f;
+            if (j >= 0 && j < L) {
+                const int i = i0 + r;
+                const float x = F[(size_t)j * L + i];
+                if (in_disk(L, j, i) && x > 0.f) v = x;
+            }
+            Tcol[r * S + jj] = v;
+        }
+    }
+}
+
+// Per-lane constants of one task (slot angle, bin).
+struct LaneTask {
+    float c, omc, om2c, r, A;
+};
+
+__device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *dtab, int item) {
+    LaneTask t;
+    if (item < P.items) {
+        const int slot = item / P.L, b = item - slot * P.L;
+        const float2 d = dtab[slot];
+        const float c = d.x, s = -d.y;
+        const float c0 = 0.5f * (float)(P.L - 1);
+        t.c = c;
+        t.r = s / c;
+        // u(i) = A + i * r
+        t.A = ((float)b - c0) / c + c0 - c0 * t.r;
+    } else {
+        t.c = 1.f;
+        t.r = 0.f;
+        t.A = -100.f;  // clamps to the zero padding
+    }
+    t.omc = 1.f - t.c;
+    t.om2c = 1.f - 2.f * t.c;
+    return t;
+}
+
+template <int TPW>
+__device__ __forceinline__ void accumulate_strip(const ProjShape &P, const float *Srow,
+                                                 const float *Tcol, int i0, int rows,
+                                                 const LaneTask (&tk)[TPW], float (&acc)[TPW][4]) {
+    const int L = P.L, S = P.S;
+    const float hi = (float)L + 0.5f;
+    for (int rr = 0; rr < rows; ++rr) {
+        const float fi = (float)(i0 + rr);
+        const float *rowS = Srow + rr * S + kPadLeft;
+        const float *rowT = Tcol + rr * S + kPadLeft;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            float u = fmaf(fi, tk[t].r, tk[t].A);
+            u = fminf(fmaxf(u, -1.5f), hi);
+            const float jf = floorf(u);
+            const float cf = tk[t].c * (u - jf);
+            const int jA = (int)jf;
+            const float w0 = fmaxf(0.f, tk[t].omc - cf);   // column jA - 1
+            const float w1 = 1.f - cf;                      // column jA
+            const float w2 = tk[t].omc + cf;                // column jA + 1
+            const float w3 = fmaxf(0.f, tk[t].om2c + cf);  // column jA + 2
+            const float *a = rowS + jA;
+            const float *b = rowT + jA;
+            const float *fa = rowS + (L - 1 - jA);
+            const float *fb = rowT + (L - 1 - jA);
+            acc[t][0] += w0 * a[-1] + w1 * a[0] + w2 * a[1] + w3 * a[2];
+            acc[t][1] += w0 * b[-1] + w1 * b[0] + w2 * b[1] + w3 * b[2];
+            acc[t][2] += w0 * fa[1] + w1 * fa[0] + w2 * fa[-1] + w3 * fa[-2];
+            acc[t][3] += w0 * fb[1] + w1 * fb[0] + w2 * fb[-1] + w3 * fb[-2];
+        }
+    }
+}
+
+// Walk one output value per (task, variant) to its columns, including the
+// theta + pi mirror.  Emit(k, b, value) is called for each produced column.
+template <int TPW, typename Emit>
+__device__ __forceinline__ void emit_outputs(const ProjShape &P, int wave, int nwaves, int lane,
+                                             const float (&acc)[TPW][4], Emit emit) {
+    const int L = P.L, n = P.n, q = n / 4, h = n / 2, o = n / 8;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int item = (wave + t * nwaves) * 64 + lane;
+        if (item >= P.items) continue;
+        const int k = item / L, b = item - k * L;
+        // variant 0: angle k, bin b
+        emit(k, b, acc[t][0]);
+        emit(k + h, L - 1 - b, acc[t][0]);
+        if (k != o) {  // variant 1: angle n/4 - k, bin L-1-b
+            emit(q - k, L - 1 - b, acc[t][1]);
+            emit(q - k + h, b, acc[t][1]);
+        }
+        if (k != 0) {  // variant 2: angle n/2 - k, bin b
+            emit(h - k, b, acc[t][2]);
+            emit(n - k, L - 1 - b, acc[t][2]);
+        }
+        if (k != 0 && k != o) {  // variant 3: angle n/4 + k, bin b
+            emit(q + k, b, acc[t][3]);
+            emit(q + k + h, L - 1 - b, acc[t][3]);
+        }
+    }
+}
+
+// Full projection of one image held in LDS strips; results handed to emit.
+template <int NT, int TPW, typename Emit>
+__device__ void project_image(const float *__restrict__ F, const ProjShape &P,
+                              const float2 *__restrict__ dtab, float *lds, int &bad_out,
+                              Emit emit) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    LaneTask tk[TPW];
+    float acc[TPW][4];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        tk[t] = make_task(P, dtab, (wave + t * NW) * 64 + lane);
+        acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0.f;
+    }
+    float *Srow = lds;
+    float *Tcol = lds + P.R * P.S;
+    int bad = 0;
+    for (int i0 = 0; i0 < P.L; i0 += P.R) {
+        const int rows = min(P.R, P.L - i0);
+        __syncthreads();
+        stage_strip<NT>(F, P, i0, rows, Srow, Tcol, bad);
+        __syncthreads();
+        accumulate_strip<TPW>(P, Srow, Tcol, i0, rows, tk, acc);
+    }
+    bad_out = __syncthreads_or(bad);
+    emit_outputs<TPW>(P, wave, NW, lane, acc, emit);
+}
+
+// Tasks (64 consecutive work items) per wave for a block of nt threads.
+inline int tasks_per_wave(int items, int nt) {
+    const int tasks = (items + 63) / 64;
+    const int nw = nt / 64;
+    return (tasks + nw - 1) / nw;
+}
+
+}  // namespace sw

@@ -1,0 +1,73 @@
+// Internal declarations shared by the kernels and the host runtime of
+// libswalign.  Not part of the public ABI (include/swalign.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sw {
+
+constexpr int kMaxL = 256;
+constexpr int kMaxN = 512;
+constexpr int kMaxQ = 512;
+constexpr int kMaxTopK = 8;
+
+// Row padding of the LDS image strips: three zero columns on the left, the
+// rest on the right, total stride odd so that both row-wise and column-wise
+// lane patterns spread over the LDS banks.
+constexpr int kPadLeft = 3;
+__host__ __device__ inline int strip_stride(int L) { return (L + 7) | 1; }
+
+struct Geo {
+    int L, n, Q, levels;
+};
+
+// Device copy of the angle table of one n: d[m] = (cos theta_m, -sin theta_m),
+// theta_m = 2 pi m / n, which is also the forward DFT twiddle e^{-2 pi i m/n}.
+struct AngleTable {
+    int n = 0;
+    float2 *d32 = nullptr;   // [n]
+    double2 *d64 = nullptr;  // [n]
+};
+
+// Result record, identical in layout to sw_result.
+struct Result {
+    int32_t rot_index;
+    float theta_rad;
+    float shift_px[2];
+    float sw2sq;
+    int32_t status;
+};
+static_assert(sizeof(Result) == 24, "sw_result is 24 bytes");
+
+// ---- launchers (each returns hipGetLastError() after its launches) ----
+hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &t, float *pmf,
+                          hipStream_t s);
+hipError_t launch_quantiles(const float *pmf, int64_t N, Geo g, const AngleTable &t, float *qt,
+                            double *aux, hipStream_t s);
+// Fused image -> quantile table; only for geometries where
+// tables_fused_fits() holds (the PMF table must fit in LDS).
+bool tables_fused_fits(Geo g);
+hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t, float *qt,
+                         double *aux, hipStream_t s);
+// Angle spectra of quantile tables: spec[g][w][j] complex, w in [0, n/2],
+// j in [0, Q); bf16 != 0 stores bfloat16 pairs instead of float pairs.
+hipError_t launch_spectrum(const float *qt, int64_t N, Geo g, const AngleTable &t, void *spec,
+                           int bf16, hipStream_t s);
+struct PairArgs {
+    const float *ref_qt;
+    const double *ref_aux;
+    const float2 *ref_spec;  // FP32 spectra of the references
+    int64_t n_ref;
+    const float *img_qt;
+    const double *img_aux;
+    int64_t n_img;
+    const int64_t *pairs;  // nullable
+    int64_t n_pairs;
+    int mode, bf16, top_k;
+    Result *out;
+    float *curve;  // nullable
+};
+hipError_t launch_align_pairs(const PairArgs &a, Geo g, const AngleTable &t, hipStream_t s);
+
+}  // namespace sw

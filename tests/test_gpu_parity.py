@@ -1,0 +1,209 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle on the
+same seeded inputs, element by element, through the C ABI.
+
+Sizes span several tiles and ragged tails: L in {16, 40, 64, 96, 128, 192,
+256}, n with radix 3 (24, 96, 192), Q != n, both level rules, both modes,
+explicit pair lists and top-k rescoring."""
+import numpy as np
+import pytest
+
+import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2503_13756_amd import api as A
+
+    return A
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def blob_stack(L, N, seed, snr=1.0):
+    ref, imgs, _, _ = synth.make_stack(seed, L, N, K=6, shift_px=max(1.0, L / 16), jitter_px=1.0,
+                                       snr=snr)
+    return ref, imgs
+
+
+GEOMS = [(16, 16, 16), (40, 24, 20), (64, 64, 64), (96, 96, 96), (128, 128, 128),
+         (64, 128, 48), (192, 192, 192), (256, 256, 256)]
+
+
+@pytest.mark.parametrize("L,n,Q", GEOMS)
+def test_project_parity(api, ctx, oracle, L, n, Q):
+    ref, imgs = blob_stack(L, 5, 100 + L)
+    imgs = np.concatenate([imgs, synth.uniform_images(7, L, 2)])
+    pmf = api.project(ctx, dev(imgs), n).cpu().numpy()
+    P0, _ = oracle.project(imgs, n)
+    err = np.abs(pmf - P0).max(axis=(1, 2)) / P0.max(axis=(1, 2))
+    assert err.max() < 1e-5, err
+
+
+@pytest.mark.parametrize("L,n,Q", GEOMS)
+@pytest.mark.parametrize("levels", [0, 1])
+def test_quantile_parity(api, ctx, oracle, L, n, Q, levels):
+    _, imgs = blob_stack(L, 4, 200 + L)
+    P0, _ = oracle.project(imgs, n)
+    pmf32 = P0.astype(np.float32)
+    qt, aux = api.quantiles(ctx, dev(pmf32), Q, levels)
+    q0, a0 = oracle.quantiles(pmf32.astype(np.float64), Q, levels)
+    qt, aux = qt.cpu().numpy(), aux.cpu().numpy()
+    assert np.abs(qt - q0).max() < 2e-6
+    assert np.allclose(aux[:, 0], a0[:, 0], rtol=1e-12)
+    assert np.allclose(aux[:, 1], a0[:, 1], rtol=1e-6)
+    assert np.abs(aux[:, 2:] - a0[:, 2:]).max() < 1e-6
+
+
+@pytest.mark.parametrize("L,n,Q", GEOMS)
+def test_tables_fused_equals_staged(api, ctx, L, n, Q):
+    _, imgs = blob_stack(L, 6, 300 + L)
+    x = dev(imgs)
+    q1, a1 = api.tables(ctx, x, n, Q)
+    q2, a2 = api.quantiles(ctx, api.project(ctx, x, n), Q)
+    assert np.array_equal(q1.cpu().numpy(), q2.cpu().numpy())
+    assert np.array_equal(a1.cpu().numpy(), a2.cpu().numpy())
+
+
+def oracle_results(oracle, rq, ra, iq, ia, L, pairs=None, mode=0):
+    return oracle.align(rq, ra, iq, ia, L, pairs=pairs, mode=mode, want_curve=True)
+
+
+@pytest.mark.parametrize("L,n,Q", GEOMS)
+@pytest.mark.parametrize("mode", [0, 1])
+def test_align_parity_on_oracle_tables(api, ctx, oracle, L, n, Q, mode):
+    """Alignment stage alone: the oracle's tables, rounded to FP32, fed to
+    both sides."""
+    ref, imgs = blob_stack(L, 12, 400 + L)
+    rq, ra = oracle.tables(ref, n, Q)
+    iq, ia = oracle.tables(imgs, n, Q)
+    rq32, iq32 = rq.astype(np.float32), iq.astype(np.float32)
+    res, _ = api.align_batch(ctx, dev(rq32), dev(ra), dev(iq32), dev(ia), L, mode=mode)
+    g = api.unpack_results(res)
+    o = oracle_results(oracle, rq32.astype(np.float64), ra, iq32.astype(np.float64), ia, L, mode=mode)
+    parity.check(g, o, L, parity.TAU_FP32, o["curve"])
+
+
+@pytest.mark.parametrize("L,n,Q", GEOMS)
+def test_end_to_end_parity(api, ctx, oracle, L, n, Q):
+    """Images -> tables -> alignment on the GPU against the oracle from the
+    same float32 images."""
+    ref, imgs = blob_stack(L, 16, 500 + L)
+    rq, ra = api.tables(ctx, dev(ref[None]), n, Q)
+    iq, ia = api.tables(ctx, dev(imgs), n, Q)
+    res, curve = api.align_batch(ctx, rq, ra, iq, ia, L, want_curve=True)
+    g = api.unpack_results(res)
+    orq, ora = oracle.tables(ref, n, Q)
+    oiq, oia = oracle.tables(imgs, n, Q)
+    o = oracle_results(oracle, orq, ora, oiq, oia, L)
+    rep = parity.check(g, o, L, parity.TAU_FP32, o["curve"])
+    # the D*(l) curve itself, to the same tolerance
+    c = curve.cpu().numpy()
+    assert np.all(np.abs(c - o["curve"]) <= parity.dist_tol(o["curve"], L, 1e-3))
+    print(rep)
+
+
+def test_single_pair_workload(api, ctx, oracle):
+    """The single-pair workload (L = 64, 5 blobs, +-4 px) end to end."""
+    w = synth.workload(0)
+    L, n, Q = w["L"], w["n"], w["Q"]
+    rq, ra = api.tables(ctx, dev(w["ref"][None]), n, Q)
+    iq, ia = api.tables(ctx, dev(w["imgs"]), n, Q)
+    res, _ = api.align_batch(ctx, rq, ra, iq, ia, L)
+    g = api.unpack_results(res)
+    o = oracle.align_images(w["ref"], w["imgs"], n, Q, want_curve=True)
+    parity.check(g, o, L, parity.TAU_FP32, o["curve"])
+
+
+def test_pairs_list_and_topk(api, ctx, oracle):
+    import torch
+
+    L, n, Q = 64, 64, 64
+    _, imgs = blob_stack(L, 10, 600)
+    q, a = api.tables(ctx, dev(imgs), n, Q)
+    rng = np.random.default_rng(3)
+    pairs = rng.integers(0, 10, size=(37, 2)).astype(np.int64)
+    res, _ = api.align_batch(ctx, q, a, q, a, L, pairs=dev(pairs), top_k=4)
+    g = api.unpack_results(res)
+    oq, oa = oracle.tables(imgs, n, Q)
+    o = oracle_results(oracle, oq, oa, oq, oa, L, pairs=pairs)
+    parity.check(g, o, L, parity.TAU_FP32, o["curve"])
+    # diagonal pairs are exactly zero
+    diag = pairs[:, 0] == pairs[:, 1]
+    assert np.all(g["sw2sq"][diag] == 0.0) and np.all(g["rot_index"][diag] == 0)
+    del torch
+
+
+def test_bf16_split_within_tolerance(api, ctx, oracle):
+    L, n, Q = 128, 128, 128
+    ref, imgs = blob_stack(L, 24, 700)
+    rq, ra = api.tables(ctx, dev(ref[None]), n, Q)
+    iq, ia = api.tables(ctx, dev(imgs), n, Q)
+    res, _ = api.align_batch(ctx, rq, ra, iq, ia, L, prec=1)
+    g = api.unpack_results(res)
+    o = oracle.align_images(ref, imgs, n, Q, want_curve=True)
+    parity.check(g, o, L, parity.TAU_BF16, o["curve"])
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_quarter_turns_and_self(api, ctx, m):
+    L, n = 96, 96
+    _, imgs = blob_stack(L, 1, 800, snr=None)
+    f = imgs[0]
+    g = np.ascontiguousarray(np.rot90(f, m))
+    q, a = api.tables(ctx, dev(np.stack([f, g])), n, n)
+    res, _ = api.align_batch(ctx, q[:1].contiguous(), a[:1].contiguous(), q, a, L)
+    r = api.unpack_results(res)
+    assert r["rot_index"][0] == 0 and r["sw2sq"][0] == 0.0
+    assert r["rot_index"][1] == (m * n // 4) % n
+    assert r["sw2sq"][1] < 1e-9 and np.all(np.abs(r["shift_px"][1]) < 1e-3)
+
+
+def test_deterministic_and_independent_of_batch(api, ctx):
+    """Same input twice gives bitwise-equal results, and a pair's result does
+    not depend on what else is in the batch."""
+    L, n = 64, 64
+    ref, imgs = blob_stack(L, 30, 900)
+    x = dev(imgs)
+    q1, a1 = api.tables(ctx, x, n, n)
+    q2, a2 = api.tables(ctx, x, n, n)
+    assert np.array_equal(q1.cpu().numpy(), q2.cpu().numpy())
+    rq, ra = api.tables(ctx, dev(ref[None]), n, n)
+    r_all, _ = api.align_batch(ctx, rq, ra, q1, a1, L)
+    r_one, _ = api.align_batch(ctx, rq, ra, q1[7:8].contiguous(), a1[7:8].contiguous(), L)
+    assert np.array_equal(r_all.cpu().numpy()[7], r_one.cpu().numpy()[0])
+    q3, a3 = api.tables(ctx, x[7:8].contiguous(), n, n)
+    assert np.array_equal(q3.cpu().numpy()[0], q1.cpu().numpy()[7])
+
+
+def test_status_codes_and_empty(api, ctx):
+    import torch
+
+    L, n = 32, 32
+    _, imgs = blob_stack(L, 3, 1000)
+    imgs[1] = 0.0
+    imgs[2, 5, 5] = np.nan
+    q, a = api.tables(ctx, dev(imgs), n, n)
+    res, _ = api.align_batch(ctx, q[:1].contiguous(), a[:1].contiguous(), q, a, L)
+    r = api.unpack_results(res)
+    assert list(r["status"]) == [0, 1, 2]
+    # N = 0 is a no-op
+    e = torch.empty((0, L, L), dtype=torch.float32, device="cuda")
+    q0, a0 = api.tables(ctx, e, n, n)
+    assert q0.shape[0] == 0
