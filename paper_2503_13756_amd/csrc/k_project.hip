@@ -5,7 +5,7 @@
 namespace sw {
 
 template <int NT, int TPW>
-__global__ __launch_bounds__(NT) void k_project(const float *__restrict__ img, int64_t N,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_project(const float *__restrict__ img, int64_t N,
                                                 ProjShape P, const float2 *__restrict__ dtab,
                                                 float *__restrict__ pmf) {
     extern __shared__ float lds[];

@@ -16,7 +16,7 @@ struct TablesShape {
 };
 
 template <int NT, int TPW>
-__global__ __launch_bounds__(NT) void k_tables(const float *__restrict__ img, int64_t N,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tables(const float *__restrict__ img, int64_t N,
                                                TablesShape T, const float2 *__restrict__ d32,
                                                const double2 *__restrict__ d64,
                                                float *__restrict__ qt, double *__restrict__ aux) {
@@ -101,7 +101,9 @@ size_t tables_lds_bytes(Geo g, int nt, TablesShape *out) {
     region = (region + 1) & ~1;
     T.region_floats = region;
     const size_t fixed = sizeof(float) * region + sizeof(double) * (nt / 64) * (g.L + 1);
-    const size_t budget = 150 * 1024;
+    // two blocks per CU when the PMF table allows it (160 KiB of LDS per CU)
+    const size_t budget2 = 79 * 1024, budget1 = 150 * 1024;
+    const size_t budget = fixed + sizeof(float) * g.Q * 9 <= budget2 ? budget2 : budget1;
     if (fixed + sizeof(float) * g.Q * 9 > budget) return 0;
     T.TC = pick_tc(g.n, g.Q, budget - fixed);
     if (out) *out = T;

@@ -116,7 +116,8 @@ __device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *
 template <int TPW>
 __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const float *Srow,
                                                  const float *Tcol, int i0, int rows,
-                                                 const LaneTask (&tk)[TPW], float (&acc)[TPW][4]) {
+                                                 const LaneTask (&tk)[TPW], float (&acc)[TPW][4],
+                                                 int my_tasks) {
     const int L = P.L, S = P.S;
     const float hi = (float)L + 0.5f;
     for (int rr = 0; rr < rows; ++rr) {
@@ -125,23 +126,30 @@ __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const float
         const float *rowT = Tcol + rr * S + kPadLeft;
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
-            float u = fmaf(fi, tk[t].r, tk[t].A);
-            u = fminf(fmaxf(u, -1.5f), hi);
-            const float jf = floorf(u);
-            const float cf = tk[t].c * (u - jf);
-            const int jA = (int)jf;
-            const float w0 = fmaxf(0.f, tk[t].omc - cf);   // column jA - 1
-            const float w1 = 1.f - cf;                      // column jA
-            const float w2 = tk[t].omc + cf;                // column jA + 1
-            const float w3 = fmaxf(0.f, tk[t].om2c + cf);  // column jA + 2
-            const float *a = rowS + jA;
-            const float *b = rowT + jA;
-            const float *fa = rowS + (L - 1 - jA);
-            const float *fb = rowT + (L - 1 - jA);
-            acc[t][0] += w0 * a[-1] + w1 * a[0] + w2 * a[1] + w3 * a[2];
-            acc[t][1] += w0 * b[-1] + w1 * b[0] + w2 * b[1] + w3 * b[2];
-            acc[t][2] += w0 * fa[1] + w1 * fa[0] + w2 * fa[-1] + w3 * fa[-2];
-            acc[t][3] += w0 * fb[1] + w1 * fb[0] + w2 * fb[-1] + w3 * fb[-2];
+            if (t < my_tasks) {  // wave-uniform
+                float u = fmaf(fi, tk[t].r, tk[t].A);
+                u = __builtin_amdgcn_fmed3f(u, -1.5f, hi);
+                const float jf = floorf(u);
+                const float cf = tk[t].c * (u - jf);
+                const int jA = (int)jf;
+                const float w0 = fmaxf(0.f, tk[t].omc - cf);   // column jA - 1
+                const float w1 = 1.f - cf;                      // column jA
+                const float w2 = tk[t].omc + cf;                // column jA + 1
+                const float w3 = fmaxf(0.f, tk[t].om2c + cf);  // column jA + 2
+                const float *a = rowS + jA;
+                const float *b = rowT + jA;
+                const float *fa = rowS + (L - 1 - jA);
+                const float *fb = rowT + (L - 1 - jA);
+                // all sixteen reads first, so they are in flight together
+                const float a0 = a[-1], a1 = a[0], a2 = a[1], a3 = a[2];
+                const float b0 = b[-1], b1 = b[0], b2 = b[1], b3 = b[2];
+                const float c0 = fa[1], c1 = fa[0], c2 = fa[-1], c3 = fa[-2];
+                const float d0 = fb[1], d1 = fb[0], d2 = fb[-1], d3 = fb[-2];
+                acc[t][0] = fmaf(w3, a3, fmaf(w2, a2, fmaf(w1, a1, fmaf(w0, a0, acc[t][0]))));
+                acc[t][1] = fmaf(w3, b3, fmaf(w2, b2, fmaf(w1, b1, fmaf(w0, b0, acc[t][1]))));
+                acc[t][2] = fmaf(w3, c3, fmaf(w2, c2, fmaf(w1, c1, fmaf(w0, c0, acc[t][2]))));
+                acc[t][3] = fmaf(w3, d3, fmaf(w2, d2, fmaf(w1, d1, fmaf(w0, d0, acc[t][3]))));
+            }
         }
     }
 }
@@ -191,13 +199,15 @@ __device__ void project_image(const float *__restrict__ F, const ProjShape &P,
     }
     float *Srow = lds;
     float *Tcol = lds + P.R * P.S;
+    const int ntasks = (P.items + 63) / 64;
+    const int my_tasks = ntasks > wave ? (ntasks - wave + NW - 1) / NW : 0;
     int bad = 0;
     for (int i0 = 0; i0 < P.L; i0 += P.R) {
         const int rows = min(P.R, P.L - i0);
         __syncthreads();
         stage_strip<NT>(F, P, i0, rows, Srow, Tcol, bad);
         __syncthreads();
-        accumulate_strip<TPW>(P, Srow, Tcol, i0, rows, tk, acc);
+        accumulate_strip<TPW>(P, Srow, Tcol, i0, rows, tk, acc, my_tasks);
     }
     bad_out = __syncthreads_or(bad);
     emit_outputs<TPW>(P, wave, NW, lane, acc, emit);
