@@ -307,6 +307,41 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
     if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const int Wn = geo.n / 2 + 1;
+    const bool same_set = b->ref_qt == b->img_qt && b->ref_aux == b->img_aux && b->n_ref == b->n_img;
+    if (!b->pairs && !curve && b->prec == SW_PREC_BF16_SPLIT && top_k <= 4 &&
+        sw::mfma_path_supported(geo) && P >= 256) {
+        // many-vs-many on the matrix cores: bf16 spectra of both sets, then
+        // the correlation/top-k kernel and the FP32 rescore
+        const size_t per = sizeof(uint32_t) * (size_t)Wn * geo.Q;
+        const size_t ref_bytes = (per * (size_t)b->n_ref + 255) & ~(size_t)255;
+        const size_t img_bytes = same_set ? 0 : (per * (size_t)b->n_img + 255) & ~(size_t)255;
+        const size_t cand_bytes = sizeof(int16_t) * (size_t)P * top_k;
+        void *scr;
+        if ((st = get_scratch(c, ref_bytes + img_bytes + cand_bytes, s, &scr)) != SW_OK) return st;
+        char *base = (char *)scr;
+        uint32_t *spec_ref = (uint32_t *)base;
+        uint32_t *spec_img = same_set ? spec_ref : (uint32_t *)(base + ref_bytes);
+        int16_t *cand = (int16_t *)(base + ref_bytes + img_bytes);
+        hipError_t e = sw::launch_spectrum(b->ref_qt, b->n_ref, geo, *t, spec_ref, 1, s);
+        if (e == hipSuccess && !same_set)
+            e = sw::launch_spectrum(b->img_qt, b->n_img, geo, *t, spec_img, 1, s);
+        if (e != hipSuccess) return hip_fail(e, "k_spectrum launch");
+        sw::MfmaArgs m;
+        m.spec_ref = spec_ref;
+        m.spec_img = spec_img;
+        m.ref_qt = b->ref_qt;
+        m.ref_aux = b->ref_aux;
+        m.n_ref = b->n_ref;
+        m.img_qt = b->img_qt;
+        m.img_aux = b->img_aux;
+        m.n_img = b->n_img;
+        m.mode = b->mode;
+        m.top_k = top_k;
+        m.cand = cand;
+        m.out = (sw::Result *)out;
+        e = sw::launch_mfma_all_pairs(m, geo, *t, s);
+        return e == hipSuccess ? SW_OK : hip_fail(e, "k_corr_mfma / k_rescore_tiles launch");
+    }
     const size_t spec_bytes = sizeof(float2) * (size_t)Wn * geo.Q * (size_t)b->n_ref;
     void *spec;
     if ((st = get_scratch(c, spec_bytes, s, &spec)) != SW_OK) return st;

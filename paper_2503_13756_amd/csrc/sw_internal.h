@@ -70,4 +70,22 @@ struct PairArgs {
 };
 hipError_t launch_align_pairs(const PairArgs &a, Geo g, const AngleTable &t, hipStream_t s);
 
+// All reference x image pairs on MFMA (bfloat16 spectra, FP32 accumulate),
+// top-k lags per pair, then an FP32 rescore of those lags.
+struct MfmaArgs {
+    const uint32_t *spec_ref;  // [n_ref][n/2+1][Q] packed bf16 complex
+    const uint32_t *spec_img;  // [n_img][n/2+1][Q]
+    const float *ref_qt;
+    const double *ref_aux;
+    int64_t n_ref;
+    const float *img_qt;
+    const double *img_aux;
+    int64_t n_img;
+    int mode, top_k;
+    int16_t *cand;  // [n_ref * n_img][top_k] scratch
+    Result *out;
+};
+bool mfma_path_supported(Geo g);
+hipError_t launch_mfma_all_pairs(const MfmaArgs &a, Geo g, const AngleTable &t, hipStream_t s);
+
 }  // namespace sw

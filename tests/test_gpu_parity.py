@@ -207,3 +207,39 @@ def test_status_codes_and_empty(api, ctx):
     e = torch.empty((0, L, L), dtype=torch.float32, device="cuda")
     q0, a0 = api.tables(ctx, e, n, n)
     assert q0.shape[0] == 0
+
+
+# ---------------------------------------------------------------- many-vs-many (MFMA)
+@pytest.mark.parametrize("L,n,nr,ni", [(64, 64, 40, 40), (32, 32, 37, 53), (64, 64, 16, 17)])
+def test_all_pairs_mfma_parity(api, ctx, oracle, L, n, nr, ni):
+    """All reference x image pairs on the matrix cores (bf16 spectra, FP32
+    accumulate, top-4 FP32 rescore), ragged tiles, BF16 tolerance."""
+    _, imgs = blob_stack(L, max(nr, ni), 1100 + nr)
+    rq, ra = api.tables(ctx, dev(imgs[:nr]), n, n)
+    iq, ia = api.tables(ctx, dev(imgs[:ni]), n, n)
+    res, _ = api.align_batch(ctx, rq, ra, iq, ia, L, prec=1, top_k=4)
+    g = api.unpack_results(res)
+    oq, oa = oracle.tables(imgs, n, n)
+    o = oracle_results(oracle, oq[:nr], oa[:nr], oq[:ni], oa[:ni], L)
+    parity.check(g, o, L, parity.TAU_BF16, o["curve"])
+    # the same image against itself: lag 0, distance exactly 0
+    m = min(nr, ni)
+    diag = np.arange(m) * ni + np.arange(m)
+    assert np.all(g["rot_index"][diag] == 0) and np.all(g["sw2sq"][diag] == 0.0)
+
+
+def test_all_pairs_mfma_same_set_sampled(api, ctx, oracle):
+    """One set against itself (spectra computed once), 300 x 300 at L = 64,
+    checked on a seeded sample of 400 pairs."""
+    L, n, N = 64, 64, 300
+    _, imgs = blob_stack(L, N, 1200)
+    q, a = api.tables(ctx, dev(imgs), n, n)
+    res, _ = api.align_batch(ctx, q, a, q, a, L, prec=1)
+    g = api.unpack_results(res)
+    rng = np.random.default_rng(5)
+    pairs = np.stack([rng.integers(0, N, 400), rng.integers(0, N, 400)], axis=1).astype(np.int64)
+    pidx = pairs[:, 0] * N + pairs[:, 1]
+    oq, oa = oracle.tables(imgs, n, n)
+    o = oracle_results(oracle, oq, oa, oq, oa, L, pairs=pairs)
+    sub = {k: v[pidx] for k, v in g.items()}
+    parity.check(sub, o, L, parity.TAU_BF16, o["curve"])
