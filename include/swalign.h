@@ -162,6 +162,90 @@ typedef struct {
 sw_status sw_align_batch(void *ctx, const sw_batch *b /*host*/, sw_result *out, float *curve,
                          void *stream);
 
+/* Uneven batch: stacks of images of different geometry, each aligned
+   against its own reference image (steps 1-5 for every image of every
+   stack).  All stacks go through persistent mixed-geometry launches (one
+   launch per stage for up to 64 stacks) whose blocks take work items from a
+   device counter, largest L first; the projection strip tile per L comes from
+   the autotuner's table when the context was created with one.
+   Outputs are caller-allocated device arrays; results go to out[N] of each
+   stack, with the reference and image tables left in ref_qt/ref_aux and
+   qt/aux.  prec SW_PREC_BF16_SPLIT rounds the spectra to bfloat16 before
+   the correlation and rescoring the top_k lags in FP32. */
+typedef struct {
+    const float *ref_img; /* [L][L] */
+    const float *imgs;    /* [N][L][L] */
+    int64_t N;
+    sw_geom geom;
+    float *ref_qt;        /* [Q][n] */
+    double *ref_aux;      /* [4] */
+    float *qt;            /* [N][Q][n] */
+    double *aux;          /* [N][4] */
+    sw_result *out;       /* [N] */
+} sw_stack;
+
+sw_status sw_align_stacks(void *ctx, const sw_stack *stacks /*host*/, int32_t n_stacks,
+                          int32_t mode, int32_t prec, int32_t top_k, void *stream);
+
+/* Autotuner: for each side L in Ls (geometry n = Q = L), times the mixed
+   pipeline on n_images synthetic images for every admissible projection
+   strip height and keeps the fastest.  The table is kept in the context and,
+   when out_json is given, written there as {"tiles": {"L": {"R": rows}}};
+   pass that file to sw_ctx_create to reuse it.  Synchronises the device. */
+sw_status sw_autotune(void *ctx, const int32_t *Ls /*host*/, int32_t nL, int64_t n_images,
+                      const char *out_json /*host, nullable*/);
+
+/* Serving: continuous batching of alignment requests (1 reference image +
+   N images each, host memory).  A scheduler thread owned by the context
+   admits queued requests in arrival order while the request fits in the HBM
+   budget and a slot is free, copies its images to the device, and launches
+   all admitted requests of one geometry together through the mixed
+   persistent kernels, replayed from a captured graph; requests that arrive
+   while others run are admitted as slots and memory free up, so their work
+   shares launches and overlaps on the device.  Reference tables with a
+   non-zero ref_key stay cached in HBM (evicted least recently used when
+   memory is needed).  Results are computed with the same kernels as
+   sw_align_stacks, so a request's results do not depend on what else was in
+   the batch.
+   Contract: the caller keeps ref_img and imgs valid until sw_serve_poll
+   returns SW_OK for the ticket or sw_serve_cancel returns.
+   Errors: sw_serve_submit returns SW_E_NOMEM when the request alone exceeds
+   the budget, SW_E_BUSY when max_queue requests are already waiting;
+   sw_serve_poll returns SW_NOT_READY until the results are in `out`,
+   SW_E_INVALID for an unknown or cancelled ticket, SW_E_DEVICE if the device
+   work failed.  Calls are thread-safe. */
+typedef struct {
+    size_t hbm_budget_bytes; /* arena for images, tables, results and the cache */
+    int32_t max_slots;       /* requests admitted at once (<= 64 per launch) */
+    int32_t prec;            /* sw_precision */
+    int32_t top_k;           /* 0 = 1 for FP32, 4 for BF16_SPLIT */
+    int32_t mode;            /* sw_mode */
+    int32_t max_queue;       /* waiting requests before SW_E_BUSY */
+    int32_t use_graphs;      /* 1: replay captured graphs, 0: plain launches */
+} sw_serve_cfg;
+
+typedef struct {
+    const float *ref_img; /* host [L][L] */
+    const float *imgs;    /* host [N][L][L] */
+    int64_t N;
+    sw_geom geom;
+    uint64_t ref_key;     /* 0 = reference tables not cached */
+} sw_request;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, cancelled, failed;
+    uint64_t steps, graph_launches, cache_hits, evictions;
+    int64_t pending, in_flight;
+    size_t arena_used, arena_peak, arena_size;
+} sw_serve_stats;
+
+sw_status sw_serve_start(void *ctx, const sw_serve_cfg *cfg /*host*/);
+sw_status sw_serve_submit(void *ctx, const sw_request *r /*host*/, uint64_t *ticket /*host*/);
+sw_status sw_serve_poll(void *ctx, uint64_t ticket, sw_result *out /*host [N]*/);
+sw_status sw_serve_cancel(void *ctx, uint64_t ticket);
+sw_status sw_serve_stats_get(void *ctx, sw_serve_stats *out /*host*/);
+sw_status sw_serve_stop(void *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,32 @@ class sw_batch(ctypes.Structure):
                 ("top_k", ctypes.c_int32)]
 
 
+class sw_stack(ctypes.Structure):
+    _fields_ = [("ref_img", ctypes.c_void_p), ("imgs", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("geom", sw_geom), ("ref_qt", ctypes.c_void_p), ("ref_aux", ctypes.c_void_p),
+                ("qt", ctypes.c_void_p), ("aux", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class sw_serve_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("top_k", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
+
+
+class sw_request(ctypes.Structure):
+    _fields_ = [("ref_img", ctypes.c_void_p), ("imgs", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("geom", sw_geom), ("ref_key", ctypes.c_uint64)]
+
+
+class sw_serve_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "admitted", "completed", "cancelled",
+                                               "failed", "steps", "graph_launches", "cache_hits",
+                                               "evictions")] + \
+               [("pending", ctypes.c_int64), ("in_flight", ctypes.c_int64),
+                ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
+                ("arena_size", ctypes.c_size_t)]
+
+
 class SwError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -58,6 +84,14 @@ SIGNATURES = [
     ("sw_quantiles", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
     ("sw_tables", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
     ("sw_align_batch", I32, [P, ctypes.POINTER(sw_batch), P, P, P]),
+    ("sw_align_stacks", I32, [P, ctypes.POINTER(sw_stack), I32, I32, I32, I32, P]),
+    ("sw_autotune", I32, [P, ctypes.POINTER(ctypes.c_int32), I32, I64, ctypes.c_char_p]),
+    ("sw_serve_start", I32, [P, ctypes.POINTER(sw_serve_cfg)]),
+    ("sw_serve_submit", I32, [P, ctypes.POINTER(sw_request), ctypes.POINTER(ctypes.c_uint64)]),
+    ("sw_serve_poll", I32, [P, ctypes.c_uint64, P]),
+    ("sw_serve_cancel", I32, [P, ctypes.c_uint64]),
+    ("sw_serve_stats_get", I32, [P, ctypes.POINTER(sw_serve_stats)]),
+    ("sw_serve_stop", I32, [P]),
 ]
 
 _lib = None

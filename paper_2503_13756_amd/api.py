@@ -11,7 +11,7 @@ import ctypes
 import torch
 
 from . import _abi
-from ._abi import check, sw_batch, sw_geom
+from ._abi import check, sw_batch, sw_geom, sw_stack, sw_serve_cfg, sw_request, sw_serve_stats
 
 
 def _stream(stream=None):
@@ -149,3 +149,103 @@ def unpack_results(res: torch.Tensor):
         "sw2sq": f[:, 4].numpy().copy(),
         "status": r[:, 5].numpy().copy(),
     }
+
+
+def align_stacks(ctx: Context, stacks, n=None, Q=None, mode=_abi.MODE_ROT_TRANS,
+                 prec=_abi.PREC_FP32, top_k=0, levels=_abi.LEVELS_MIDPOINT, stream=None):
+    """sw_align_stacks over a list of (ref_img [L, L], imgs [N, L, L]) device
+    tensors; n and Q default to L per stack.  Returns per stack a dict with
+    the raw [N, 6] result records and the tables."""
+    descs = (sw_stack * len(stacks))()
+    keep = []
+    for i, (ref, imgs) in enumerate(stacks):
+        _need(ref, torch.float32, "ref_img")
+        _need(imgs, torch.float32, "imgs")
+        N, L = imgs.shape[0], imgs.shape[-1]
+        nn = n if n is not None else L
+        qq = Q if Q is not None else L
+        dev = imgs.device
+        o = {"ref_qt": torch.empty((qq, nn), dtype=torch.float32, device=dev),
+             "ref_aux": torch.empty((4,), dtype=torch.float64, device=dev),
+             "qt": torch.empty((N, qq, nn), dtype=torch.float32, device=dev),
+             "aux": torch.empty((N, 4), dtype=torch.float64, device=dev),
+             "res": torch.empty((N, 6), dtype=torch.int32, device=dev), "L": L}
+        d = descs[i]
+        d.ref_img, d.imgs, d.N = ref.data_ptr(), imgs.data_ptr(), N
+        d.geom = geom(L, nn, qq, levels)
+        d.ref_qt, d.ref_aux = o["ref_qt"].data_ptr(), o["ref_aux"].data_ptr()
+        d.qt, d.aux, d.out = o["qt"].data_ptr(), o["aux"].data_ptr(), o["res"].data_ptr()
+        keep.append(o)
+    check(ctx._lib.sw_align_stacks(ctx.handle, descs, len(stacks), int(mode), int(prec),
+                                   int(top_k), _stream(stream)))
+    return keep
+
+
+def autotune(ctx: Context, Ls, n_images=2048, out_json=None):
+    arr = (ctypes.c_int32 * len(Ls))(*[int(x) for x in Ls])
+    check(ctx._lib.sw_autotune(ctx.handle, arr, len(Ls), int(n_images),
+                               None if out_json is None else out_json.encode()))
+
+
+class Server:
+    """Continuous-batching server on a context (sw_serve_*).  Requests hold
+    host numpy arrays that must stay alive until polled or cancelled; this
+    wrapper keeps a reference to them."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots=64, prec=_abi.PREC_BF16_SPLIT,
+                 top_k=0, mode=_abi.MODE_ROT_TRANS, max_queue=4096, use_graphs=True):
+        self.ctx = ctx
+        cfg = sw_serve_cfg(int(hbm_budget_bytes), int(max_slots), int(prec), int(top_k), int(mode),
+                           int(max_queue), 1 if use_graphs else 0)
+        check(ctx._lib.sw_serve_start(ctx.handle, ctypes.byref(cfg)))
+        self._live = {}
+
+    def submit(self, ref_img, imgs, n=None, Q=None, ref_key=0, levels=_abi.LEVELS_MIDPOINT):
+        import numpy as np
+
+        ref_img = np.ascontiguousarray(ref_img, dtype=np.float32)
+        imgs = np.ascontiguousarray(imgs, dtype=np.float32)
+        N, L = imgs.shape[0], imgs.shape[-1]
+        req = sw_request(ref_img.ctypes.data, imgs.ctypes.data, N,
+                         geom(L, n or L, Q or L, levels), int(ref_key))
+        t = ctypes.c_uint64()
+        check(self.ctx._lib.sw_serve_submit(self.ctx.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._live[t.value] = (ref_img, imgs, N)
+        return t.value
+
+    def poll(self, ticket):
+        """None while not ready, else the [N, 6] int32 result records (numpy)."""
+        import numpy as np
+
+        N = self._live[ticket][2] if ticket in self._live else 0
+        out = np.zeros((N, 6), dtype=np.int32)
+        st = self.ctx._lib.sw_serve_poll(self.ctx.handle, ctypes.c_uint64(ticket),
+                                         out.ctypes.data_as(ctypes.c_void_p) if N else None)
+        if st == _abi.SW_NOT_READY:
+            return None
+        self._live.pop(ticket, None)
+        check(st)
+        return out
+
+    def cancel(self, ticket):
+        check(self.ctx._lib.sw_serve_cancel(self.ctx.handle, ctypes.c_uint64(ticket)))
+        self._live.pop(ticket, None)
+
+    def stats(self):
+        s = sw_serve_stats()
+        check(self.ctx._lib.sw_serve_stats_get(self.ctx.handle, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def stop(self):
+        check(self.ctx._lib.sw_serve_stop(self.ctx.handle))
+        self._live.clear()
+
+
+def records_to_dict(rec):
+    """[P, 6] int32 numpy records -> dict of arrays."""
+    import numpy as np
+
+    rec = np.asarray(rec, dtype=np.int32)
+    f = rec.view(np.float32)
+    return {"rot_index": rec[:, 0].copy(), "theta_rad": f[:, 1].copy(),
+            "shift_px": f[:, 2:4].copy(), "sw2sq": f[:, 4].copy(), "status": rec[:, 5].copy()}

@@ -1,0 +1,61 @@
+// Host-side internals of libswalign shared by the C entry points
+// (sw_host.cpp) and the serving runtime (sw_serve.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "swalign.h"
+#include "sw_internal.h"
+
+namespace swh {
+
+sw_status fail(sw_status s, const char *fmt, ...);
+sw_status hip_fail(hipError_t e, const char *where);
+const std::string &last_error();
+
+// Pinned host staging of the device-side stack descriptors: a ring of slots,
+// each reused only after the copy that last read it has completed.
+struct DescRing {
+    static constexpr int kSlots = 8;
+    sw::MixGroup *host = nullptr;  // [kSlots][2]
+    hipEvent_t ev[kSlots] = {};
+    bool used[kSlots] = {};
+    int next = 0;
+};
+
+struct Server;  // serving runtime (sw_serve.cpp)
+
+struct Ctx {
+    int device = 0;
+    int cu_count = 256;
+    std::mutex mu;
+    std::map<int, sw::AngleTable> tables;
+    std::map<int, int> tile_R;  // projection strip rows per L (autotuner)
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    DescRing ring;
+    Server *server = nullptr;
+};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+sw_status check_geom(const sw_geom *g, sw::Geo *out);
+sw_status get_table(Ctx *ctx, int n, const sw::AngleTable **out);
+void stop_server(Ctx *c);
+
+}  // namespace swh

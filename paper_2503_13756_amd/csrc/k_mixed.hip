@@ -1,0 +1,266 @@
+// Mixed-geometry persistent kernels: one launch covers many image stacks (or
+// serving requests) of different side L, each stack with its own reference.
+// Blocks pull work items (one image each) from a device counter; the
+// description of the stacks (pointers, geometry, strip-row tile, counts)
+// lives in device memory, so a captured graph can be replayed with new
+// contents and live counts.  The per-image arithmetic is the same device code
+// as the single-geometry kernels (projection, CDF/quantiles, FFT alignment).
+#include "align_dev.h"
+#include "proj_dev.h"
+#include "quant_dev.h"
+
+namespace sw {
+
+__global__ void k_reset_counters(unsigned long long *c, int n) {
+    if (threadIdx.x < n) c[threadIdx.x] = 0ull;
+}
+
+// Index of the item whose [first, first + count) range holds work index w.
+__device__ __forceinline__ int find_item(const MixGroup *G, int64_t w) {
+    int lo = 0, hi = G->nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (G->items[mid].first <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int NT>
+__device__ __forceinline__ int64_t next_work(unsigned long long *counter, int64_t *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(counter, 1ull);
+    __syncthreads();
+    return *slot;
+}
+
+// Images -> quantile tables for every item of the group.  `scratch` holds one
+// PMF slot of slot_floats per block, used by images whose PMF table does not
+// fit in LDS.
+template <int NT, int TPW>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tables_mixed(
+    const MixGroup *__restrict__ G, unsigned long long *counter, float *scratch,
+    int64_t slot_floats, int region_floats, int lmax) {
+    constexpr int NW = NT / 64;
+    extern __shared__ double ldsd[];
+    __shared__ double red[NW][4];
+    __shared__ int64_t wslot;
+    float *region = (float *)ldsd;
+    double *C0 = ldsd + region_floats / 2;
+    float *Ut = (float *)(C0 + NW * (lmax + 1));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t total = G->total;
+    for (;;) {
+        const int64_t w = next_work<NT>(counter, &wslot);
+        if (w >= total) break;
+        const MixItem &it = G->items[find_item(G, w)];
+        const int64_t gi = w - it.first;
+        ProjShape P;
+        P.L = it.L;
+        P.n = it.n;
+        P.S = strip_stride(it.L);
+        P.R = it.R;
+        P.slots = it.n / 8 + 1;
+        P.items = P.slots * it.L;
+        const int L = P.L, n = P.n, Q = it.Q, TC = it.TC;
+        float *pmf = it.fused ? region : scratch + (int64_t)blockIdx.x * slot_floats;
+        const float *F = it.img + gi * (int64_t)L * L;
+        int bad = 0;
+        project_image<NT, TPW>(F, P, it.d32, region, bad,
+                               [&](int k, int b, float v) { pmf[k * L + b] = v; });
+        if (bad)
+            for (int t = threadIdx.x; t < n * L; t += NT) pmf[t] = __int_as_float(0x7fc00000);
+        __threadfence_block();
+        __syncthreads();
+        double *C = C0 + wave * (L + 1);
+        const int ldt = TC + 1;
+        float *U = it.qt + gi * (int64_t)Q * n;
+        double E = 0.0, ar = 0.0, ai = 0.0, mass0 = 0.0;
+        for (int k0 = 0; k0 < n; k0 += TC) {
+            for (int kl = wave; kl < TC; kl += NW) {
+                const int k = k0 + kl;
+                const float *colp = pmf + k * L;
+                double su, sq;
+                const double mass = invert_column([&](int b) { return colp[b]; }, L, Q, it.levels,
+                                                  C, Ut, ldt, kl, lane, &su, &sq);
+                if (k == 0) mass0 = mass;
+                su = wave_sum_d(su);
+                sq = wave_sum_d(sq);
+                const double qbar = su / (double)Q;
+                const double2 d = it.d64[k];
+                E += sq;
+                ar += qbar * d.x;
+                ai += qbar * d.y;
+            }
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < Q * TC; idx += NT) {
+                const int j = idx / TC, kl = idx - j * TC;
+                U[(int64_t)j * n + k0 + kl] = Ut[j * ldt + kl];
+            }
+            __syncthreads();
+        }
+        if (lane == 0) {
+            red[wave][0] = E;
+            red[wave][1] = ar;
+            red[wave][2] = ai;
+            red[wave][3] = mass0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double e = 0, x = 0, y = 0;
+            for (int v = 0; v < NW; ++v) {
+                e += red[v][0];
+                x += red[v][1];
+                y += red[v][2];
+            }
+            double *A = it.aux + 4 * gi;
+            A[0] = red[0][3];
+            A[1] = e;
+            A[2] = x / (double)n;
+            A[3] = y / (double)n;
+        }
+    }
+}
+
+// FP32 spectrum of the reference of every item: one block per item.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_refspec_mixed(const MixGroup *__restrict__ G) {
+    extern __shared__ float2 lds2[];
+    const int i = blockIdx.x;
+    if (i >= G->nitems) return;
+    const MixItem &it = G->items[i];
+    if (it.count <= 0) return;
+    spectrum_block<NT>(it.ref_qt, it.n, it.Q, it.ref_spec, 0, it.d32, lds2);
+}
+
+// Alignment of every image of every item against the item's reference.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_align_mixed(const MixGroup *__restrict__ G,
+                                                    unsigned long long *counter) {
+    extern __shared__ float2 lds2[];
+    __shared__ int64_t wslot;
+    const int64_t total = G->total;
+    for (;;) {
+        const int64_t w = next_work<NT>(counter, &wslot);
+        if (w >= total) break;
+        const MixItem &it = G->items[find_item(G, w)];
+        const int64_t gi = w - it.first;
+        Geo g{it.L, it.n, it.Q, it.levels};
+        PairJob job;
+        job.U = it.ref_qt;
+        job.au = it.ref_aux;
+        job.Uh = it.ref_spec;
+        job.V = it.qt + gi * (int64_t)it.Q * it.n;
+        job.av = it.aux + 4 * gi;
+        job.res = it.out + gi;
+        job.curve = nullptr;
+        int status = 0;
+        if (isnan(job.au[0]) || isnan(job.av[0])) status = 2;
+        else if (!(job.au[0] > 0.0) || !(job.av[0] > 0.0)) status = 1;
+        job.status = status;
+        align_pair_block<NT>(job, g, it.mode, it.bf16, it.top_k, it.d32, it.d64, lds2);
+    }
+}
+
+// LDS and scratch needs of a set of items; fills the per-item tile fields
+// (fused, TC) and returns the launch parameters.
+MixLaunch plan_mixed(MixItem *items, int nitems) {
+    constexpr int kStripFloats = 16384;
+    constexpr int NT = 256;
+    MixLaunch m{};
+    int lmax = 8, region = 0;
+    int64_t slot = 0;
+    size_t align_lds = 0;
+    for (int i = 0; i < nitems; ++i) {
+        MixItem &it = items[i];
+        const int S = strip_stride(it.L);
+        int R = it.R > 0 ? it.R : kStripFloats / (2 * S);
+        if (R > kStripFloats / (2 * S)) R = kStripFloats / (2 * S);
+        if (R > it.L) R = it.L;
+        if (R < 1) R = 1;
+        if (R > NT) R = NT;
+        it.R = R;
+        const int slots = it.n / 8 + 1;
+        const int ntasks = (slots * it.L + 63) / 64;
+        const bool one_group = ntasks <= (NT / 64) * 12;
+        const int strip = 2 * R * S;
+        const int pmf = it.n * it.L;
+        // fused when a single task group and the PMF fits beside nothing else
+        it.fused = one_group && pmf <= kStripFloats ? 1 : 0;
+        region = max(region, it.fused ? max(strip, pmf) : strip);
+        if (!it.fused) slot = max(slot, (int64_t)pmf);
+        lmax = max(lmax, it.L);
+        const int Wn = it.n / 2 + 1;
+        const int G = Wn >= NT ? 1 : NT / Wn;
+        align_lds = max(align_lds, sizeof(float2) * (it.n + 2 * kFftElems + Wn * G) +
+                                       sizeof(double) * it.n);
+    }
+    region = (region + 1) & ~1;
+    const size_t fixed = sizeof(float) * region + sizeof(double) * (NT / 64) * (lmax + 1);
+    const size_t budget = fixed + 16 * 1024 <= 79 * 1024 ? 79 * 1024 : 150 * 1024;
+    int qmax = 8;
+    for (int i = 0; i < nitems; ++i) {
+        MixItem &it = items[i];
+        it.TC = pick_tc(it.n, it.Q, budget - fixed);
+        qmax = max(qmax, it.Q * (it.TC + 1));
+    }
+    m.region_floats = region;
+    m.lmax = lmax;
+    m.tables_lds = fixed + sizeof(float) * qmax;
+    m.slot_floats = slot;
+    m.align_lds = align_lds;
+    return m;
+}
+
+void prepare_mixed() {
+    constexpr int NT = 256, TPW = 12;
+    static const hipError_t a1 = hipFuncSetAttribute(
+        (const void *)k_tables_mixed<NT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        150 * 1024);
+    static const hipError_t a2 = hipFuncSetAttribute(
+        (const void *)k_refspec_mixed<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    static const hipError_t a3 = hipFuncSetAttribute(
+        (const void *)k_align_mixed<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    (void)a1;
+    (void)a2;
+    (void)a3;
+}
+
+// Every kernel of the sequence reads its item and work counts from the
+// descriptors in device memory, so the sequence can be captured once and
+// replayed with new descriptor contents.
+hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const MixLaunch &m,
+                        unsigned long long *counters, float *scratch, int grid, hipStream_t s) {
+    constexpr int NT = 256, TPW = 12;
+    prepare_mixed();
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, 3);
+    hipLaunchKernelGGL((k_tables_mixed<NT, TPW>), dim3((unsigned)grid), dim3(NT), m.tables_lds, s,
+                       d_refs, counters + 0, scratch, m.slot_floats, m.region_floats, m.lmax);
+    hipLaunchKernelGGL((k_refspec_mixed<NT>), dim3((unsigned)kMaxMix), dim3(NT),
+                       sizeof(float2) * (kMaxN + 2 * kFftElems), s, d_imgs);
+    hipLaunchKernelGGL((k_tables_mixed<NT, TPW>), dim3((unsigned)grid), dim3(NT), m.tables_lds, s,
+                       d_imgs, counters + 1, scratch, m.slot_floats, m.region_floats, m.lmax);
+    hipLaunchKernelGGL((k_align_mixed<NT>), dim3((unsigned)grid), dim3(NT), m.align_lds, s, d_imgs,
+                       counters + 2);
+    return hipGetLastError();
+}
+
+// Deterministic synthetic images for timing (autotuner): a hash of the
+// element index mapped to [0, 1).
+__global__ void k_fill_synthetic(float *x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)i * 2654435761u;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        x[i] = (float)(h >> 8) * (1.0f / 16777216.0f);
+    }
+}
+
+hipError_t launch_fill_synthetic(float *x, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_synthetic, dim3(1024), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
+}  // namespace sw

@@ -156,13 +156,14 @@ __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const float
 
 // Walk one output value per (task, variant) to its columns, including the
 // theta + pi mirror.  Emit(k, b, value) is called for each produced column.
+// Tasks of this wave are tg0 + wave + t * nwaves.
 template <int TPW, typename Emit>
-__device__ __forceinline__ void emit_outputs(const ProjShape &P, int wave, int nwaves, int lane,
-                                             const float (&acc)[TPW][4], Emit emit) {
+__device__ __forceinline__ void emit_outputs(const ProjShape &P, int tg0, int wave, int nwaves,
+                                             int lane, const float (&acc)[TPW][4], Emit emit) {
     const int L = P.L, n = P.n, q = n / 4, h = n / 2, o = n / 8;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-        const int item = (wave + t * nwaves) * 64 + lane;
+        const int item = (tg0 + wave + t * nwaves) * 64 + lane;
         if (item >= P.items) continue;
         const int k = item / L, b = item - k * L;
         // variant 0: angle k, bin b
@@ -183,10 +184,12 @@ __device__ __forceinline__ void emit_outputs(const ProjShape &P, int wave, int n
     }
 }
 
-// Full projection of one image held in LDS strips; results handed to emit.
+// Projection of the tasks [tg0, tg0 + NW * TPW) of one image held in LDS
+// strips; results handed to emit.  Returns (in bad_out) whether the image
+// holds a non-finite value.
 template <int NT, int TPW, typename Emit>
-__device__ void project_image(const float *__restrict__ F, const ProjShape &P,
-                              const float2 *__restrict__ dtab, float *lds, int &bad_out,
+__device__ void project_group(const float *__restrict__ F, const ProjShape &P,
+                              const float2 *__restrict__ dtab, float *lds, int tg0, int &bad_out,
                               Emit emit) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -194,13 +197,14 @@ __device__ void project_image(const float *__restrict__ F, const ProjShape &P,
     float acc[TPW][4];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-        tk[t] = make_task(P, dtab, (wave + t * NW) * 64 + lane);
+        tk[t] = make_task(P, dtab, (tg0 + wave + t * NW) * 64 + lane);
         acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0.f;
     }
     float *Srow = lds;
     float *Tcol = lds + P.R * P.S;
     const int ntasks = (P.items + 63) / 64;
-    const int my_tasks = ntasks > wave ? (ntasks - wave + NW - 1) / NW : 0;
+    const int mine = ntasks - tg0 - wave;
+    const int my_tasks = mine > 0 ? min(TPW, (mine + NW - 1) / NW) : 0;
     int bad = 0;
     for (int i0 = 0; i0 < P.L; i0 += P.R) {
         const int rows = min(P.R, P.L - i0);
@@ -210,7 +214,23 @@ __device__ void project_image(const float *__restrict__ F, const ProjShape &P,
         accumulate_strip<TPW>(P, Srow, Tcol, i0, rows, tk, acc, my_tasks);
     }
     bad_out = __syncthreads_or(bad);
-    emit_outputs<TPW>(P, wave, NW, lane, acc, emit);
+    emit_outputs<TPW>(P, tg0, wave, NW, lane, acc, emit);
+}
+
+// Full projection of one image: as many task groups as needed.  emit must
+// not write to the strip buffers (the next group restages them).
+template <int NT, int TPW, typename Emit>
+__device__ void project_image(const float *__restrict__ F, const ProjShape &P,
+                              const float2 *__restrict__ dtab, float *lds, int &bad_out,
+                              Emit emit) {
+    constexpr int NW = NT / 64;
+    const int ntasks = (P.items + 63) / 64;
+    bad_out = 0;
+    for (int tg0 = 0; tg0 < ntasks; tg0 += NW * TPW) {
+        int bad = 0;
+        project_group<NT, TPW>(F, P, dtab, lds, tg0, bad, emit);
+        bad_out |= bad;
+    }
 }
 
 // Tasks (64 consecutive work items) per wave for a block of nt threads.

@@ -6,17 +6,23 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <fstream>
 #include <map>
 #include <mutex>
+#include <numeric>
+#include <regex>
+#include <sstream>
 #include <string>
 #include <vector>
 
-#include "swalign.h"
-#include "sw_internal.h"
+#include "host_internal.h"
 
-namespace {
+namespace swh {
 
 thread_local std::string g_err;
+
+const std::string &last_error() { return g_err; }
 
 sw_status fail(sw_status s, const char *fmt, ...) {
     char buf[512];
@@ -32,27 +38,7 @@ sw_status hip_fail(hipError_t e, const char *where) {
     return fail(SW_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
 }
 
-struct Ctx {
-    int device = 0;
-    std::mutex mu;
-    std::map<int, sw::AngleTable> tables;
-    void *scratch = nullptr;
-    size_t scratch_bytes = 0;
-};
 
-// Restores the caller's current device on scope exit.
-struct DeviceGuard {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) err = hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 bool only_2_3(int n) {
     while (n % 2 == 0) n /= 2;
@@ -160,9 +146,112 @@ sw_status get_scratch(Ctx *ctx, size_t bytes, hipStream_t stream, void **out) {
     return SW_OK;
 }
 
+// Pinned descriptor slot for one mixed launch (two groups: refs, images).
+sw_status ring_slot(Ctx *c, sw::MixGroup **host) {
+    DescRing &r = c->ring;
+    const int i = r.next;
+    r.next = (r.next + 1) % DescRing::kSlots;
+    if (r.used[i]) {
+        hipError_t e = hipEventSynchronize(r.ev[i]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(descriptor slot)");
+    }
+    r.used[i] = true;
+    *host = r.host + 2 * i;
+    return SW_OK;
+}
+hipEvent_t ring_event(Ctx *c, sw::MixGroup *host) {
+    return c->ring.ev[(host - c->ring.host) / 2];
+}
+
+// Align up to kMaxMix stacks in one set of mixed launches.  Stacks must be
+// validated.  R_override > 0 forces the projection strip rows (autotuner).
+sw_status run_stack_chunk(Ctx *c, const sw_stack *const *st, int n, int mode, int bf16, int top_k,
+                          int R_override, hipStream_t s) {
+    sw::MixGroup *hg;
+    sw_status stt = ring_slot(c, &hg);
+    if (stt != SW_OK) return stt;
+    sw::MixGroup &gr = hg[0], &gi = hg[1];
+    gr.nitems = gi.nitems = n;
+    gr.total = gi.total = 0;
+    int64_t first = 0;
+    for (int i = 0; i < n; ++i) {
+        const sw_stack &k = *st[i];
+        sw::Geo geo{k.geom.L, k.geom.n_angles, k.geom.n_quantiles, k.geom.levels};
+        const sw::AngleTable *t;
+        if ((stt = get_table(c, geo.n, &t)) != SW_OK) return stt;
+        sw::MixItem a{};
+        a.L = geo.L;
+        a.n = geo.n;
+        a.Q = geo.Q;
+        a.levels = geo.levels;
+        auto tr = c->tile_R.find(geo.L);
+        a.R = R_override > 0 ? R_override : (tr != c->tile_R.end() ? tr->second : 0);
+        a.d32 = t->d32;
+        a.d64 = t->d64;
+        a.mode = mode;
+        a.bf16 = bf16;
+        a.top_k = top_k;
+        a.ref_qt = k.ref_qt;
+        a.ref_aux = k.ref_aux;
+        sw::MixItem r = a;
+        r.img = k.ref_img;
+        r.qt = k.ref_qt;
+        r.aux = k.ref_aux;
+        r.first = i;
+        r.count = 1;
+        a.img = k.imgs;
+        a.qt = k.qt;
+        a.aux = k.aux;
+        a.out = (sw::Result *)k.out;
+        a.first = first;
+        a.count = k.N;
+        first += k.N;
+        gr.items[i] = r;
+        gi.items[i] = a;
+    }
+    gr.total = n;
+    gi.total = first;
+    sw::MixLaunch m = sw::plan_mixed(gi.items, n);
+    for (int i = 0; i < n; ++i) {
+        gr.items[i].R = gi.items[i].R;
+        gr.items[i].TC = gi.items[i].TC;
+        gr.items[i].fused = gi.items[i].fused;
+    }
+    // device scratch: two groups, counters, reference spectra, PMF slots
+    const int grid = 2 * c->cu_count;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t o_groups = take(2 * sizeof(sw::MixGroup));
+    const size_t o_cnt = take(4 * sizeof(unsigned long long));
+    std::vector<size_t> o_spec(n);
+    for (int i = 0; i < n; ++i)
+        o_spec[i] = take(sizeof(float2) * (size_t)(gi.items[i].n / 2 + 1) * gi.items[i].Q);
+    const size_t o_slots = take(sizeof(float) * (size_t)m.slot_floats * grid);
+    void *scr;
+    if ((stt = get_scratch(c, off, s, &scr)) != SW_OK) return stt;
+    char *base = (char *)scr;
+    for (int i = 0; i < n; ++i) {
+        gi.items[i].ref_spec = (float2 *)(base + o_spec[i]);
+        gr.items[i].ref_spec = gi.items[i].ref_spec;
+    }
+    sw::MixGroup *d_groups = (sw::MixGroup *)(base + o_groups);
+    hipError_t e = hipMemcpyAsync(d_groups, hg, 2 * sizeof(sw::MixGroup), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(ring_event(c, hg), s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    e = sw::launch_mixed(d_groups, d_groups + 1, m, (unsigned long long *)(base + o_cnt),
+                         (float *)(base + o_slots), grid, s);
+    return e == hipSuccess ? SW_OK : hip_fail(e, "mixed launch");
+}
+
 Ctx *as_ctx(void *p) { return static_cast<Ctx *>(p); }
 
-}  // namespace
+}  // namespace swh
+
+using namespace swh;
 
 extern "C" {
 
@@ -181,6 +270,37 @@ sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
     Ctx *c = new (std::nothrow) Ctx;
     if (!c) return fail(SW_E_NOMEM, "out of host memory");
     c->device = device;
+    {
+        DeviceGuard dg(device);
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+            cu > 0)
+            c->cu_count = cu;
+        e = hipHostMalloc((void **)&c->ring.host, sizeof(sw::MixGroup) * 2 * DescRing::kSlots);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "hipHostMalloc(descriptor ring)");
+        }
+        for (int i = 0; i < DescRing::kSlots; ++i)
+            if ((e = hipEventCreateWithFlags(&c->ring.ev[i], hipEventDisableTiming)) != hipSuccess) {
+                delete c;
+                return hip_fail(e, "hipEventCreate");
+            }
+    }
+    if (tune_json && *tune_json) {
+        std::ifstream f(tune_json);
+        if (!f) {
+            delete c;
+            return fail(SW_E_INVALID, "cannot read tile table %s", tune_json);
+        }
+        std::stringstream ss;
+        ss << f.rdbuf();
+        const std::string txt = ss.str();
+        const std::regex re("\"(\\d+)\"\\s*:\\s*\\{\\s*\"R\"\\s*:\\s*(\\d+)");
+        for (auto it = std::sregex_iterator(txt.begin(), txt.end(), re); it != std::sregex_iterator();
+             ++it)
+            c->tile_R[std::stoi((*it)[1])] = std::stoi((*it)[2]);
+    }
     *ctx = c;
     return SW_OK;
 }
@@ -188,6 +308,7 @@ sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
 sw_status sw_ctx_destroy(void *ctx) {
     if (!ctx) return SW_OK;
     Ctx *c = as_ctx(ctx);
+    stop_server(c);
     {
         DeviceGuard dg(c->device);
         (void)hipDeviceSynchronize();
@@ -196,6 +317,9 @@ sw_status sw_ctx_destroy(void *ctx) {
             (void)hipFree(kv.second.d64);
         }
         if (c->scratch) (void)hipFree(c->scratch);
+        for (int i = 0; i < DescRing::kSlots; ++i)
+            if (c->ring.ev[i]) (void)hipEventDestroy(c->ring.ev[i]);
+        if (c->ring.host) (void)hipHostFree(c->ring.host);
     }
     delete c;
     return SW_OK;
@@ -364,6 +488,128 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
     a.curve = curve;
     e = sw::launch_align_pairs(a, geo, *t, s);
     return e == hipSuccess ? SW_OK : hip_fail(e, "k_align_pairs launch");
+}
+
+sw_status sw_align_stacks(void *ctx, const sw_stack *stacks, int32_t n_stacks, int32_t mode,
+                          int32_t prec, int32_t top_k, void *stream) {
+    if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
+    if (n_stacks < 0 || (n_stacks > 0 && !stacks)) return fail(SW_E_INVALID, "bad stack list");
+    if (mode != SW_MODE_ROT_TRANS && mode != SW_MODE_ROT_ONLY)
+        return fail(SW_E_INVALID, "mode = %d is not a sw_mode value", mode);
+    if (prec != SW_PREC_FP32 && prec != SW_PREC_BF16_SPLIT)
+        return fail(SW_E_INVALID, "prec = %d is not a sw_precision value", prec);
+    if (top_k == 0) top_k = prec == SW_PREC_BF16_SPLIT ? 4 : 1;
+    if (top_k < 1 || top_k > sw::kMaxTopK) return fail(SW_E_INVALID, "top_k = %d", top_k);
+    std::vector<const sw_stack *> live;
+    for (int i = 0; i < n_stacks; ++i) {
+        const sw_stack &k = stacks[i];
+        sw::Geo geo;
+        sw_status st = check_geom(&k.geom, &geo);
+        if (st != SW_OK) return fail(st, "stack %d: %s", i, g_err.c_str());
+        if (k.N < 0) return fail(SW_E_INVALID, "stack %d: N < 0", i);
+        if (top_k > geo.n) return fail(SW_E_INVALID, "stack %d: top_k > n", i);
+        if (k.N == 0) continue;
+        if (!k.ref_img || !k.imgs || !k.ref_qt || !k.ref_aux || !k.qt || !k.aux || !k.out)
+            return fail(SW_E_INVALID, "stack %d: a pointer is NULL", i);
+        live.push_back(&k);
+    }
+    if (live.empty()) return SW_OK;
+    // largest images first so that the tail of the work queue is short
+    std::stable_sort(live.begin(), live.end(), [](const sw_stack *a, const sw_stack *b) {
+        return a->geom.L > b->geom.L;
+    });
+    Ctx *c = as_ctx(ctx);
+    DeviceGuard dg(c->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    for (size_t i0 = 0; i0 < live.size(); i0 += sw::kMaxMix) {
+        const int m = (int)std::min(live.size() - i0, (size_t)sw::kMaxMix);
+        sw_status st = run_stack_chunk(c, live.data() + i0, m, mode, prec == SW_PREC_BF16_SPLIT,
+                                       top_k, 0, (hipStream_t)stream);
+        if (st != SW_OK) return st;
+    }
+    return SW_OK;
+}
+
+sw_status sw_autotune(void *ctx, const int32_t *Ls, int32_t nL, int64_t n_images,
+                      const char *out_json) {
+    if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
+    if (nL < 0 || (nL > 0 && !Ls)) return fail(SW_E_INVALID, "bad L list");
+    if (n_images < 1 || n_images > (1 << 20)) return fail(SW_E_INVALID, "n_images out of range");
+    Ctx *c = as_ctx(ctx);
+    DeviceGuard dg(c->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    std::map<int, int> best_R;
+    std::map<int, float> best_ms;
+    for (int li = 0; li < nL; ++li) {
+        const int L = Ls[li];
+        sw_geom g{L, L, L, SW_LEVELS_MIDPOINT};
+        sw::Geo geo;
+        sw_status st = check_geom(&g, &geo);
+        if (st != SW_OK) return st;
+        const size_t nimg = (size_t)n_images * L * L, ntab = (size_t)n_images * L * L;
+        float *img = nullptr, *qt = nullptr, *rqt = nullptr;
+        double *aux = nullptr, *raux = nullptr;
+        sw_result *out = nullptr;
+        hipError_t e = hipMalloc(&img, sizeof(float) * nimg);
+        if (e == hipSuccess) e = hipMalloc(&qt, sizeof(float) * ntab);
+        if (e == hipSuccess) e = hipMalloc(&rqt, sizeof(float) * L * L);
+        if (e == hipSuccess) e = hipMalloc(&aux, sizeof(double) * 4 * n_images);
+        if (e == hipSuccess) e = hipMalloc(&raux, sizeof(double) * 4);
+        if (e == hipSuccess) e = hipMalloc(&out, sizeof(sw_result) * n_images);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = sw::launch_fill_synthetic(img, (int64_t)nimg, nullptr);
+        sw_stack k{img, img, (int64_t)n_images, g, rqt, raux, qt, aux, out};
+        const sw_stack *kp = &k;
+        const int S = sw::strip_stride(L);
+        const int Rmax = std::min(L, 16384 / (2 * S));
+        const int cands[] = {4, 8, 12, 16, 24, 32, 40, 48, 60, 64, 80, 96, 128};
+        for (int R : cands) {
+            if (e != hipSuccess) break;
+            if (R > Rmax) continue;
+            float tbest = 1e30f;
+            for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, nullptr);
+                if (e == hipSuccess) {
+                    st = run_stack_chunk(c, &kp, 1, SW_MODE_ROT_TRANS, 0, 1, R, nullptr);
+                    if (st != SW_OK) e = hipErrorUnknown;
+                }
+                if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0 && ms < tbest) tbest = ms;  // first run warms up
+            }
+            if (e == hipSuccess && (best_R.find(L) == best_R.end() || tbest < best_ms[L])) {
+                best_R[L] = R;
+                best_ms[L] = tbest;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(img);
+        (void)hipFree(qt);
+        (void)hipFree(rqt);
+        (void)hipFree(aux);
+        (void)hipFree(raux);
+        (void)hipFree(out);
+        if (e != hipSuccess) return hip_fail(e, "autotune run");
+    }
+    for (auto &kv : best_R) c->tile_R[kv.first] = kv.second;
+    if (out_json && *out_json) {
+        std::ofstream f(out_json);
+        if (!f) return fail(SW_E_INVALID, "cannot write %s", out_json);
+        f << "{\"tiles\": {";
+        bool firstk = true;
+        for (auto &kv : best_R) {
+            f << (firstk ? "" : ", ") << "\"" << kv.first << "\": {\"R\": " << kv.second
+              << ", \"ms\": " << best_ms[kv.first] << ", \"images\": " << n_images << "}";
+            firstk = false;
+        }
+        f << "}}\n";
+    }
+    return SW_OK;
 }
 
 }  // extern "C"

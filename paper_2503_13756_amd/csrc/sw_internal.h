@@ -88,4 +88,48 @@ struct MfmaArgs {
 bool mfma_path_supported(Geo g);
 hipError_t launch_mfma_all_pairs(const MfmaArgs &a, Geo g, const AngleTable &t, hipStream_t s);
 
+// ---- mixed-geometry persistent launches (uneven stacks, serving) ----
+constexpr int kMaxMix = 64;  // stacks (or requests) per launch
+
+// One stack of images of one geometry aligned against one reference.
+struct MixItem {
+    const float *img;   // [count][L][L]
+    float *qt;          // [count][Q][n]
+    double *aux;        // [count][4]
+    const float *ref_qt;
+    const double *ref_aux;
+    float2 *ref_spec;   // [n/2+1][Q] FP32, written by the launch
+    Result *out;        // [count]
+    const float2 *d32;  // angle table of n
+    const double2 *d64;
+    int64_t first, count;  // work-index range
+    int L, n, Q, levels;
+    int R;      // projection strip rows (tile)
+    int TC;     // quantile column tile
+    int fused;  // PMF kept in LDS
+    int mode, bf16, top_k;
+};
+struct MixGroup {
+    int64_t total;
+    int nitems;
+    int pad;
+    MixItem items[kMaxMix];
+};
+struct MixLaunch {
+    int region_floats, lmax;
+    size_t tables_lds;
+    int64_t slot_floats;
+    size_t align_lds;
+};
+// Fills the per-item tile fields (R clamped, TC, fused) and the launch sizes.
+MixLaunch plan_mixed(MixItem *items, int nitems);
+// Reference tables (group d_refs), reference spectra, image tables and
+// alignment (group d_imgs).  counters: 3 device words; scratch: grid *
+// slot_floats floats.  Capturable: no host-side dependence on the contents.
+hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const MixLaunch &m,
+                        unsigned long long *counters, float *scratch, int grid, hipStream_t s);
+void prepare_mixed();
+
+hipError_t launch_fill_synthetic(float *x, int64_t n, hipStream_t s);
+
 }  // namespace sw

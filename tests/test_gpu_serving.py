@@ -1,0 +1,211 @@
+"""GPU tests of the uneven-stack path (mixed-geometry persistent launches),
+the autotuner, and the continuous-batching server, through the C ABI."""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2503_13756_amd import api as A
+
+    return A
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def stack(L, N, seed):
+    ref, imgs, _, _ = synth.make_stack(seed, L, N, K=6, shift_px=max(1.0, L / 16), jitter_px=1.0,
+                                       snr=1.0)
+    return ref, imgs
+
+
+def oracle_for(oracle, ref, imgs, L):
+    return oracle.align_images(ref, imgs, L, L, want_curve=True)
+
+
+SIDES = [(64, 7), (96, 5), (128, 9), (192, 3), (256, 4), (64, 2)]
+
+
+def test_align_stacks_parity(api, ctx, oracle):
+    data = [stack(L, N, 2000 + i) for i, (L, N) in enumerate(SIDES)]
+    outs = api.align_stacks(ctx, [(dev(r), dev(x)) for r, x in data])
+    for (L, N), (r, x), o in zip(SIDES, data, outs):
+        g = api.unpack_results(o["res"])
+        parity.check(g, oracle_for(oracle, r, x, L), L, parity.TAU_FP32,
+                     oracle_for(oracle, r, x, L)["curve"])
+
+
+def test_align_stacks_matches_single_geometry_path(api, ctx):
+    data = [stack(L, N, 2100 + i) for i, (L, N) in enumerate(SIDES)]
+    outs = api.align_stacks(ctx, [(dev(r), dev(x)) for r, x in data])
+    for (L, N), (r, x), o in zip(SIDES, data, outs):
+        rq, ra = api.tables(ctx, dev(r[None]), L, L)
+        iq, ia = api.tables(ctx, dev(x), L, L)
+        res, _ = api.align_batch(ctx, rq, ra, iq, ia, L)
+        a, b = api.unpack_results(o["res"]), api.unpack_results(res)
+        assert np.array_equal(a["rot_index"], b["rot_index"])
+        assert np.allclose(a["sw2sq"], b["sw2sq"], rtol=1e-5, atol=1e-9)
+        assert np.abs(o["qt"].cpu().numpy() - iq.cpu().numpy()).max() < 1e-6
+
+
+def test_align_stacks_bf16(api, ctx, oracle):
+    data = [stack(L, N, 2200 + i) for i, (L, N) in enumerate(SIDES[:3])]
+    outs = api.align_stacks(ctx, [(dev(r), dev(x)) for r, x in data], prec=1)
+    for (L, N), (r, x), o in zip(SIDES, data, outs):
+        orc = oracle_for(oracle, r, x, L)
+        parity.check(api.unpack_results(o["res"]), orc, L, parity.TAU_BF16, orc["curve"])
+
+
+def test_autotune_table_roundtrip(api, ctx, tmp_path):
+    path = str(tmp_path / "tiles.json")
+    api.autotune(ctx, [64, 128], n_images=256, out_json=path)
+    tiles = json.load(open(path))["tiles"]
+    assert set(tiles) == {"64", "128"}
+    for L, v in tiles.items():
+        assert 1 <= v["R"] <= int(L) and v["ms"] > 0
+    c2 = api.Context(0, tune_json=path)
+    data = [stack(L, N, 2300 + i) for i, (L, N) in enumerate(SIDES[:3])]
+    a = api.align_stacks(c2, [(dev(r), dev(x)) for r, x in data])
+    b = api.align_stacks(ctx, [(dev(r), dev(x)) for r, x in data])
+    for oa, ob in zip(a, b):
+        # the strip height changes neither the summation order nor the result
+        assert np.array_equal(oa["res"].cpu().numpy(), ob["res"].cpu().numpy())
+    c2.close()
+
+
+# ---------------------------------------------------------------- serving
+def wait_all(srv, tickets, timeout=60.0):
+    out, t0 = {}, time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < timeout, "serving timed out"
+        time.sleep(0.001)
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_serving_alone_equals_mix(api, oracle, prec):
+    c = api.Context(0)
+    srv = api.Server(c, hbm_budget_bytes=1 << 30, prec=prec)
+    A = stack(128, 12, 2400)
+    alone = wait_all(srv, [srv.submit(*A)])
+    ra = list(alone.values())[0]
+    mix = [stack(64, 30, 2401), A, stack(256, 5, 2402), stack(128, 20, 2403), A]
+    ts = [srv.submit(r, x) for r, x in mix]
+    got = wait_all(srv, ts)
+    for k in (1, 4):  # A in the mix, twice
+        assert np.array_equal(got[ts[k]], ra)
+    tau = parity.TAU_FP32 if prec == 0 else parity.TAU_BF16
+    for t, (r, x) in zip(ts, mix):
+        L = x.shape[-1]
+        orc = oracle_for(oracle, r, x, L)
+        parity.check(api.records_to_dict(got[t]), orc, L, tau, orc["curve"])
+    st = srv.stats()
+    assert st["completed"] == 6 and st["failed"] == 0
+    srv.stop()
+    c.close()
+
+
+def test_serving_admission_by_budget_and_backpressure(api):
+    c = api.Context(0)
+    L, N = 128, 40
+    per_req = N * L * L * 4 * 2 + 4 * L * L * 3  # images + tables + small parts, roughly
+    budget = int(per_req * 2.5)
+    srv = api.Server(c, hbm_budget_bytes=budget, prec=0, max_queue=3)
+    reqs = [stack(L, N, 2500 + i) for i in range(6)]
+    ts, busy = [], 0
+    for i in range(12):
+        try:
+            ts.append(srv.submit(*reqs[i % 6]))
+        except Exception as e:  # back-pressure: queue full
+            assert "BUSY" in str(e)
+            busy += 1
+    assert busy >= 1 and len(ts) >= 3
+    big = np.zeros((4000, L, L), np.float32)
+    with pytest.raises(Exception) as ei:  # alone larger than the budget
+        srv.submit(reqs[0][0], big)
+    assert "NOMEM" in str(ei.value)
+    got = wait_all(srv, ts)
+    st = srv.stats()
+    assert st["arena_peak"] <= budget
+    assert st["completed"] == len(ts)
+    # the same requests alone give the same results
+    for t, (r, x) in zip(ts, reqs[:2]):
+        one = wait_all(srv, [srv.submit(r, x)])
+        assert np.array_equal(list(one.values())[0], got[t])
+    srv.stop()
+    c.close()
+
+
+def test_serving_graph_replays_match_plain_launches(api):
+    reqs = [stack(64, 9, 2600 + i) for i in range(4)] + [stack(96, 6, 2610)]
+    res = {}
+    for use_graphs in (0, 1):
+        c = api.Context(0)
+        srv = api.Server(c, hbm_budget_bytes=1 << 29, prec=1, use_graphs=use_graphs)
+        outs = []
+        for rep in range(3):  # several replays with host work in between
+            ts = [srv.submit(r, x) for r, x in reqs]
+            got = wait_all(srv, ts)
+            outs.append([got[t] for t in ts])
+            time.sleep(0.01)
+        st = srv.stats()
+        if use_graphs:
+            assert st["graph_launches"] >= 3
+        srv.stop()
+        c.close()
+        for o in outs[1:]:
+            for a, b in zip(o, outs[0]):
+                assert np.array_equal(a, b)
+        res[use_graphs] = outs[0]
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+
+
+def test_serving_reference_cache_and_cancel(api):
+    c = api.Context(0)
+    srv = api.Server(c, hbm_budget_bytes=1 << 29, prec=0)
+    r, x = stack(64, 16, 2700)
+    plain = wait_all(srv, [srv.submit(r, x)])
+    t1 = srv.submit(r, x, ref_key=77)
+    got1 = wait_all(srv, [t1])
+    t2 = srv.submit(r, x[:5], ref_key=77)
+    got2 = wait_all(srv, [t2])
+    assert srv.stats()["cache_hits"] >= 1
+    p = list(plain.values())[0]
+    assert np.array_equal(got1[t1], p) and np.array_equal(got2[t2], p[:5])
+    # cancel: pending or in flight, the ticket is gone afterwards
+    ts = [srv.submit(*stack(128, 50, 2710 + i)) for i in range(4)]
+    srv.cancel(ts[3])
+    with pytest.raises(Exception):
+        srv.poll(ts[3])
+    wait_all(srv, ts[:3])
+    srv.stop()
+    c.close()
