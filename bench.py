@@ -50,6 +50,9 @@ def parse():
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain 512 MiB device copy (HBM counter calibration)")
     p.add_argument("--out", default=None, help="also write the JSON line to this file")
+    p.add_argument("--skip-extra", action="store_true",
+                   help="only the 1-vs-10,000 workload (for profiling runs)")
+    p.add_argument("--requests", type=int, default=400, help="serving trace length")
     return p.parse_args()
 
 
@@ -174,8 +177,19 @@ def main():
         "input_generation_s": t_gen,
     }
 
+    extra_res = {}
+    if not args.skip_extra:
+        del pmf, iq, ia, res
+        torch.cuda.empty_cache()
+        line["all_pairs"], extra_res["all_pairs"] = bench_all_pairs(api, ctx, torch)
+        torch.cuda.empty_cache()
+        line["uneven_stacks"] = bench_uneven(api, ctx, torch)
+        torch.cuda.empty_cache()
+        line["serving"] = bench_serving(api, torch, args.requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, res32, res16, L, n, Q)
+        if "all_pairs" in extra_res:
+            line["cpu_baseline"]["all_pairs_error"] = all_pairs_error(*extra_res["all_pairs"])
 
     s = json.dumps(line)
     print(s, flush=True)
@@ -183,6 +197,202 @@ def main():
         with open(args.out, "w") as f:
             f.write(s + "\n")
     ctx.close()
+
+
+def timed(torch, fn, K, W=1):
+    for _ in range(W):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / K
+
+
+def bench_all_pairs(api, ctx, torch, N=2000, L=64):
+    """All ordered pairs of 2,000 images at L = 64 (4,000,000 alignments):
+    tables, then bf16 angle spectra and the MFMA correlation with top-4 FP32
+    rescoring."""
+    w = synth.workload(2, N=N)
+    imgs = torch.from_numpy(w["imgs"]).cuda()
+    q = torch.empty((N, L, L), dtype=torch.float32, device="cuda")
+    a = torch.empty((N, 4), dtype=torch.float64, device="cuda")
+    res = torch.empty((N * N, 6), dtype=torch.int32, device="cuda")
+    t_tab = timed(torch, lambda: api.tables(ctx, imgs, L, L, out=q, aux=a), 5)
+    t_al = timed(torch, lambda: api.align_batch(ctx, q, a, q, a, L, prec=1, top_k=4, out=res), 5)
+    ms = t_tab + t_al
+    # algorithmic MFMA work: two real GEMMs of K = 2Q per frequency and pair
+    flops = 2.0 * 2.0 * (L // 2 + 1) * (2 * L) * N * N
+    out = {"workload": f"all ordered pairs of {N} images, L={L}, n=Q={L}, bf16 MFMA correlation, "
+                       "top-4 FP32 rescore", "alignments": N * N, "ms_per_step": ms,
+           "value": N * N / (ms * 1e-3), "unit": "alignments/s", "tables_ms": t_tab,
+           "align_ms": t_al, "mfma_flops_per_step": flops}
+    return out, (w, api.unpack_results(res), L)
+
+
+def all_pairs_error(w, g, L, S=1000):
+    """GPU all-pairs results against the FP64 oracle on a seeded sample."""
+    from oracle import oracle as O
+    from tests import parity
+
+    N = len(w["imgs"])
+    rng = np.random.Generator(np.random.PCG64(1002))
+    pairs = np.stack([rng.integers(0, N, S), rng.integers(0, N, S)], axis=1)
+    pairs[:10, 1] = pairs[:10, 0]  # ten diagonal pairs
+    ids = np.unique(pairs)
+    q, a = O.tables(w["imgs"][ids], L, L)
+    remap = {v: i for i, v in enumerate(ids)}
+    lp = np.array([[remap[x] for x in p] for p in pairs])
+    o = O.align(q, a, q, a, L, pairs=lp, want_curve=True)
+    sub = {k: v[pairs[:, 0] * N + pairs[:, 1]] for k, v in g.items()}
+    rel = np.abs(sub["sw2sq"] - o["sw2sq"]) / np.maximum(o["sw2sq"], 1e-12)
+    out = {"pairs": S, "max_rel_err_sw2sq": float(np.max(rel[10:])),
+           "median_rel_err_sw2sq": float(np.median(rel[10:])),
+           "rot_exact_rate": float(np.mean(sub["rot_index"] == o["rot_index"])),
+           "diagonal_zero": bool(np.all(sub["sw2sq"][:10] == 0.0))}
+    try:
+        rep = parity.check(sub, o, L, parity.TAU_BF16, o["curve"])
+        out["parity"] = f"{rep['pairs']} pairs ok (bf16 tolerance)"
+    except AssertionError as e:
+        out["parity"] = "FAILED: " + str(e)[:300]
+    return out
+
+
+def bench_uneven(api, ctx, torch, total=50000, distinct=64):
+    """Stacks of L in {64, 96, 128, 192, 256} with sizes drawn uniformly in
+    [100, 5000] until 50,000 images, each with its own reference, through the
+    mixed persistent launches.  Each stack holds `distinct` rendered copies of
+    its reference, tiled to the drawn size."""
+    stacks = synth.uneven_stacks(total=total, cap_per_stack=distinct)
+    dev = []
+    for L, ref, imgs, size in stacks:
+        x = torch.from_numpy(imgs).cuda()
+        reps = (size + len(imgs) - 1) // len(imgs)
+        dev.append((torch.from_numpy(ref).cuda(), x.repeat(reps, 1, 1)[:size].contiguous()))
+    ms = timed(torch, lambda: api.align_stacks(ctx, dev, prec=1), 3)
+    per_L = {}
+    for L in sorted({s[0] for s in stacks}):
+        sub = [d for d, s in zip(dev, stacks) if s[0] == L]
+        nimg = sum(int(d[1].shape[0]) for d in sub)
+        t = timed(torch, lambda: api.align_stacks(ctx, sub, prec=1), 3)
+        per_L[str(L)] = {"images": nimg, "ms": t, "alignments_per_s": nimg / (t * 1e-3)}
+    n = sum(int(d[1].shape[0]) for d in dev)
+    return {"workload": f"{len(stacks)} stacks, {n} images, L in {{64,96,128,192,256}}, sizes "
+                        "U[100,5000], own reference each, FP32 tables, bf16 correlation, top-4 "
+                        "FP32 rescore", "images": n, "ms_per_step": ms,
+            "value": n / (ms * 1e-3), "unit": "alignments/s", "per_L": per_L}
+
+
+def _pool(L, N, seed):
+    ref, imgs, _, _ = synth.make_stack(seed, L, N)
+    return ref, imgs
+
+
+def bench_serving(api, torch, n_req, Ls=(128,), pool_n=5000, seed=1004):
+    """Poisson trace of requests (1 reference + N images, N log-uniform in
+    [1, 5000]); served bf16 form (continuous batching) against the plain FP32
+    path serving one request at a time.  Images come from a pool of rendered
+    copies per L (requests take slices), so host rendering stays out of the
+    clocks.  Reported: saturated alignments/s (all requests arrive at once)
+    and latency percentiles at a fixed arrival rate of 0.8x the plain form's
+    measured capacity."""
+    import threading
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pools = {L: _pool(L, pool_n, 3000 + L) for L in Ls}
+    reqs = []
+    for _ in range(n_req):
+        L = int(rng.choice(Ls))
+        N = int(max(1, min(5000, round(math.exp(rng.uniform(0, math.log(5000)))))))
+        off = int(rng.integers(0, pool_n - N + 1))
+        reqs.append((L, N, off))
+    total = sum(r[1] for r in reqs)
+
+    def plain(arrivals):
+        ctx = api.Context(0)
+        done = []
+        t0 = time.perf_counter()
+        for (L, N, off), ta in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            ref, imgs = pools[L]
+            x = torch.from_numpy(imgs[off:off + N]).cuda()
+            r = torch.from_numpy(ref[None]).cuda()
+            rq, ra = api.tables(ctx, r, L, L)
+            iq, ia = api.tables(ctx, x, L, L)
+            res, _ = api.align_batch(ctx, rq, ra, iq, ia, L)
+            res.cpu()
+            done.append(time.perf_counter() - t0)
+        ctx.close()
+        return np.array(done)
+
+    def served(arrivals):
+        ctx = api.Context(0)
+        srv = api.Server(ctx, hbm_budget_bytes=16 << 30, prec=1, max_slots=64)
+        tickets = [None] * len(reqs)
+        done = np.zeros(len(reqs))
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i, ((L, N, off), ta) in enumerate(zip(reqs, arrivals)):
+                now = time.perf_counter() - t0
+                if now < ta:
+                    time.sleep(ta - now)
+                ref, imgs = pools[L]
+                while True:
+                    try:
+                        tickets[i] = srv.submit(ref, imgs[off:off + N])
+                        break
+                    except Exception as e:
+                        if "BUSY" not in str(e):
+                            raise
+                        time.sleep(0.0005)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        left = set(range(len(reqs)))
+        while left:
+            for i in list(left):
+                if tickets[i] is not None and srv.poll(tickets[i]) is not None:
+                    done[i] = time.perf_counter() - t0
+                    left.discard(i)
+            time.sleep(0.0002)
+        th.join()
+        st = srv.stats()
+        srv.stop()
+        ctx.close()
+        return done, st
+
+    zero = np.zeros(len(reqs))
+    plain(zero[:8])  # warm-up
+    d_plain = plain(zero)
+    cap_req_s = len(reqs) / d_plain[-1]
+    d_srv, st_sat = served(zero)
+    lam = 0.8 * cap_req_s
+    arr = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
+    arr -= arr[0]
+    d_plain_l = plain(arr)
+    d_srv_l, st_l = served(arr)
+
+    def lat(d):
+        x = (d - arr) * 1e3
+        return {"p50_ms": float(np.percentile(x, 50)), "p99_ms": float(np.percentile(x, 99)),
+                "alignments_per_s": float(total / (d.max() - arr[0]))}
+
+    return {
+        "workload": f"{len(reqs)} requests, L in {list(Ls)}, N log-uniform [1, 5000] "
+                    f"({total} images), Poisson arrivals at {lam:.1f} req/s = 0.8 x plain capacity",
+        "served_bf16": {"saturated_alignments_per_s": float(total / d_srv.max()), **lat(d_srv_l),
+                        "steps": int(st_sat["steps"]), "graph_launches": int(st_sat["graph_launches"]),
+                        "arena_peak_bytes": int(st_sat["arena_peak"])},
+        "plain_fp32_one_at_a_time": {"saturated_alignments_per_s": float(total / d_plain.max()),
+                                     **lat(d_plain_l)},
+        "arrival_rate_req_per_s": lam,
+    }
 
 
 def cpu_baseline(w, S, res32, res16, L, n, Q):

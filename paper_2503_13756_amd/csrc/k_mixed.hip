@@ -40,15 +40,14 @@ __device__ __forceinline__ int64_t next_work(unsigned long long *counter, int64_
 template <int NT, int TPW>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tables_mixed(
     const MixGroup *__restrict__ G, unsigned long long *counter, float *scratch,
-    int64_t slot_floats, int region_floats, int lmax) {
+    int64_t slot_floats, int region_floats, int lmax, int nmax) {
     constexpr int NW = NT / 64;
     extern __shared__ double ldsd[];
-    __shared__ double red[NW][4];
     __shared__ int64_t wslot;
     float *region = (float *)ldsd;
     double *C0 = ldsd + region_floats / 2;
-    float *Ut = (float *)(C0 + NW * (lmax + 1));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *colS = C0 + NW * (lmax + 1);
+    float *Ut = (float *)(colS + 2 * nmax);
     const int64_t total = G->total;
     for (;;) {
         const int64_t w = next_work<NT>(counter, &wslot);
@@ -62,7 +61,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         P.R = it.R;
         P.slots = it.n / 8 + 1;
         P.items = P.slots * it.L;
-        const int L = P.L, n = P.n, Q = it.Q, TC = it.TC;
+        const int L = P.L, n = P.n, Q = it.Q;
         float *pmf = it.fused ? region : scratch + (int64_t)blockIdx.x * slot_floats;
         const float *F = it.img + gi * (int64_t)L * L;
         int bad = 0;
@@ -72,53 +71,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
             for (int t = threadIdx.x; t < n * L; t += NT) pmf[t] = __int_as_float(0x7fc00000);
         __threadfence_block();
         __syncthreads();
-        double *C = C0 + wave * (L + 1);
-        const int ldt = TC + 1;
-        float *U = it.qt + gi * (int64_t)Q * n;
-        double E = 0.0, ar = 0.0, ai = 0.0, mass0 = 0.0;
-        for (int k0 = 0; k0 < n; k0 += TC) {
-            for (int kl = wave; kl < TC; kl += NW) {
-                const int k = k0 + kl;
-                const float *colp = pmf + k * L;
-                double su, sq;
-                const double mass = invert_column([&](int b) { return colp[b]; }, L, Q, it.levels,
-                                                  C, Ut, ldt, kl, lane, &su, &sq);
-                if (k == 0) mass0 = mass;
-                su = wave_sum_d(su);
-                sq = wave_sum_d(sq);
-                const double qbar = su / (double)Q;
-                const double2 d = it.d64[k];
-                E += sq;
-                ar += qbar * d.x;
-                ai += qbar * d.y;
-            }
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < Q * TC; idx += NT) {
-                const int j = idx / TC, kl = idx - j * TC;
-                U[(int64_t)j * n + k0 + kl] = Ut[j * ldt + kl];
-            }
-            __syncthreads();
-        }
-        if (lane == 0) {
-            red[wave][0] = E;
-            red[wave][1] = ar;
-            red[wave][2] = ai;
-            red[wave][3] = mass0;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double e = 0, x = 0, y = 0;
-            for (int v = 0; v < NW; ++v) {
-                e += red[v][0];
-                x += red[v][1];
-                y += red[v][2];
-            }
-            double *A = it.aux + 4 * gi;
-            A[0] = red[0][3];
-            A[1] = e;
-            A[2] = x / (double)n;
-            A[3] = y / (double)n;
-        }
+        quantile_phase<NT>([&](int k, int b) { return pmf[k * L + b]; }, L, n, Q, it.levels, it.TC,
+                           it.d64, C0, Ut, colS, it.qt + gi * (int64_t)Q * n, it.aux + 4 * gi);
     }
 }
 
@@ -168,7 +122,7 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
     constexpr int kStripFloats = 16384;
     constexpr int NT = 256;
     MixLaunch m{};
-    int lmax = 8, region = 0;
+    int lmax = 8, nmax = 8, region = 0;
     int64_t slot = 0;
     size_t align_lds = 0;
     for (int i = 0; i < nitems; ++i) {
@@ -190,13 +144,15 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
         region = max(region, it.fused ? max(strip, pmf) : strip);
         if (!it.fused) slot = max(slot, (int64_t)pmf);
         lmax = max(lmax, it.L);
+        nmax = max(nmax, it.n);
         const int Wn = it.n / 2 + 1;
         const int G = Wn >= NT ? 1 : NT / Wn;
         align_lds = max(align_lds, sizeof(float2) * (it.n + 2 * kFftElems + Wn * G) +
                                        sizeof(double) * it.n);
     }
     region = (region + 1) & ~1;
-    const size_t fixed = sizeof(float) * region + sizeof(double) * (NT / 64) * (lmax + 1);
+    const size_t fixed =
+        sizeof(float) * region + sizeof(double) * ((NT / 64) * (lmax + 1) + 2 * nmax);
     const size_t budget = fixed + 16 * 1024 <= 79 * 1024 ? 79 * 1024 : 150 * 1024;
     int qmax = 8;
     for (int i = 0; i < nitems; ++i) {
@@ -206,6 +162,7 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
     }
     m.region_floats = region;
     m.lmax = lmax;
+    m.nmax = nmax;
     m.tables_lds = fixed + sizeof(float) * qmax;
     m.slot_floats = slot;
     m.align_lds = align_lds;
@@ -235,11 +192,13 @@ hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const Mi
     prepare_mixed();
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, 3);
     hipLaunchKernelGGL((k_tables_mixed<NT, TPW>), dim3((unsigned)grid), dim3(NT), m.tables_lds, s,
-                       d_refs, counters + 0, scratch, m.slot_floats, m.region_floats, m.lmax);
+                       d_refs, counters + 0, scratch, m.slot_floats, m.region_floats, m.lmax,
+                       m.nmax);
     hipLaunchKernelGGL((k_refspec_mixed<NT>), dim3((unsigned)kMaxMix), dim3(NT),
                        sizeof(float2) * (kMaxN + 2 * kFftElems), s, d_imgs);
     hipLaunchKernelGGL((k_tables_mixed<NT, TPW>), dim3((unsigned)grid), dim3(NT), m.tables_lds, s,
-                       d_imgs, counters + 1, scratch, m.slot_floats, m.region_floats, m.lmax);
+                       d_imgs, counters + 1, scratch, m.slot_floats, m.region_floats, m.lmax,
+                       m.nmax);
     hipLaunchKernelGGL((k_align_mixed<NT>), dim3((unsigned)grid), dim3(NT), m.align_lds, s, d_imgs,
                        counters + 2);
     return hipGetLastError();

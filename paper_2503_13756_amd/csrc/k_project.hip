@@ -5,7 +5,7 @@
 namespace sw {
 
 template <int NT, int TPW>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_project(const float *__restrict__ img, int64_t N,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256 ? 2 : 4))) void k_project(const float *__restrict__ img, int64_t N,
                                                 ProjShape P, const float2 *__restrict__ dtab,
                                                 float *__restrict__ pmf) {
     extern __shared__ float lds[];
@@ -40,15 +40,16 @@ hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &
     if (N <= 0) return hipSuccess;
     constexpr int kLdsFloats = 16384;  // 64 KiB: two blocks per CU
     ProjShape P = proj_shape(g.L, g.n, kLdsFloats);
-    const int tpw256 = tasks_per_wave(P.items, 256);
-    if (tpw256 <= 4) return launch_project_t<256, 4>(img, N, P, t.d32, pmf, s);
-    if (tpw256 <= 8) return launch_project_t<256, 8>(img, N, P, t.d32, pmf, s);
-    if (tpw256 <= 12) return launch_project_t<256, 12>(img, N, P, t.d32, pmf, s);
-    const int tpw512 = tasks_per_wave(P.items, 512);
-    if (tpw512 <= 12) return launch_project_t<512, 12>(img, N, P, t.d32, pmf, s);
-    const int tpw1024 = tasks_per_wave(P.items, 1024);
-    if (tpw1024 <= 12) return launch_project_t<1024, 12>(img, N, P, t.d32, pmf, s);
-    return launch_project_t<1024, 20>(img, N, P, t.d32, pmf, s);
+    const int w512 = tasks_per_wave(P.items, 512);
+    if (w512 <= 2) return launch_project_t<512, 2>(img, N, P, t.d32, pmf, s);
+    if (w512 <= 4) return launch_project_t<512, 4>(img, N, P, t.d32, pmf, s);
+    if (w512 <= 6) return launch_project_t<512, 6>(img, N, P, t.d32, pmf, s);
+    if (w512 <= 9) return launch_project_t<512, 9>(img, N, P, t.d32, pmf, s);
+    const int w1024 = tasks_per_wave(P.items, 1024);
+    if (w1024 <= 9) return launch_project_t<1024, 9>(img, N, P, t.d32, pmf, s);
+    if (w1024 <= 12) return launch_project_t<1024, 12>(img, N, P, t.d32, pmf, s);
+    // larger task counts run in several task groups
+    return launch_project_t<1024, 12>(img, N, P, t.d32, pmf, s);
 }
 
 }  // namespace sw

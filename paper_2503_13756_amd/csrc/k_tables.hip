@@ -16,22 +16,20 @@ struct TablesShape {
 };
 
 template <int NT, int TPW>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tables(const float *__restrict__ img, int64_t N,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256 ? 2 : 4))) void k_tables(const float *__restrict__ img, int64_t N,
                                                TablesShape T, const float2 *__restrict__ d32,
                                                const double2 *__restrict__ d64,
                                                float *__restrict__ qt, double *__restrict__ aux) {
     constexpr int NW = NT / 64;
     extern __shared__ double ldsd[];
-    __shared__ double red[NW][4];
     const int64_t g = blockIdx.x;
     if (g >= N) return;
     const ProjShape &P = T.P;
-    const int L = P.L, n = P.n, Q = T.Q, TC = T.TC;
+    const int L = P.L, n = P.n, Q = T.Q;
     float *region = (float *)ldsd;
     double *C0 = ldsd + T.region_floats / 2;
-    float *Ut = (float *)(C0 + NW * (L + 1));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-
+    double *colS = C0 + NW * (L + 1);
+    float *Ut = (float *)(colS + 2 * n);
     const float *F = img + g * (int64_t)L * L;
     int bad = 0;
     project_image<NT, TPW>(F, P, d32, region, bad,
@@ -39,54 +37,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     if (bad)
         for (int t = threadIdx.x; t < n * L; t += NT) region[t] = __int_as_float(0x7fc00000);
     __syncthreads();
-
-    double *C = C0 + wave * (L + 1);
-    const int ldt = TC + 1;
-    float *U = qt + g * (int64_t)Q * n;
-    double E = 0.0, ar = 0.0, ai = 0.0, mass0 = 0.0;
-    for (int k0 = 0; k0 < n; k0 += TC) {
-        for (int kl = wave; kl < TC; kl += NW) {
-            const int k = k0 + kl;
-            const float *colp = region + k * L;
-            double su, sq;
-            const double mass = invert_column([&](int b) { return colp[b]; }, L, Q, T.levels, C, Ut,
-                                              ldt, kl, lane, &su, &sq);
-            if (k == 0) mass0 = mass;
-            su = wave_sum_d(su);
-            sq = wave_sum_d(sq);
-            const double qbar = su / (double)Q;
-            const double2 d = d64[k];
-            E += sq;
-            ar += qbar * d.x;
-            ai += qbar * d.y;
-        }
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < Q * TC; idx += NT) {
-            const int j = idx / TC, kl = idx - j * TC;
-            U[(int64_t)j * n + k0 + kl] = Ut[j * ldt + kl];
-        }
-        __syncthreads();
-    }
-    if (lane == 0) {
-        red[wave][0] = E;
-        red[wave][1] = ar;
-        red[wave][2] = ai;
-        red[wave][3] = mass0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && aux) {
-        double e = 0, x = 0, y = 0;
-        for (int w = 0; w < NW; ++w) {
-            e += red[w][0];
-            x += red[w][1];
-            y += red[w][2];
-        }
-        double *A = aux + 4 * g;
-        A[0] = red[0][3];
-        A[1] = e;
-        A[2] = x / (double)n;
-        A[3] = y / (double)n;
-    }
+    quantile_phase<NT>([&](int k, int b) { return region[k * L + b]; }, L, n, Q, T.levels, T.TC,
+                       d64, C0, Ut, colS, qt + g * (int64_t)Q * n, aux ? aux + 4 * g : nullptr);
 }
 
 // Bytes of LDS the fused kernel needs for a geometry (0 when it cannot run).
@@ -100,7 +52,8 @@ size_t tables_lds_bytes(Geo g, int nt, TablesShape *out) {
     if (region < g.n * g.L) region = g.n * g.L;
     region = (region + 1) & ~1;
     T.region_floats = region;
-    const size_t fixed = sizeof(float) * region + sizeof(double) * (nt / 64) * (g.L + 1);
+    const size_t fixed =
+        sizeof(float) * region + sizeof(double) * ((nt / 64) * (g.L + 1) + 2 * g.n);
     // two blocks per CU when the PMF table allows it (160 KiB of LDS per CU)
     const size_t budget2 = 79 * 1024, budget1 = 150 * 1024;
     const size_t budget = fixed + sizeof(float) * g.Q * 9 <= budget2 ? budget2 : budget1;
@@ -127,8 +80,16 @@ hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t
                          double *aux, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     TablesShape T;
-    const size_t lds = tables_lds_bytes(g, 256, &T);
-    if (lds == 0) return hipErrorInvalidValue;  // caller checks tables_lds_bytes first
+    size_t lds = tables_lds_bytes(g, 512, &T);
+    if (lds != 0 && lds <= 79 * 1024) {
+        const int w = tasks_per_wave(T.P.items, 512);
+        if (w <= 2) return launch_tables_t<512, 2>(img, N, T, lds, t, qt, aux, s);
+        if (w <= 4) return launch_tables_t<512, 4>(img, N, T, lds, t, qt, aux, s);
+        if (w <= 6) return launch_tables_t<512, 6>(img, N, T, lds, t, qt, aux, s);
+        if (w <= 9) return launch_tables_t<512, 9>(img, N, T, lds, t, qt, aux, s);
+    }
+    lds = tables_lds_bytes(g, 256, &T);
+    if (lds == 0) return hipErrorInvalidValue;  // caller checks tables_fused_fits first
     const int tpw = tasks_per_wave(T.P.items, 256);
     if (tpw <= 4) return launch_tables_t<256, 4>(img, N, T, lds, t, qt, aux, s);
     if (tpw <= 8) return launch_tables_t<256, 8>(img, N, T, lds, t, qt, aux, s);

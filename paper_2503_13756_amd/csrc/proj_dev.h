@@ -113,43 +113,50 @@ __device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *
     return t;
 }
 
+// Accumulate one LDS strip into the accumulators of this wave's tasks.  Task
+// slots are the outer loop (a wave-uniform guard each) and rows the inner,
+// unrolled loop, so the LDS reads of consecutive rows are in flight together.
 template <int TPW>
-__device__ __forceinline__ void accumulate_strip(const ProjShape &P, const float *Srow,
-                                                 const float *Tcol, int i0, int rows,
-                                                 const LaneTask (&tk)[TPW], float (&acc)[TPW][4],
-                                                 int my_tasks) {
+__device__ __forceinline__ void accumulate_strip(const ProjShape &P, const float2 *dtab,
+                                                 const float *Srow, int i0, int rows, int tg0,
+                                                 int wave, int nwaves, int lane,
+                                                 float (&acc)[TPW][4], int my_tasks) {
     const int L = P.L, S = P.S;
     const float hi = (float)L + 0.5f;
-    for (int rr = 0; rr < rows; ++rr) {
-        const float fi = (float)(i0 + rr);
-        const float *rowS = Srow + rr * S + kPadLeft;
-        const float *rowT = Tcol + rr * S + kPadLeft;
+    // the transposed strip sits R * S floats after the row strip
+    const int toff = P.R * S;
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) {
-            if (t < my_tasks) {  // wave-uniform
-                float u = fmaf(fi, tk[t].r, tk[t].A);
+    for (int t = 0; t < TPW; ++t) {
+        if (t < my_tasks) {  // wave-uniform
+            const LaneTask tk = make_task(P, dtab, (tg0 + wave + t * nwaves) * 64 + lane);
+            float s0 = acc[t][0], s1 = acc[t][1], s2 = acc[t][2], s3 = acc[t][3];
+            const float *row = Srow + kPadLeft;
+#pragma unroll 4
+            for (int rr = 0; rr < rows; ++rr) {
+                float u = fmaf((float)(i0 + rr), tk.r, tk.A);
                 u = __builtin_amdgcn_fmed3f(u, -1.5f, hi);
                 const float jf = floorf(u);
-                const float cf = tk[t].c * (u - jf);
+                const float cf = tk.c * (u - jf);
                 const int jA = (int)jf;
-                const float w0 = fmaxf(0.f, tk[t].omc - cf);   // column jA - 1
-                const float w1 = 1.f - cf;                      // column jA
-                const float w2 = tk[t].omc + cf;                // column jA + 1
-                const float w3 = fmaxf(0.f, tk[t].om2c + cf);  // column jA + 2
-                const float *a = rowS + jA;
-                const float *b = rowT + jA;
-                const float *fa = rowS + (L - 1 - jA);
-                const float *fb = rowT + (L - 1 - jA);
-                // all sixteen reads first, so they are in flight together
+                const float w0 = __builtin_amdgcn_fmed3f(tk.omc - cf, 0.f, 1.f);   // column jA - 1
+                const float w1 = 1.f - cf;                                          // column jA
+                const float w2 = tk.omc + cf;                                       // column jA + 1
+                const float w3 = __builtin_amdgcn_fmed3f(tk.om2c + cf, 0.f, 1.f);  // column jA + 2
+                const float *a = row + rr * S + jA;
+                const float *fa = row + rr * S + (L - 1 - jA);
                 const float a0 = a[-1], a1 = a[0], a2 = a[1], a3 = a[2];
-                const float b0 = b[-1], b1 = b[0], b2 = b[1], b3 = b[2];
+                const float b0 = a[toff - 1], b1 = a[toff], b2 = a[toff + 1], b3 = a[toff + 2];
                 const float c0 = fa[1], c1 = fa[0], c2 = fa[-1], c3 = fa[-2];
-                const float d0 = fb[1], d1 = fb[0], d2 = fb[-1], d3 = fb[-2];
-                acc[t][0] = fmaf(w3, a3, fmaf(w2, a2, fmaf(w1, a1, fmaf(w0, a0, acc[t][0]))));
-                acc[t][1] = fmaf(w3, b3, fmaf(w2, b2, fmaf(w1, b1, fmaf(w0, b0, acc[t][1]))));
-                acc[t][2] = fmaf(w3, c3, fmaf(w2, c2, fmaf(w1, c1, fmaf(w0, c0, acc[t][2]))));
-                acc[t][3] = fmaf(w3, d3, fmaf(w2, d2, fmaf(w1, d1, fmaf(w0, d0, acc[t][3]))));
+                const float d0 = fa[toff + 1], d1 = fa[toff], d2 = fa[toff - 1], d3 = fa[toff - 2];
+                s0 = fmaf(w3, a3, fmaf(w2, a2, fmaf(w1, a1, fmaf(w0, a0, s0))));
+                s1 = fmaf(w3, b3, fmaf(w2, b2, fmaf(w1, b1, fmaf(w0, b0, s1))));
+                s2 = fmaf(w3, c3, fmaf(w2, c2, fmaf(w1, c1, fmaf(w0, c0, s2))));
+                s3 = fmaf(w3, d3, fmaf(w2, d2, fmaf(w1, d1, fmaf(w0, d0, s3))));
             }
+            acc[t][0] = s0;
+            acc[t][1] = s1;
+            acc[t][2] = s2;
+            acc[t][3] = s3;
         }
     }
 }
@@ -193,13 +200,9 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
                               Emit emit) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    LaneTask tk[TPW];
     float acc[TPW][4];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        tk[t] = make_task(P, dtab, (tg0 + wave + t * NW) * 64 + lane);
-        acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0.f;
-    }
+    for (int t = 0; t < TPW; ++t) acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0.f;
     float *Srow = lds;
     float *Tcol = lds + P.R * P.S;
     const int ntasks = (P.items + 63) / 64;
@@ -211,7 +214,7 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
         __syncthreads();
         stage_strip<NT>(F, P, i0, rows, Srow, Tcol, bad);
         __syncthreads();
-        accumulate_strip<TPW>(P, Srow, Tcol, i0, rows, tk, acc, my_tasks);
+        accumulate_strip<TPW>(P, dtab, Srow, i0, rows, tg0, wave, NW, lane, acc, my_tasks);
     }
     bad_out = __syncthreads_or(bad);
     emit_outputs<TPW>(P, tg0, wave, NW, lane, acc, emit);

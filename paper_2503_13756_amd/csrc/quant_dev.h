@@ -103,6 +103,63 @@ __device__ double invert_column(ColFn col, int L, int Q, int levels, double *C, 
     return mass;
 }
 
+// The whole CDF/quantile phase of one image, shared by the stand-alone,
+// fused and mixed kernels.  col(k, b) reads bin b of column k.  LDS: C
+// (NW * (L + 1) doubles), Ut (Q * (TC + 1) floats), colS (2 n doubles).
+// Column sums are stored per column and reduced by wave 0 in a fixed order,
+// so the per-image scalars do not depend on the block size or tile width.
+template <int NT, typename ColFn>
+__device__ void quantile_phase(ColFn col, int L, int n, int Q, int levels, int TC,
+                               const double2 *__restrict__ d64, double *C0, float *Ut,
+                               double *colS, float *__restrict__ U, double *__restrict__ A) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *C = C0 + wave * (L + 1);
+    const int ldt = TC + 1;
+    double mass0 = 0.0;
+    for (int k0 = 0; k0 < n; k0 += TC) {
+        for (int kl = wave; kl < TC; kl += NW) {
+            const int k = k0 + kl;
+            double su, sq;
+            const double mass = invert_column([&](int b) { return col(k, b); }, L, Q, levels, C,
+                                              Ut, ldt, kl, lane, &su, &sq);
+            if (k == 0) mass0 = mass;
+            su = wave_sum_d(su);
+            sq = wave_sum_d(sq);
+            if (lane == 0) {
+                colS[2 * k] = su;
+                colS[2 * k + 1] = sq;
+            }
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < Q * TC; idx += NT) {
+            const int j = idx / TC, kl = idx - j * TC;
+            U[(int64_t)j * n + k0 + kl] = Ut[j * ldt + kl];
+        }
+        __syncthreads();
+    }
+    if (wave == 0) {
+        double e = 0.0, x = 0.0, y = 0.0;
+        for (int k = lane; k < n; k += 64) {
+            const double qbar = colS[2 * k] / (double)Q;
+            const double2 d = d64[k];
+            e += colS[2 * k + 1];
+            x += qbar * d.x;
+            y += qbar * d.y;
+        }
+        e = wave_sum_d(e);
+        x = wave_sum_d(x);
+        y = wave_sum_d(y);
+        if (lane == 0 && A) {
+            A[0] = mass0;  // column 0 is inverted by wave 0
+            A[1] = e;
+            A[2] = x / (double)n;
+            A[3] = y / (double)n;
+        }
+    }
+    __syncthreads();
+}
+
 inline int pick_tc(int n, int Q, size_t budget) {
     const int cands[4] = {64, 32, 16, 8};
     for (int c : cands)

@@ -116,7 +116,7 @@ struct MixGroup {
     MixItem items[kMaxMix];
 };
 struct MixLaunch {
-    int region_floats, lmax;
+    int region_floats, lmax, nmax;
     size_t tables_lds;
     int64_t slot_floats;
     size_t align_lds;
