@@ -32,6 +32,42 @@ METRIC = "alignments/s at L=128, plain FP32 vs served BF16 form; p50/p99 latency
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 
+# HBM traffic of the fused tables kernel on this workload, from two rocprofv3
+# counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a plain copy kernel; only
+# used while the kernel's sources are the ones the counters were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tables_L128_10k_hbm.txt")
+TABLES_SOURCES = ["k_tables.hip", "proj_dev.h", "quant_dev.h", "sw_internal.h"]
+
+
+def tables_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in TABLES_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_13756_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """(bytes per launch, note) from the counter summary, or (None, why)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary"
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256") != tables_sources_sha256():
+        return None, "kernel changed since the counters were taken"
+    return float(kv["traffic_bytes_per_launch"]), os.path.relpath(TRAFFIC_FILE, ROOT)
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
 
 def disk_pixels(L):
     j = np.arange(L)
@@ -45,7 +81,8 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--images", type=int, default=10000)
-    p.add_argument("--cpu-sample", type=int, default=2000)
+    p.add_argument("--cpu-sample", type=int, default=10000,
+                   help="images of the workload the oracle aligns for the CPU baseline")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a plain 512 MiB device copy (HBM counter calibration)")
@@ -59,8 +96,9 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the workload is data-parallel over images; see the sharding notes)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path "
+              "is data-parallel over images and would shard by image stacks, which is not "
+              "implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -123,10 +161,13 @@ def main():
         return wall * 1e3, seg.mean(axis=0), seg
 
     K, W = args.steps, args.warmup
+    log(f"inputs ready ({t_gen:.1f} s); timing {K} FP32 steps after {W} warm-up")
     ms32, seg32, _ = run(lambda ev: step(0, ev), K, W, 4)
     res32 = api.unpack_results(res)
+    log(f"FP32 {ms32:.3f} ms/step; timing BF16-split steps")
     ms16, seg16, _ = run(lambda ev: step(1, ev), K, W, 4)
     res16 = api.unpack_results(res)
+    log(f"BF16 {ms16:.3f} ms/step; timing staged tables")
     mss, segs, _ = run(staged_step, max(3, K // 4), 1, 3)
 
     value = N / (ms32 * 1e-3)
@@ -153,12 +194,17 @@ def main():
                 "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
+    if roof["kernel"] == "k_tables":
+        roof["algorithmic_bytes"] = bytes_tables
+        roof["traffic"], roof["traffic_source"] = measured_traffic()
 
     if args.copy_probe:
-        a = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+        # a plain elementwise kernel over 512 MiB (reads 512 MiB, writes
+        # 512 MiB): the reference for scaling the HBM byte counters
+        a = torch.ones(128 << 20, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
 
@@ -181,12 +227,16 @@ def main():
     if not args.skip_extra:
         del pmf, iq, ia, res
         torch.cuda.empty_cache()
+        log("all pairs")
         line["all_pairs"], extra_res["all_pairs"] = bench_all_pairs(api, ctx, torch)
         torch.cuda.empty_cache()
+        log("uneven stacks")
         line["uneven_stacks"] = bench_uneven(api, ctx, torch)
         torch.cuda.empty_cache()
+        log("serving trace")
         line["serving"] = bench_serving(api, torch, args.requests)
     if not args.no_cpu_baseline:
+        log("CPU baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, res32, res16, L, n, Q)
         if "all_pairs" in extra_res:
             line["cpu_baseline"]["all_pairs_error"] = all_pairs_error(*extra_res["all_pairs"])
@@ -371,11 +421,14 @@ def bench_serving(api, torch, n_req, Ls=(128,), pool_n=5000, seed=1004):
     plain(zero[:8])  # warm-up
     d_plain = plain(zero)
     cap_req_s = len(reqs) / d_plain[-1]
+    log(f"serving: plain saturated {d_plain[-1]:.2f} s")
     d_srv, st_sat = served(zero)
+    log(f"serving: served saturated {d_srv.max():.2f} s")
     lam = 0.8 * cap_req_s
     arr = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
     arr -= arr[0]
     d_plain_l = plain(arr)
+    log("serving: plain at fixed rate done")
     d_srv_l, st_l = served(arr)
 
     def lat(d):
@@ -406,7 +459,9 @@ def cpu_baseline(w, S, res32, res16, L, n, Q):
     o = O.align_images(w["ref"], w["imgs"][:S], n, Q, want_curve=True)
     dt = time.perf_counter() - t0
     out = {"value": S / dt, "unit": "alignments/s", "cores": O.num_threads(), "kind": "oracle",
-           "sample": f"first {S} of the images against the reference, whole path (FP64)",
+           "sample": (f"all {S} images against the reference" if S == len(w["imgs"]) else
+                      f"first {S} of the images against the reference") +
+                     ", whole path (projection, quantiles, all lags, translation; FP64)",
            "seconds": dt}
     for name, r, tau in (("fp32", res32, parity.TAU_FP32), ("bf16_split", res16, parity.TAU_BF16)):
         sub = {k: v[:S] for k, v in r.items()}

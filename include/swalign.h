@@ -99,7 +99,10 @@ typedef struct {
 } sw_result;
 
 /* Context: binds a device and owns scratch.  tune_json (host, nullable) is a
-   path to a tile table written by the autotuner. */
+   path to a JSON file with optional keys: "tiles" (the table written by
+   sw_autotune) and "small_batch": calls on fewer images than this take the
+   split launches (several blocks per image; default: the number of compute
+   units).  Both change launch shapes only, never results. */
 sw_status sw_ctx_create(void **ctx, int device, const char *tune_json);
 sw_status sw_ctx_destroy(void *ctx);
 const char *sw_last_error(void);

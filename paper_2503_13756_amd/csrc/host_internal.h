@@ -34,6 +34,10 @@ struct Ctx {
     std::mutex mu;
     std::map<int, sw::AngleTable> tables;
     std::map<int, int> tile_R;  // projection strip rows per L (autotuner)
+    // batches of fewer images take the split (many blocks per image) launches;
+    // -1: the number of compute units
+    int small_batch = -1;
+    bool small(int64_t N) const { return N < (small_batch >= 0 ? small_batch : cu_count); }
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     DescRing ring;

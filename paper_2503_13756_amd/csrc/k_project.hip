@@ -23,6 +23,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256
     }
 }
 
+// Small batches: one block per (image, task group), so that a single image
+// spreads over many compute units.  Every block stages the whole image.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_project_split(const float *__restrict__ img, int64_t N,
+                                                      ProjShape P, const float2 *__restrict__ dtab,
+                                                      float *__restrict__ pmf) {
+    extern __shared__ float lds[];
+    const int64_t g = blockIdx.x;
+    if (g >= N) return;
+    const float *F = img + g * (int64_t)P.L * P.L;
+    float *out = pmf + g * (int64_t)P.n * P.L;
+    int bad = 0;
+    project_group<NT, 1>(F, P, dtab, lds, (int)blockIdx.y * (NT / 64), bad,
+                         [&](int k, int b, float v) { out[k * P.L + b] = v; });
+    if (bad && blockIdx.y == 0)
+        for (int t = threadIdx.x; t < P.n * P.L; t += NT) out[t] = __int_as_float(0x7fc00000);
+}
+
 template <int NT, int TPW>
 static hipError_t launch_project_t(const float *img, int64_t N, const ProjShape &P,
                                    const float2 *dtab, float *pmf, hipStream_t s) {
@@ -36,10 +54,22 @@ static hipError_t launch_project_t(const float *img, int64_t N, const ProjShape 
 }
 
 hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &t, float *pmf,
-                          hipStream_t s) {
+                          hipStream_t s, bool split) {
     if (N <= 0) return hipSuccess;
     constexpr int kLdsFloats = 16384;  // 64 KiB: two blocks per CU
     ProjShape P = proj_shape(g.L, g.n, kLdsFloats);
+    if (split) {
+        constexpr int NT = 128;
+        const int groups = (P.items + 64 * (NT / 64) - 1) / (64 * (NT / 64));
+        const size_t lds = sizeof(float) * 2 * P.R * P.S;
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void *)k_project_split<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+            96 * 1024);
+        (void)attr;
+        hipLaunchKernelGGL((k_project_split<NT>), dim3((unsigned)N, (unsigned)groups), dim3(NT),
+                           lds, s, img, N, P, t.d32, pmf);
+        return hipGetLastError();
+    }
     const int w512 = tasks_per_wave(P.items, 512);
     if (w512 <= 2) return launch_project_t<512, 2>(img, N, P, t.d32, pmf, s);
     if (w512 <= 4) return launch_project_t<512, 4>(img, N, P, t.d32, pmf, s);

@@ -22,16 +22,27 @@ __global__ __launch_bounds__(NT) void k_quantile(const float *__restrict__ pmf, 
                        d64, C0, Ut, colS, qt + g * (int64_t)Q * n, aux ? aux + 4 * g : nullptr);
 }
 
-hipError_t launch_quantiles(const float *pmf, int64_t N, Geo g, const AngleTable &t, float *qt,
-                            double *aux, hipStream_t s) {
-    if (N <= 0) return hipSuccess;
-    constexpr int NT = 256;
+template <int NT>
+static hipError_t launch_quantiles_t(const float *pmf, int64_t N, Geo g, const AngleTable &t,
+                                     float *qt, double *aux, hipStream_t s) {
     QuantShape<NT> S{g.L, g.n, g.Q, g.levels, pick_tc(g.n, g.Q, 68 * 1024)};
     const size_t lds = sizeof(double) * ((NT / 64) * (g.L + 1) + 2 * g.n) +
                        sizeof(float) * g.Q * (S.TC + 1);
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_quantile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
+    (void)attr;
     hipLaunchKernelGGL((k_quantile<NT>), dim3((unsigned)N), dim3(NT), lds, s, pmf, N, S, t.d64, qt,
                        aux);
     return hipGetLastError();
+}
+
+// Small batches take 16 waves per image (columns in parallel); the results
+// do not depend on the block size.
+hipError_t launch_quantiles(const float *pmf, int64_t N, Geo g, const AngleTable &t, float *qt,
+                            double *aux, hipStream_t s, bool small) {
+    if (N <= 0) return hipSuccess;
+    if (small) return launch_quantiles_t<1024>(pmf, N, g, t, qt, aux, s);
+    return launch_quantiles_t<256>(pmf, N, g, t, qt, aux, s);
 }
 
 }  // namespace sw

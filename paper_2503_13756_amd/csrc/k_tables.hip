@@ -48,6 +48,8 @@ size_t tables_lds_bytes(Geo g, int nt, TablesShape *out) {
     T.P = proj_shape(g.L, g.n, kStripFloats);
     T.Q = g.Q;
     T.levels = g.levels;
+    // all tasks in one group: the PMF table is written over the strip buffers
+    if (tasks_per_wave(T.P.items, nt) > (nt >= 512 ? 9 : 20)) return 0;
     int region = 2 * T.P.R * T.P.S;
     if (region < g.n * g.L) region = g.n * g.L;
     region = (region + 1) & ~1;

@@ -217,7 +217,8 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
         accumulate_strip<TPW>(P, dtab, Srow, i0, rows, tg0, wave, NW, lane, acc, my_tasks);
     }
     bad_out = __syncthreads_or(bad);
-    emit_outputs<TPW>(P, tg0, wave, NW, lane, acc, emit);
+    // an image with a non-finite value emits nothing; the caller fills it
+    if (!bad_out) emit_outputs<TPW>(P, tg0, wave, NW, lane, acc, emit);
 }
 
 // Full projection of one image: as many task groups as needed.  emit must

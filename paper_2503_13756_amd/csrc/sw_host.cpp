@@ -300,6 +300,9 @@ sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
         for (auto it = std::sregex_iterator(txt.begin(), txt.end(), re); it != std::sregex_iterator();
              ++it)
             c->tile_R[std::stoi((*it)[1])] = std::stoi((*it)[2]);
+        std::smatch m;
+        if (std::regex_search(txt, m, std::regex("\"small_batch\"\\s*:\\s*(\\d+)")))
+            c->small_batch = std::stoi(m[1]);
     }
     *ctx = c;
     return SW_OK;
@@ -339,7 +342,8 @@ sw_status sw_project(void *ctx, const float *img, int64_t N, const sw_geom *g, f
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
     const sw::AngleTable *t;
     if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
-    hipError_t e = sw::launch_project(img, N, geo, *t, pmf, (hipStream_t)stream);
+    hipError_t e = sw::launch_project(img, N, geo, *t, pmf, (hipStream_t)stream,
+                                      c->small(N));
     return e == hipSuccess ? SW_OK : hip_fail(e, "k_project launch");
 }
 
@@ -357,7 +361,8 @@ sw_status sw_quantiles(void *ctx, const float *pmf, int64_t N, const sw_geom *g,
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
     const sw::AngleTable *t;
     if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
-    hipError_t e = sw::launch_quantiles(pmf, N, geo, *t, qt, aux, (hipStream_t)stream);
+    hipError_t e = sw::launch_quantiles(pmf, N, geo, *t, qt, aux, (hipStream_t)stream,
+                                        c->small(N));
     return e == hipSuccess ? SW_OK : hip_fail(e, "k_quantile launch");
 }
 
@@ -376,12 +381,16 @@ sw_status sw_tables(void *ctx, const float *img, int64_t N, const sw_geom *g, fl
     const sw::AngleTable *t;
     if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    if (sw::tables_fused_fits(geo)) {
+    // Fewer images than compute units: one block per image would leave most
+    // of the device idle, so project with one block per (image, task group)
+    // and invert with 16 waves per image, through scratch.
+    const bool small = c->small(N);
+    if (!small && sw::tables_fused_fits(geo)) {
         hipError_t e = sw::launch_tables(img, N, geo, *t, qt, aux, s);
         return e == hipSuccess ? SW_OK : hip_fail(e, "k_tables launch");
     }
-    // The PMF table of one image does not fit in LDS: project and invert in
-    // chunks of images through a bounded scratch buffer.
+    // Otherwise the PMF table of one image does not fit in LDS: project and
+    // invert in chunks of images through a bounded scratch buffer.
     const size_t per = sizeof(float) * (size_t)geo.n * geo.L;
     int64_t chunk = (int64_t)((size_t)256 << 20) / (int64_t)per;
     if (chunk < 1) chunk = 1;
@@ -391,10 +400,10 @@ sw_status sw_tables(void *ctx, const float *img, int64_t N, const sw_geom *g, fl
     for (int64_t i0 = 0; i0 < N; i0 += chunk) {
         const int64_t m = N - i0 < chunk ? N - i0 : chunk;
         hipError_t e = sw::launch_project(img + i0 * (int64_t)geo.L * geo.L, m, geo, *t,
-                                          (float *)pmf, s);
+                                          (float *)pmf, s, small);
         if (e != hipSuccess) return hip_fail(e, "k_project launch");
         e = sw::launch_quantiles((const float *)pmf, m, geo, *t, qt + i0 * (int64_t)geo.Q * geo.n,
-                                 aux ? aux + 4 * i0 : nullptr, s);
+                                 aux ? aux + 4 * i0 : nullptr, s, small);
         if (e != hipSuccess) return hip_fail(e, "k_quantile launch");
     }
     return SW_OK;

@@ -41,10 +41,12 @@ struct Result {
 static_assert(sizeof(Result) == 24, "sw_result is 24 bytes");
 
 // ---- launchers (each returns hipGetLastError() after its launches) ----
+// split: one block per (image, task group), for batches too small to fill the
+// device with one block per image
 hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &t, float *pmf,
-                          hipStream_t s);
+                          hipStream_t s, bool split = false);
 hipError_t launch_quantiles(const float *pmf, int64_t N, Geo g, const AngleTable &t, float *qt,
-                            double *aux, hipStream_t s);
+                            double *aux, hipStream_t s, bool small = false);
 // Fused image -> quantile table; only for geometries where
 // tables_fused_fits() holds (the PMF table must fit in LDS).
 bool tables_fused_fits(Geo g);

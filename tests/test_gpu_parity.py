@@ -24,10 +24,23 @@ def api():
 
 
 @pytest.fixture(scope="module")
-def ctx(api):
-    c = api.Context(0)
-    yield c
-    c.close()
+def ctxs(api, tmp_path_factory):
+    """Contexts for the two launch policies of the image stages: one block
+    per image (fused tables kernel) and several blocks per image (split
+    projection, then the 16-wave quantile kernel)."""
+    out = {}
+    for name, thr in (("perimage", 0), ("split", 1 << 30)):
+        path = tmp_path_factory.mktemp("tune") / f"{name}.json"
+        path.write_text('{"small_batch": %d}' % thr)
+        out[name] = api.Context(0, tune_json=str(path))
+    yield out
+    for c in out.values():
+        c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx(ctxs):
+    return ctxs["perimage"]
 
 
 def dev(x):
@@ -46,23 +59,25 @@ GEOMS = [(16, 16, 16), (40, 24, 20), (64, 64, 64), (96, 96, 96), (128, 128, 128)
          (64, 128, 48), (192, 192, 192), (256, 256, 256)]
 
 
+@pytest.mark.parametrize("policy", ["perimage", "split"])
 @pytest.mark.parametrize("L,n,Q", GEOMS)
-def test_project_parity(api, ctx, oracle, L, n, Q):
+def test_project_parity(api, ctxs, oracle, L, n, Q, policy):
     ref, imgs = blob_stack(L, 5, 100 + L)
     imgs = np.concatenate([imgs, synth.uniform_images(7, L, 2)])
-    pmf = api.project(ctx, dev(imgs), n).cpu().numpy()
+    pmf = api.project(ctxs[policy], dev(imgs), n).cpu().numpy()
     P0, _ = oracle.project(imgs, n)
     err = np.abs(pmf - P0).max(axis=(1, 2)) / P0.max(axis=(1, 2))
     assert err.max() < 1e-5, err
 
 
+@pytest.mark.parametrize("policy", ["perimage", "split"])
 @pytest.mark.parametrize("L,n,Q", GEOMS)
 @pytest.mark.parametrize("levels", [0, 1])
-def test_quantile_parity(api, ctx, oracle, L, n, Q, levels):
+def test_quantile_parity(api, ctxs, oracle, L, n, Q, levels, policy):
     _, imgs = blob_stack(L, 4, 200 + L)
     P0, _ = oracle.project(imgs, n)
     pmf32 = P0.astype(np.float32)
-    qt, aux = api.quantiles(ctx, dev(pmf32), Q, levels)
+    qt, aux = api.quantiles(ctxs[policy], dev(pmf32), Q, levels)
     q0, a0 = oracle.quantiles(pmf32.astype(np.float64), Q, levels)
     qt, aux = qt.cpu().numpy(), aux.cpu().numpy()
     assert np.abs(qt - q0).max() < 2e-6
@@ -72,13 +87,18 @@ def test_quantile_parity(api, ctx, oracle, L, n, Q, levels):
 
 
 @pytest.mark.parametrize("L,n,Q", GEOMS)
-def test_tables_fused_equals_staged(api, ctx, L, n, Q):
+def test_tables_fused_equals_staged(api, ctxs, L, n, Q):
+    """Fused, staged and split launches give bitwise-equal tables."""
     _, imgs = blob_stack(L, 6, 300 + L)
     x = dev(imgs)
+    ctx, cs = ctxs["perimage"], ctxs["split"]
     q1, a1 = api.tables(ctx, x, n, Q)
     q2, a2 = api.quantiles(ctx, api.project(ctx, x, n), Q)
-    assert np.array_equal(q1.cpu().numpy(), q2.cpu().numpy())
-    assert np.array_equal(a1.cpu().numpy(), a2.cpu().numpy())
+    q3, a3 = api.tables(cs, x, n, Q)
+    q4, a4 = api.quantiles(cs, api.project(ctx, x, n), Q)
+    for q, a in ((q2, a2), (q3, a3), (q4, a4)):
+        assert np.array_equal(q1.cpu().numpy(), q.cpu().numpy())
+        assert np.array_equal(a1.cpu().numpy(), a.cpu().numpy())
 
 
 def oracle_results(oracle, rq, ra, iq, ia, L, pairs=None, mode=0):
@@ -190,6 +210,12 @@ def test_deterministic_and_independent_of_batch(api, ctx):
     assert np.array_equal(r_all.cpu().numpy()[7], r_one.cpu().numpy()[0])
     q3, a3 = api.tables(ctx, x[7:8].contiguous(), n, n)
     assert np.array_equal(q3.cpu().numpy()[0], q1.cpu().numpy()[7])
+    # the default policy (one image: split launches) agrees bitwise
+    c = api.Context(0)
+    q4, a4 = api.tables(c, x[7:8].contiguous(), n, n)
+    c.close()
+    assert np.array_equal(q4.cpu().numpy()[0], q1.cpu().numpy()[7])
+    assert np.array_equal(a4.cpu().numpy()[0], a1.cpu().numpy()[7])
 
 
 def test_status_codes_and_empty(api, ctx):
