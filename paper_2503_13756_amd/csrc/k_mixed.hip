@@ -40,13 +40,12 @@ __device__ __forceinline__ int64_t next_work(unsigned long long *counter, int64_
 template <int NT, int TPW>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tables_mixed(
     const MixGroup *__restrict__ G, unsigned long long *counter, float *scratch,
-    int64_t slot_floats, int region_floats, int lmax, int nmax) {
+    int64_t slot_floats, int region_floats, int /*lmax*/, int nmax) {
     constexpr int NW = NT / 64;
     extern __shared__ double ldsd[];
     __shared__ int64_t wslot;
     float *region = (float *)ldsd;
-    double *C0 = ldsd + region_floats / 2;
-    double *colS = C0 + NW * (lmax + 1);
+    double *colS = ldsd + region_floats / 2;
     float *Ut = (float *)(colS + 2 * nmax);
     const int64_t total = G->total;
     for (;;) {
@@ -58,6 +57,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         P.L = it.L;
         P.n = it.n;
         P.S = strip_stride(it.L);
+        P.RS = strip_row_floats(it.L);
         P.R = it.R;
         P.slots = it.n / 8 + 1;
         P.items = P.slots * it.L;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         __threadfence_block();
         __syncthreads();
         quantile_phase<NT>([&](int k, int b) { return pmf[k * L + b]; }, L, n, Q, it.levels, it.TC,
-                           it.d64, C0, Ut, colS, it.qt + gi * (int64_t)Q * n, it.aux + 4 * gi);
+                           it.d64, Ut, colS, it.qt + gi * (int64_t)Q * n, it.aux + 4 * gi);
     }
 }
 
@@ -119,7 +119,6 @@ __global__ __launch_bounds__(NT) void k_align_mixed(const MixGroup *__restrict__
 // LDS and scratch needs of a set of items; fills the per-item tile fields
 // (fused, TC) and returns the launch parameters.
 MixLaunch plan_mixed(MixItem *items, int nitems) {
-    constexpr int kStripFloats = 16384;
     constexpr int NT = 256;
     MixLaunch m{};
     int lmax = 8, nmax = 8, region = 0;
@@ -127,9 +126,8 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
     size_t align_lds = 0;
     for (int i = 0; i < nitems; ++i) {
         MixItem &it = items[i];
-        const int S = strip_stride(it.L);
-        int R = it.R > 0 ? it.R : kStripFloats / (2 * S);
-        if (R > kStripFloats / (2 * S)) R = kStripFloats / (2 * S);
+        int R = it.R > 0 ? it.R : strip_rows_max(it.L);
+        if (R > strip_rows_max(it.L)) R = strip_rows_max(it.L);
         if (R > it.L) R = it.L;
         if (R < 1) R = 1;
         if (R > NT) R = NT;
@@ -137,7 +135,7 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
         const int slots = it.n / 8 + 1;
         const int ntasks = (slots * it.L + 63) / 64;
         const bool one_group = ntasks <= (NT / 64) * 12;
-        const int strip = 2 * R * S;
+        const int strip = kStripFloats;
         const int pmf = it.n * it.L;
         // fused when a single task group and the PMF fits beside nothing else
         it.fused = one_group && pmf <= kStripFloats ? 1 : 0;
@@ -151,8 +149,7 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
                                        sizeof(double) * it.n);
     }
     region = (region + 1) & ~1;
-    const size_t fixed =
-        sizeof(float) * region + sizeof(double) * ((NT / 64) * (lmax + 1) + 2 * nmax);
+    const size_t fixed = sizeof(float) * region + sizeof(double) * 2 * nmax;
     const size_t budget = fixed + 16 * 1024 <= 79 * 1024 ? 79 * 1024 : 150 * 1024;
     int qmax = 8;
     for (int i = 0; i < nitems; ++i) {

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(NT) void k_project_split(const float *__restrict__ 
 template <int NT, int TPW>
 static hipError_t launch_project_t(const float *img, int64_t N, const ProjShape &P,
                                    const float2 *dtab, float *pmf, hipStream_t s) {
-    const size_t lds = sizeof(float) * 2 * P.R * P.S;
+    const size_t lds = sizeof(float) * kStripFloats;
     static const hipError_t attr = hipFuncSetAttribute(
         (const void *)k_project<NT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     (void)attr;
@@ -56,12 +56,11 @@ static hipError_t launch_project_t(const float *img, int64_t N, const ProjShape 
 hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &t, float *pmf,
                           hipStream_t s, bool split) {
     if (N <= 0) return hipSuccess;
-    constexpr int kLdsFloats = 16384;  // 64 KiB: two blocks per CU
-    ProjShape P = proj_shape(g.L, g.n, kLdsFloats);
+    ProjShape P = proj_shape(g.L, g.n);  // 64 KiB of strips: two blocks per CU
     if (split) {
         constexpr int NT = 128;
         const int groups = (P.items + 64 * (NT / 64) - 1) / (64 * (NT / 64));
-        const size_t lds = sizeof(float) * 2 * P.R * P.S;
+        const size_t lds = sizeof(float) * kStripFloats;
         static const hipError_t attr = hipFuncSetAttribute(
             (const void *)k_project_split<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
             96 * 1024);

@@ -14,20 +14,18 @@ __global__ __launch_bounds__(NT) void k_quantile(const float *__restrict__ pmf, 
     const int64_t g = blockIdx.x;
     if (g >= N) return;
     const int L = S.L, n = S.n, Q = S.Q;
-    double *C0 = ldsd;
-    double *colS = ldsd + NW * (L + 1);
+    double *colS = ldsd;
     float *Ut = (float *)(colS + 2 * n);
     const float *P = pmf + g * (int64_t)n * L;
     quantile_phase<NT>([&](int k, int b) { return P[(int64_t)k * L + b]; }, L, n, Q, S.levels, S.TC,
-                       d64, C0, Ut, colS, qt + g * (int64_t)Q * n, aux ? aux + 4 * g : nullptr);
+                       d64, Ut, colS, qt + g * (int64_t)Q * n, aux ? aux + 4 * g : nullptr);
 }
 
 template <int NT>
 static hipError_t launch_quantiles_t(const float *pmf, int64_t N, Geo g, const AngleTable &t,
                                      float *qt, double *aux, hipStream_t s) {
     QuantShape<NT> S{g.L, g.n, g.Q, g.levels, pick_tc(g.n, g.Q, 68 * 1024)};
-    const size_t lds = sizeof(double) * ((NT / 64) * (g.L + 1) + 2 * g.n) +
-                       sizeof(float) * g.Q * (S.TC + 1);
+    const size_t lds = sizeof(double) * 2 * g.n + sizeof(float) * g.Q * (S.TC + 1);
     static const hipError_t attr = hipFuncSetAttribute(
         (const void *)k_quantile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
     (void)attr;

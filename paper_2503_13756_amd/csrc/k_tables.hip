@@ -27,8 +27,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256
     const ProjShape &P = T.P;
     const int L = P.L, n = P.n, Q = T.Q;
     float *region = (float *)ldsd;
-    double *C0 = ldsd + T.region_floats / 2;
-    double *colS = C0 + NW * (L + 1);
+    double *colS = ldsd + T.region_floats / 2;
     float *Ut = (float *)(colS + 2 * n);
     const float *F = img + g * (int64_t)L * L;
     int bad = 0;
@@ -38,24 +37,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256
         for (int t = threadIdx.x; t < n * L; t += NT) region[t] = __int_as_float(0x7fc00000);
     __syncthreads();
     quantile_phase<NT>([&](int k, int b) { return region[k * L + b]; }, L, n, Q, T.levels, T.TC,
-                       d64, C0, Ut, colS, qt + g * (int64_t)Q * n, aux ? aux + 4 * g : nullptr);
+                       d64, Ut, colS, qt + g * (int64_t)Q * n, aux ? aux + 4 * g : nullptr);
 }
 
 // Bytes of LDS the fused kernel needs for a geometry (0 when it cannot run).
 size_t tables_lds_bytes(Geo g, int nt, TablesShape *out) {
-    constexpr int kStripFloats = 16384;
     TablesShape T;
-    T.P = proj_shape(g.L, g.n, kStripFloats);
+    T.P = proj_shape(g.L, g.n);
     T.Q = g.Q;
     T.levels = g.levels;
     // all tasks in one group: the PMF table is written over the strip buffers
     if (tasks_per_wave(T.P.items, nt) > (nt >= 512 ? 9 : 20)) return 0;
-    int region = 2 * T.P.R * T.P.S;
+    int region = kStripFloats;
     if (region < g.n * g.L) region = g.n * g.L;
     region = (region + 1) & ~1;
     T.region_floats = region;
-    const size_t fixed =
-        sizeof(float) * region + sizeof(double) * ((nt / 64) * (g.L + 1) + 2 * g.n);
+    const size_t fixed = sizeof(float) * region + sizeof(double) * 2 * g.n;
     // two blocks per CU when the PMF table allows it (160 KiB of LDS per CU)
     const size_t budget2 = 79 * 1024, budget1 = 150 * 1024;
     const size_t budget = fixed + sizeof(float) * g.Q * 9 <= budget2 ? budget2 : budget1;

@@ -19,9 +19,10 @@
 // built with these symmetries exact.
 //
 // The image is staged through LDS in strips of R rows together with the same
-// R columns transposed, so that all four variants read along LDS rows (lanes
-// take consecutive bins, hence near-consecutive columns: conflict-light with
-// an odd row stride).  Accumulators live in registers across strips.
+// R columns transposed (layout in sw_internal.h: four shifted copies of each,
+// so that every four-pixel window is one aligned 16-byte LDS read), so that
+// all four variants read along LDS rows.  Accumulators live in registers
+// across strips.
 #pragma once
 #include "sw_internal.h"
 
@@ -34,57 +35,83 @@ __device__ __forceinline__ bool in_disk(int L, int i, int j) {
 }
 
 struct ProjShape {
-    int L, n, S, R, slots, items;
+    int L, n, S, RS, R, slots, items;  // S positions per copy, RS floats per strip row
 };
 
-__host__ inline ProjShape proj_shape(int L, int n, int lds_floats) {
+// R: requested strip rows (0: as many as fit).
+__host__ inline ProjShape proj_shape(int L, int n, int R = 0) {
     ProjShape p;
     p.L = L;
     p.n = n;
     p.S = strip_stride(L);
-    p.R = lds_floats / (2 * p.S);
-    if (p.R > L) p.R = L;
+    p.RS = strip_row_floats(L);
+    const int rmax = strip_rows_max(L) < L ? strip_rows_max(L) : L;
+    p.R = (R > 0 && R < rmax) ? R : rmax;
     p.slots = n / 8 + 1;
     p.items = p.slots * L;
     return p;
 }
 
-// Stage image rows [i0, i0 + rows) into Srow[r][S] and image columns
-// [i0, i0 + rows) transposed into Tcol[r][S]; masked, clipped, zero padded.
+// Masked, clipped pixel (row i, column j) of the image, 0 outside it.
+__device__ __forceinline__ float pixel(const float *__restrict__ F, int L, int i, int j) {
+    if (j < 0 || j >= L || i < 0 || i >= L) return 0.f;
+    const float x = F[(size_t)i * L + j];
+    return (in_disk(L, i, j) && x > 0.f) ? x : 0.f;
+}
+
+// Write chunk k of the four copies of one strip row from elements
+// x[0..6] = 4k-6 .. 4k: copy c's chunk k holds elements 4k-3-c .. 4k-c.
+__device__ __forceinline__ void store_chunks(float *row, int k, const float (&x)[7]) {
+    float *p = row + 16 * k;
+    *(float4 *)(p + 0) = make_float4(x[3], x[4], x[5], x[6]);
+    *(float4 *)(p + 4) = make_float4(x[2], x[3], x[4], x[5]);
+    *(float4 *)(p + 8) = make_float4(x[1], x[2], x[3], x[4]);
+    *(float4 *)(p + 12) = make_float4(x[0], x[1], x[2], x[3]);
+}
+
+// Stage image rows [i0, i0 + rows) and image columns [i0, i0 + rows)
+// (transposed) into the strip buffer; masked, clipped, zero padded.  One
+// thread per (strip row, chunk) loads the seven elements its four chunks
+// need.  Row kind: threads along the row (coalesced loads); column kind:
+// threads along the strip rows (consecutive image columns).
 template <int NT>
 __device__ void stage_strip(const float *__restrict__ F, const ProjShape &P, int i0, int rows,
-                            float *Srow, float *Tcol, int &bad) {
-    const int L = P.L, S = P.S;
-    for (int r = 0; r < rows; ++r) {
+                            float *lds, int &bad) {
+    const int L = P.L, K = P.S / 4, RS = P.RS;
+    for (int t = threadIdx.x; t < rows * K; t += NT) {
+        const int r = t / K, k = t - r * K;
         const int i = i0 + r;
-        for (int jj = threadIdx.x; jj < S; jj += NT) {
-            const int j = jj - kPadLeft;
+        float x[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            const int j = 4 * k - 6 + m;
             float v = 0.f;
             if (j >= 0 && j < L) {
-                const float x = F[(size_t)i * L + j];
-                if (!isfinite(x)) bad = 1;
-                if (in_disk(L, i, j) && x > 0.f) v = x;
+                const float y = F[(size_t)i * L + j];
+                if (!isfinite(y)) bad = 1;
+                if (in_disk(L, i, j) && y > 0.f) v = y;
             }
-            Srow[r * S + jj] = v;
+            x[m] = v;
         }
+        store_chunks(lds + r * RS, k, x);
     }
-    // threads as (column block, row): consecutive threads read consecutive
-    // image columns of one image row
-    const int per = NT / rows;  // rows <= NT is guaranteed by the launcher
-    const int r = threadIdx.x % rows;
-    const int jb = threadIdx.x / rows;
-    if (jb < per) {
-        for (int jj = jb; jj < S; jj += per) {
-            const int j = jj - kPadLeft;
-            float v = 0.f;
-            if (j >= 0 && j < L) {
-                const int i = i0 + r;
-                const float x = F[(size_t)j * L + i];
-                if (in_disk(L, j, i) && x > 0.f) v = x;
-            }
-            Tcol[r * S + jj] = v;
-        }
+    for (int t = threadIdx.x; t < rows * K; t += NT) {
+        const int k = t / rows, r = t - k * rows;
+        const int i = i0 + r;
+        float x[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) x[m] = pixel(F, L, 4 * k - 6 + m, i);
+        store_chunks(lds + kKindFloats + r * RS, k, x);
     }
+}
+
+// LDS offset (floats) of the four-element window starting at element e of
+// the strip row at rowoff: with q = e + kStripPad its position in copy 0,
+// the window is aligned in copy c = (-q) mod 4 at position q + c, a multiple
+// of four, i.e. at float 4 (q + c) + 4 c = 8 (q + c) - 4 q of the row.
+__device__ __forceinline__ int window_pos(int e, int rowoff) {
+    const int q = e + kStripPad;
+    return rowoff + 8 * ((q + 3) & ~3) - 4 * q;
 }
 
 // Per-lane constants of one task (slot angle, bin).
@@ -118,40 +145,41 @@ __device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *
 // unrolled loop, so the LDS reads of consecutive rows are in flight together.
 template <int TPW>
 __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const float2 *dtab,
-                                                 const float *Srow, int i0, int rows, int tg0,
+                                                 const float *lds, int i0, int rows, int tg0,
                                                  int wave, int nwaves, int lane,
                                                  float (&acc)[TPW][4], int my_tasks) {
-    const int L = P.L, S = P.S;
+    const int L = P.L;
     const float hi = (float)L + 0.5f;
-    // the transposed strip sits R * S floats after the row strip
-    const int toff = P.R * S;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         if (t < my_tasks) {  // wave-uniform
             const LaneTask tk = make_task(P, dtab, (tg0 + wave + t * nwaves) * 64 + lane);
             float s0 = acc[t][0], s1 = acc[t][1], s2 = acc[t][2], s3 = acc[t][3];
-            const float *row = Srow + kPadLeft;
-#pragma unroll 4
-            for (int rr = 0; rr < rows; ++rr) {
-                float u = fmaf((float)(i0 + rr), tk.r, tk.A);
+            float fi = (float)i0;  // row index, exact in FP32
+#pragma unroll 2
+            for (int rr = 0; rr < rows; ++rr, fi += 1.f) {
+                float u = fmaf(fi, tk.r, tk.A);
                 u = __builtin_amdgcn_fmed3f(u, -1.5f, hi);
-                const float jf = floorf(u);
-                const float cf = tk.c * (u - jf);
-                const int jA = (int)jf;
+                const float fr = __builtin_amdgcn_fractf(u);  // u - floor(u), exact
+                const int jA = (int)floorf(u);
+                const float cf = tk.c * fr;
                 const float w0 = __builtin_amdgcn_fmed3f(tk.omc - cf, 0.f, 1.f);   // column jA - 1
                 const float w1 = 1.f - cf;                                          // column jA
                 const float w2 = tk.omc + cf;                                       // column jA + 1
                 const float w3 = __builtin_amdgcn_fmed3f(tk.om2c + cf, 0.f, 1.f);  // column jA + 2
-                const float *a = row + rr * S + jA;
-                const float *fa = row + rr * S + (L - 1 - jA);
-                const float a0 = a[-1], a1 = a[0], a2 = a[1], a3 = a[2];
-                const float b0 = a[toff - 1], b1 = a[toff], b2 = a[toff + 1], b3 = a[toff + 2];
-                const float c0 = fa[1], c1 = fa[0], c2 = fa[-1], c3 = fa[-2];
-                const float d0 = fa[toff + 1], d1 = fa[toff], d2 = fa[toff - 1], d3 = fa[toff - 2];
-                s0 = fmaf(w3, a3, fmaf(w2, a2, fmaf(w1, a1, fmaf(w0, a0, s0))));
-                s1 = fmaf(w3, b3, fmaf(w2, b2, fmaf(w1, b1, fmaf(w0, b0, s1))));
-                s2 = fmaf(w3, c3, fmaf(w2, c2, fmaf(w1, c1, fmaf(w0, c0, s2))));
-                s3 = fmaf(w3, d3, fmaf(w2, d2, fmaf(w1, d1, fmaf(w0, d0, s3))));
+                // window jA-1 .. jA+2 of this row (and of the transposed
+                // column), and the mirrored window L-3-jA .. L-jA
+                const int rowoff = rr * P.RS;
+                const int pa = window_pos(jA - 1, rowoff);
+                const int pc = window_pos(L - 3 - jA, rowoff);
+                const float4 A = *(const float4 *)(lds + pa);
+                const float4 B = *(const float4 *)(lds + kKindFloats + pa);
+                const float4 C = *(const float4 *)(lds + pc);
+                const float4 D = *(const float4 *)(lds + kKindFloats + pc);
+                s0 = fmaf(w3, A.w, fmaf(w2, A.z, fmaf(w1, A.y, fmaf(w0, A.x, s0))));
+                s1 = fmaf(w3, B.w, fmaf(w2, B.z, fmaf(w1, B.y, fmaf(w0, B.x, s1))));
+                s2 = fmaf(w3, C.x, fmaf(w2, C.y, fmaf(w1, C.z, fmaf(w0, C.w, s2))));
+                s3 = fmaf(w3, D.x, fmaf(w2, D.y, fmaf(w1, D.z, fmaf(w0, D.w, s3))));
             }
             acc[t][0] = s0;
             acc[t][1] = s1;
@@ -203,8 +231,6 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
     float acc[TPW][4];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0.f;
-    float *Srow = lds;
-    float *Tcol = lds + P.R * P.S;
     const int ntasks = (P.items + 63) / 64;
     const int mine = ntasks - tg0 - wave;
     const int my_tasks = mine > 0 ? min(TPW, (mine + NW - 1) / NW) : 0;
@@ -212,9 +238,9 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
     for (int i0 = 0; i0 < P.L; i0 += P.R) {
         const int rows = min(P.R, P.L - i0);
         __syncthreads();
-        stage_strip<NT>(F, P, i0, rows, Srow, Tcol, bad);
+        stage_strip<NT>(F, P, i0, rows, lds, bad);
         __syncthreads();
-        accumulate_strip<TPW>(P, dtab, Srow, i0, rows, tg0, wave, NW, lane, acc, my_tasks);
+        accumulate_strip<TPW>(P, dtab, lds, i0, rows, tg0, wave, NW, lane, acc, my_tasks);
     }
     bad_out = __syncthreads_or(bad);
     // an image with a non-finite value emits nothing; the caller fills it

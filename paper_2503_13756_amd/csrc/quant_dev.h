@@ -4,14 +4,15 @@
 //
 // One block per image, one wave per column at a time.  A column of L <= 256
 // bins is held as up to four values per lane; the mass and the cumulative
-// sums are accumulated in FP64 (lane-local sums, then a wave-wide exclusive
-// scan of the lane totals) and the normalised CDF is kept in a per-wave LDS
-// buffer.  Each lane then inverts the CDF at its quantile levels by binary
-// search (lower bound: first bin whose CDF reaches z) and linear
-// interpolation inside that bin.  Quantiles are gathered in an LDS tile
-// [Q][TC] and written out as rows of the [Q][n] table (angle fastest).  The
-// per-image scalars (mass, E = sum of squares, translation moment a) are
-// reduced in FP64 on the way.
+// sums are accumulated in FP64 (lane-local sums, then a wave-wide DPP scan of
+// the lane totals), so each lane holds the normalised CDF at the right edges
+// of its own bins.  Levels are then assigned from the bins' side rather than
+// searched for: level z_j falls in bin b exactly when C[b] < z_j <= C[b+1]
+// (the first bin whose CDF reaches z_j), so a lane counts the levels at or
+// below each of its edges and interpolates the levels in between.  Quantiles
+// are gathered in an LDS tile [Q][TC] and written out as rows of the [Q][n]
+// table (angle fastest).  The per-image scalars (mass, E = sum of squares,
+// translation moment a) are reduced in FP64 on the way.
 #pragma once
 #include "sw_internal.h"
 
@@ -22,29 +23,63 @@ struct QuantShape {
     int L, n, Q, levels, TC;
 };
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// v moved across lanes by a DPP control (row_mask selects the 16-lane rows
+// that receive; lanes without a valid source, and rows not selected, get 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Inclusive scan over the 64 lanes of a wave: shifts by 1, 2, 4, 8 inside
+// each row of 16 lanes, then the row totals carried across rows.  Fixed
+// summation order, so the result is deterministic.
+__device__ __forceinline__ double wave_inclusive_scan_d(double v) {
+    v += dpp_d<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_d<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_d<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_d<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 
-// Inclusive scan over the 64 lanes of a wave (Hillis-Steele).
-__device__ __forceinline__ double wave_inclusive_scan_d(double v, int lane) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double o = __shfl_up(v, off, 64);
-        if (lane >= off) v += o;
-    }
-    return v;
+__device__ __forceinline__ double read_lane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave (same value on all lanes).
+__device__ __forceinline__ double wave_sum_d(double v) {
+    return read_lane_d(wave_inclusive_scan_d(v), 63);
+}
+
+// Quantile level z_j: midpoint (j + 1/2)/Q or left j/Q.
+__device__ __forceinline__ double level_z(int j, int levels, double invQ) {
+    return ((double)j + (levels ? 0.0 : 0.5)) * invQ;
+}
+
+// Number of levels z_j <= c (levels increase with j): an estimate from c Q,
+// corrected with the same comparisons that define the assignment.
+__device__ __forceinline__ int levels_at_or_below(double c, int Q, int levels, double invQ) {
+    double est = c * (double)Q - (levels ? 0.0 : 0.5);
+    est = est < -1.0 ? -1.0 : (est > (double)Q ? (double)Q : est);
+    int j = (int)floor(est) + 1;
+    j = j < 0 ? 0 : (j > Q ? Q : j);
+    if (j > 0 && level_z(j - 1, levels, invQ) > c) --j;
+    if (j < Q && level_z(j, levels, invQ) <= c) ++j;
+    return j;
 }
 
 // Invert one column.  `col` reads bin b of the column (FP32).  Writes the
-// quantiles of levels j = lane, lane + 64, ... into Ut[j * ldt + kl] and
-// returns the lane's partial (sum of quantiles, sum of squares) in *su, *sq.
-// Returns the column mass (same value on all lanes).
+// quantile of every level j into Ut[j * ldt + kl] and returns the lane's
+// partial (sum of quantiles, sum of squares) in *su, *sq, and the column
+// mass (same value on all lanes).
 template <typename ColFn>
-__device__ double invert_column(ColFn col, int L, int Q, int levels, double *C, float *Ut, int ldt,
-                                int kl, int lane, double *su, double *sq) {
+__device__ double invert_column(ColFn col, int L, int Q, int levels, float *Ut, int ldt, int kl,
+                                int lane, double *su, double *sq) {
     const int m = (L + 63) >> 6;  // bins per lane, <= 4
     double v[4];
     double run = 0.0;
@@ -56,46 +91,64 @@ __device__ double invert_column(ColFn col, int L, int Q, int levels, double *C, 
         run += x;
         v[t] = run;  // lane-local inclusive sums
     }
-    const double incl = wave_inclusive_scan_d(run, lane);
-    const double excl = incl - run;
+    const double excl = wave_inclusive_scan_d(run) - run;
     // mass = cumulative sum at the last bin, taken from the lane holding it,
-    // so that C[L-1] is exactly 1
+    // so that the CDF at the right edge is exactly 1
     const int last_lane = (L - 1) / m;
     const int last_t = (L - 1) - last_lane * m;
     double lastv = v[0];
 #pragma unroll
     for (int t = 1; t < 4; ++t)
         if (t == last_t) lastv = v[t];
-    const double mass = __shfl(excl + lastv, last_lane, 64);
-    const bool pos = mass > 0.0;
-    if (lane == 0) C[0] = 0.0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int b = lane * m + t;
-        if (t < m && b < L) C[b + 1] = pos ? (excl + v[t]) / mass : 0.0;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double mass = read_lane_d(excl + lastv, last_lane);
     const double h = 2.0 / (double)L;
+    const double invQ = 1.0 / (double)Q;
     double s1 = 0.0, s2 = 0.0;
-    for (int j = lane; j < Q; j += 64) {
-        const double z = levels ? (double)j / (double)Q : ((double)j + 0.5) / (double)Q;
-        int lo = 0, hi = L;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (C[mid + 1] >= z) hi = mid;
-            else lo = mid + 1;
+    if (!(mass > 0.0)) {
+        // empty (or non-finite) column: the inverse of a zero CDF, as in the
+        // lower-bound rule with every CDF value 0
+        for (int j = lane; j < Q; j += 64) {
+            const int b = (levels && j == 0) ? 0 : L - 1;
+            const float uf = (float)(-1.0 + (double)b * h);
+            Ut[j * ldt + kl] = uf;
+            s1 += (double)uf;
+            s2 += (double)uf * (double)uf;
         }
-        const int b = lo < L ? lo : L - 1;
-        const double tl = -1.0 + (double)b * h, tr = -1.0 + (double)(b + 1) * h;
-        const double den = C[b + 1] - C[b];
-        double u = den > 0.0 ? tl + h * (z - C[b]) / den : tl;
-        u = u < tl ? tl : (u > tr ? tr : u);
-        const float uf = (float)u;
-        Ut[j * ldt + kl] = uf;
-        s1 += (double)uf;
-        s2 += (double)uf * (double)uf;
+    } else {
+        double c[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) c[t] = (excl + v[t]) / mass;  // C at the right edge of bin
+        double cm = c[0];
+#pragma unroll
+        for (int t = 1; t < 4; ++t)
+            if (t == m - 1) cm = c[t];
+        // C at the left edge of this lane's first bin: the previous lane's
+        // last right edge (0 on lane 0)
+        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(cm), 0x138, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(cm), 0x138, 0xf, 0xf, false);
+        double cl = __hiloint2double(hi, lo);  // wave_shr:1
+        int jl = lane == 0 ? 0 : levels_at_or_below(cl, Q, levels, invQ);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int b = lane * m + t;
+            if (t < m && b < L) {
+                const double cr = c[t];
+                const int jr = levels_at_or_below(cr, Q, levels, invQ);
+                const double tl = -1.0 + (double)b * h, tr = -1.0 + (double)(b + 1) * h;
+                const double den = cr - cl;
+                const double slope = den > 0.0 ? h / den : 0.0;
+                for (int j = jl; j < jr; ++j) {
+                    double u = tl + (level_z(j, levels, invQ) - cl) * slope;
+                    u = u < tl ? tl : (u > tr ? tr : u);
+                    const float uf = (float)u;
+                    Ut[j * ldt + kl] = uf;
+                    s1 += (double)uf;
+                    s2 += (double)uf * (double)uf;
+                }
+                cl = cr;
+                jl = jr;
+            }
+        }
     }
     *su = s1;
     *sq = s2;
@@ -104,25 +157,24 @@ __device__ double invert_column(ColFn col, int L, int Q, int levels, double *C, 
 }
 
 // The whole CDF/quantile phase of one image, shared by the stand-alone,
-// fused and mixed kernels.  col(k, b) reads bin b of column k.  LDS: C
-// (NW * (L + 1) doubles), Ut (Q * (TC + 1) floats), colS (2 n doubles).
+// fused and mixed kernels.  col(k, b) reads bin b of column k.  LDS: Ut
+// (Q * (TC + 1) floats), colS (2 n doubles).
 // Column sums are stored per column and reduced by wave 0 in a fixed order,
 // so the per-image scalars do not depend on the block size or tile width.
 template <int NT, typename ColFn>
 __device__ void quantile_phase(ColFn col, int L, int n, int Q, int levels, int TC,
-                               const double2 *__restrict__ d64, double *C0, float *Ut,
-                               double *colS, float *__restrict__ U, double *__restrict__ A) {
+                               const double2 *__restrict__ d64, float *Ut, double *colS,
+                               float *__restrict__ U, double *__restrict__ A) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double *C = C0 + wave * (L + 1);
     const int ldt = TC + 1;
     double mass0 = 0.0;
     for (int k0 = 0; k0 < n; k0 += TC) {
         for (int kl = wave; kl < TC; kl += NW) {
             const int k = k0 + kl;
             double su, sq;
-            const double mass = invert_column([&](int b) { return col(k, b); }, L, Q, levels, C,
-                                              Ut, ldt, kl, lane, &su, &sq);
+            const double mass = invert_column([&](int b) { return col(k, b); }, L, Q, levels, Ut,
+                                              ldt, kl, lane, &su, &sq);
             if (k == 0) mass0 = mass;
             su = wave_sum_d(su);
             sq = wave_sum_d(sq);

@@ -571,12 +571,12 @@ sw_status sw_autotune(void *ctx, const int32_t *Ls, int32_t nL, int64_t n_images
         if (e == hipSuccess) e = sw::launch_fill_synthetic(img, (int64_t)nimg, nullptr);
         sw_stack k{img, img, (int64_t)n_images, g, rqt, raux, qt, aux, out};
         const sw_stack *kp = &k;
-        const int S = sw::strip_stride(L);
-        const int Rmax = std::min(L, 16384 / (2 * S));
-        const int cands[] = {4, 8, 12, 16, 24, 32, 40, 48, 60, 64, 80, 96, 128};
+        const int Rmax = std::min(L, sw::strip_rows_max(L));
+        const int cands[] = {2, 4, 6, 8, 12, 16, 24, 32, 0};  // 0: the largest that fits
         for (int R : cands) {
             if (e != hipSuccess) break;
-            if (R > Rmax) continue;
+            if (R == 0) R = Rmax;
+            else if (R >= Rmax) continue;
             float tbest = 1e30f;
             for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
                 e = hipEventRecord(e0, nullptr);
