@@ -35,7 +35,7 @@ __device__ __forceinline__ bool in_disk(int L, int i, int j) {
 }
 
 struct ProjShape {
-    int L, n, S, RS, R, slots, items;  // S positions per copy, RS floats per strip row
+    int L, n, S, RS, R, slots, items;  // S chunks, RS floats per strip row
 };
 
 // R: requested strip rows (0: as many as fit).
@@ -59,64 +59,88 @@ __device__ __forceinline__ float pixel(const float *__restrict__ F, int L, int i
     return (in_disk(L, i, j) && x > 0.f) ? x : 0.f;
 }
 
-// Write chunk k of the four copies of one strip row from elements
-// x[0..6] = 4k-6 .. 4k: copy c's chunk k holds elements 4k-3-c .. 4k-c.
-__device__ __forceinline__ void store_chunks(float *row, int k, const float (&x)[7]) {
-    float *p = row + 16 * k;
-    *(float4 *)(p + 0) = make_float4(x[3], x[4], x[5], x[6]);
-    *(float4 *)(p + 4) = make_float4(x[2], x[3], x[4], x[5]);
-    *(float4 *)(p + 8) = make_float4(x[1], x[2], x[3], x[4]);
-    *(float4 *)(p + 12) = make_float4(x[0], x[1], x[2], x[3]);
+// The four elements q-3 .. q of one image line (row or column) as one strip
+// chunk, masked to the disk and clipped at 0.  The loads are unconditional
+// from indexes clamped into the line and masked afterwards (the disk lies
+// inside the image, so a clamped element is always masked), so that the
+// four loads of a chunk are in flight together.  `stride` is the element
+// step in memory (1 along a row, L down a column); with a0 = 2 (q-3) - L + 1
+// and bb = (2 i - L + 1)^2 - (L - 2)^2 the disk test of element m is
+// (a0 + 2 m)^2 + bb <= 0.
+__device__ __forceinline__ float4 line_chunk(const float *__restrict__ line, int L, int stride,
+                                             int q, int bb, bool &finite) {
+    float x[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        int j = q - kStripPad + m;
+        j = j < 0 ? 0 : (j > L - 1 ? L - 1 : j);
+        x[m] = line[(size_t)j * stride];
+    }
+    const int a0 = 2 * (q - kStripPad) - L + 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        finite = finite && isfinite(x[m]);
+        const int a = a0 + 2 * m;
+        x[m] = (a * a + bb <= 0 && x[m] > 0.f) ? x[m] : 0.f;
+    }
+    return make_float4(x[0], x[1], x[2], x[3]);
 }
 
 // Stage image rows [i0, i0 + rows) and image columns [i0, i0 + rows)
 // (transposed) into the strip buffer; masked, clipped, zero padded.  One
-// thread per (strip row, chunk) loads the seven elements its four chunks
-// need.  Row kind: threads along the row (coalesced loads); column kind:
-// threads along the strip rows (consecutive image columns).
+// thread per (strip row, chunk).  Row kind: threads along the row
+// (coalesced loads, consecutive chunks); column kind: threads along the
+// strip rows (consecutive image columns).
 template <int NT>
 __device__ void stage_strip(const float *__restrict__ F, const ProjShape &P, int i0, int rows,
                             float *lds, int &bad) {
-    const int L = P.L, K = P.S / 4, RS = P.RS;
-    for (int t = threadIdx.x; t < rows * K; t += NT) {
-        const int r = t / K, k = t - r * K;
-        const int i = i0 + r;
-        float x[7];
-#pragma unroll
-        for (int m = 0; m < 7; ++m) {
-            const int j = 4 * k - 6 + m;
-            float v = 0.f;
-            if (j >= 0 && j < L) {
-                const float y = F[(size_t)i * L + j];
-                if (!isfinite(y)) bad = 1;
-                if (in_disk(L, i, j) && y > 0.f) v = y;
+    const int L = P.L, S = P.S, RS = P.RS, n = rows * S;
+    const int rr2 = (L - 2) * (L - 2);
+    bool finite = true;
+    {
+        int r = threadIdx.x / S, q = threadIdx.x - (threadIdx.x / S) * S;
+        const int dr = NT / S, dq = NT - (NT / S) * S;
+#pragma unroll 2
+        for (int t = threadIdx.x; t < n; t += NT) {
+            const int i = i0 + r, b = 2 * i - L + 1;
+            const float4 v = line_chunk(F + (size_t)i * L, L, 1, q, b * b - rr2, finite);
+            *(float4 *)(lds + r * RS + 4 * q) = v;
+            q += dq;
+            r += dr;
+            if (q >= S) {
+                q -= S;
+                ++r;
             }
-            x[m] = v;
         }
-        store_chunks(lds + r * RS, k, x);
     }
-    for (int t = threadIdx.x; t < rows * K; t += NT) {
-        const int k = t / rows, r = t - k * rows;
-        const int i = i0 + r;
-        float x[7];
-#pragma unroll
-        for (int m = 0; m < 7; ++m) x[m] = pixel(F, L, 4 * k - 6 + m, i);
-        store_chunks(lds + kKindFloats + r * RS, k, x);
+    {
+        int q = threadIdx.x / rows, r = threadIdx.x - (threadIdx.x / rows) * rows;
+        const int dq = NT / rows, dr = NT - (NT / rows) * rows;
+#pragma unroll 2
+        for (int t = threadIdx.x; t < n; t += NT) {
+            const int i = i0 + r, b = 2 * i - L + 1;
+            const float4 v = line_chunk(F + i, L, L, q, b * b - rr2, finite);
+            *(float4 *)(lds + kKindFloats + r * RS + 4 * q) = v;
+            r += dr;
+            q += dq;
+            if (r >= rows) {
+                r -= rows;
+                ++q;
+            }
+        }
     }
+    if (!finite) bad = 1;
 }
 
 // LDS offset (floats) of the four-element window starting at element e of
-// the strip row at rowoff: with q = e + kStripPad its position in copy 0,
-// the window is aligned in copy c = (-q) mod 4 at position q + c, a multiple
-// of four, i.e. at float 4 (q + c) + 4 c = 8 (q + c) - 4 q of the row.
+// the strip row at rowoff.
 __device__ __forceinline__ int window_pos(int e, int rowoff) {
-    const int q = e + kStripPad;
-    return rowoff + 8 * ((q + 3) & ~3) - 4 * q;
+    return rowoff + 4 * (e + kStripPad);
 }
 
 // Per-lane constants of one task (slot angle, bin).
 struct LaneTask {
-    float c, omc, om2c, r, A;
+    float c, r, A;
 };
 
 __device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *dtab, int item) {
@@ -135,8 +159,6 @@ __device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *
         t.r = 0.f;
         t.A = -100.f;  // clamps to the zero padding
     }
-    t.omc = 1.f - t.c;
-    t.om2c = 1.f - 2.f * t.c;
     return t;
 }
 
@@ -144,16 +166,16 @@ __device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *
 // slots are the outer loop (a wave-uniform guard each) and rows the inner,
 // unrolled loop, so the LDS reads of consecutive rows are in flight together.
 template <int TPW>
-__device__ __forceinline__ void accumulate_strip(const ProjShape &P, const float2 *dtab,
-                                                 const float *lds, int i0, int rows, int tg0,
-                                                 int wave, int nwaves, int lane,
+__device__ __forceinline__ void accumulate_strip(const ProjShape &P, const LaneTask (&tasks)[TPW],
+                                                 const float *lds, int i0, int rows,
                                                  float (&acc)[TPW][4], int my_tasks) {
     const int L = P.L;
     const float hi = (float)L + 0.5f;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         if (t < my_tasks) {  // wave-uniform
-            const LaneTask tk = make_task(P, dtab, (tg0 + wave + t * nwaves) * 64 + lane);
+            const LaneTask tk = tasks[t];
+            const float omc = 1.f - tk.c, om2c = 1.f - 2.f * tk.c;
             float s0 = acc[t][0], s1 = acc[t][1], s2 = acc[t][2], s3 = acc[t][3];
             float fi = (float)i0;  // row index, exact in FP32
 #pragma unroll 2
@@ -163,10 +185,10 @@ __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const float
                 const float fr = __builtin_amdgcn_fractf(u);  // u - floor(u), exact
                 const int jA = (int)floorf(u);
                 const float cf = tk.c * fr;
-                const float w0 = __builtin_amdgcn_fmed3f(tk.omc - cf, 0.f, 1.f);   // column jA - 1
-                const float w1 = 1.f - cf;                                          // column jA
-                const float w2 = tk.omc + cf;                                       // column jA + 1
-                const float w3 = __builtin_amdgcn_fmed3f(tk.om2c + cf, 0.f, 1.f);  // column jA + 2
+                const float w0 = __builtin_amdgcn_fmed3f(omc - cf, 0.f, 1.f);   // column jA - 1
+                const float w1 = 1.f - cf;                                       // column jA
+                const float w2 = omc + cf;                                       // column jA + 1
+                const float w3 = __builtin_amdgcn_fmed3f(om2c + cf, 0.f, 1.f);  // column jA + 2
                 // window jA-1 .. jA+2 of this row (and of the transposed
                 // column), and the mirrored window L-3-jA .. L-jA
                 const int rowoff = rr * P.RS;
@@ -234,13 +256,17 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
     const int ntasks = (P.items + 63) / 64;
     const int mine = ntasks - tg0 - wave;
     const int my_tasks = mine > 0 ? min(TPW, (mine + NW - 1) / NW) : 0;
+    // per-lane constants of this wave's tasks, set up once for all strips
+    LaneTask tasks[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) tasks[t] = make_task(P, dtab, (tg0 + wave + t * NW) * 64 + lane);
     int bad = 0;
     for (int i0 = 0; i0 < P.L; i0 += P.R) {
         const int rows = min(P.R, P.L - i0);
         __syncthreads();
         stage_strip<NT>(F, P, i0, rows, lds, bad);
         __syncthreads();
-        accumulate_strip<TPW>(P, dtab, lds, i0, rows, tg0, wave, NW, lane, acc, my_tasks);
+        accumulate_strip<TPW>(P, tasks, lds, i0, rows, acc, my_tasks);
     }
     bad_out = __syncthreads_or(bad);
     // an image with a non-finite value emits nothing; the caller fills it

@@ -13,19 +13,19 @@ constexpr int kMaxQ = 512;
 constexpr int kMaxTopK = 8;
 
 // LDS image strips of the projection.  A strip holds R image rows and the
-// same R image columns transposed (two "kinds", kKindFloats apart).  Each
-// strip row is stored as four shifted copies interleaved by 16-byte chunks:
-// position p of copy c holds element p - kStripPad - c of the row (zero
-// outside the image) at float 16 (p / 4) + 4 c + p % 4 of the row, so that
-// any window of four consecutive elements is one aligned 16-byte chunk of
-// one copy.  Rows are strip_row_floats(L) apart: four copies of S positions
-// plus one chunk, which staggers the banks of consecutive rows.
+// same R image columns transposed (two "kinds", kKindFloats apart).  A strip
+// row is stored as sliding windows: the 16-byte chunk q (floats 4q .. 4q+3
+// of the row) holds elements q - kStripPad .. q - kStripPad + 3 of the row
+// (zero outside the image), so that the window of four consecutive elements
+// starting at element e is the one aligned chunk e + kStripPad, and lanes
+// reading neighbouring windows read neighbouring chunks.  Rows hold an odd
+// number of chunks, so that consecutive rows start in different banks.
 constexpr int kStripPad = 3;
 constexpr int kKindFloats = 8192;
 constexpr int kStripFloats = 2 * kKindFloats;  // 64 KiB
-// positions per copy: a multiple of four with room for the padding
-__host__ __device__ inline int strip_stride(int L) { return (L + 12) & ~3; }
-__host__ __device__ inline int strip_row_floats(int L) { return 4 * strip_stride(L) + 4; }
+// chunks per strip row: windows start at elements -3 .. L-1
+__host__ __device__ inline int strip_stride(int L) { return (L + kStripPad) | 1; }
+__host__ __device__ inline int strip_row_floats(int L) { return 4 * strip_stride(L); }
 __host__ __device__ inline int strip_rows_max(int L) { return kKindFloats / strip_row_floats(L); }
 
 struct Geo {
