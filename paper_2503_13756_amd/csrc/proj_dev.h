@@ -59,77 +59,52 @@ __device__ __forceinline__ float pixel(const float *__restrict__ F, int L, int i
     return (in_disk(L, i, j) && x > 0.f) ? x : 0.f;
 }
 
-// The four elements q-3 .. q of one image line (row or column) as one strip
-// chunk, masked to the disk and clipped at 0.  The loads are unconditional
-// from indexes clamped into the line and masked afterwards (the disk lies
-// inside the image, so a clamped element is always masked), so that the
-// four loads of a chunk are in flight together.  `stride` is the element
-// step in memory (1 along a row, L down a column); with a0 = 2 (q-3) - L + 1
-// and bb = (2 i - L + 1)^2 - (L - 2)^2 the disk test of element m is
-// (a0 + 2 m)^2 + bb <= 0.
-__device__ __forceinline__ float4 line_chunk(const float *__restrict__ line, int L, int stride,
-                                             int q, int bb, bool &finite) {
-    float x[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        int j = q - kStripPad + m;
-        j = j < 0 ? 0 : (j > L - 1 ? L - 1 : j);
-        x[m] = line[(size_t)j * stride];
-    }
-    const int a0 = 2 * (q - kStripPad) - L + 1;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        finite = finite && isfinite(x[m]);
-        const int a = a0 + 2 * m;
-        x[m] = (a * a + bb <= 0 && x[m] > 0.f) ? x[m] : 0.f;
-    }
-    return make_float4(x[0], x[1], x[2], x[3]);
+// Value of lane - 1 (0 on lane 0): DPP wave_shr:1.
+__device__ __forceinline__ float lane_prev(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
 
 // Stage image rows [i0, i0 + rows) and image columns [i0, i0 + rows)
-// (transposed) into the strip buffer; masked, clipped, zero padded.  One
-// thread per (strip row, chunk).  Row kind: threads along the row
-// (coalesced loads, consecutive chunks); column kind: threads along the
-// strip rows (consecutive image columns).
+// (transposed) into the strip buffer; masked to the disk, clipped at 0 and
+// zero outside the image.  Per kind, the strip rows are walked as one
+// sequence of entries (row r, element j) with j = -3 .. S-1; a wave takes 64
+// consecutive entries, each lane loads one element, and a lane with j >= 0
+// writes chunk j from its own element and those of the three lanes before
+// it (DPP shifts), so consecutive waves overlap by three entries.  The image
+// is read through a buffer resource covering exactly this image: loads are
+// range-checked by the hardware (out-of-range offsets read 0) and go out
+// unconditionally; every element outside the image lies outside the disk
+// and is masked.  A non-finite pixel sets `bad`.
 template <int NT>
 __device__ void stage_strip(const float *__restrict__ F, const ProjShape &P, int i0, int rows,
                             float *lds, int &bad) {
-    const int L = P.L, S = P.S, RS = P.RS, n = rows * S;
+    constexpr int NW = NT / 64, STEP = 64 - kStripPad;
+    const int L = P.L, RS = P.RS, W = P.S + kStripPad, total = rows * W;
     const int rr2 = (L - 2) * (L - 2);
-    bool finite = true;
-    {
-        int r = threadIdx.x / S, q = threadIdx.x - (threadIdx.x / S) * S;
-        const int dr = NT / S, dq = NT - (NT / S) * S;
-#pragma unroll 2
-        for (int t = threadIdx.x; t < n; t += NT) {
-            const int i = i0 + r, b = 2 * i - L + 1;
-            const float4 v = line_chunk(F + (size_t)i * L, L, 1, q, b * b - rr2, finite);
-            *(float4 *)(lds + r * RS + 4 * q) = v;
-            q += dq;
-            r += dr;
-            if (q >= S) {
-                q -= S;
-                ++r;
-            }
+    const float invW = 1.f / (float)W;  // entry -> strip row, exact for these sizes
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const __amdgpu_buffer_rsrc_t img =
+        __builtin_amdgcn_make_buffer_rsrc((void *)F, (short)0, 4 * L * L, 0x00020000);
+    float nf = 0.f;  // becomes NaN once a non-finite pixel is read
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+        float *dst = lds + kind * kKindFloats;
+        for (int f0 = wave * STEP; f0 + kStripPad < total; f0 += NW * STEP) {
+            const int f = f0 + lane;
+            const int r = (int)fmaf((float)f, invW, 0.5f * invW);
+            const int j = f - __mul24(r, W) - kStripPad;
+            const int i = i0 + r;
+            const int off = kind == 0 ? 4 * (__mul24(i, L) + j) : 4 * (__mul24(j, L) + i);
+            const float x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off, 0, 0));
+            nf = fmaf(x, 0.f, nf);
+            const int a = 2 * j - L + 1, b = 2 * i - L + 1;
+            const float v = (__mul24(a, a) + __mul24(b, b) <= rr2) ? fmaxf(x, 0.f) : 0.f;
+            const float v1 = lane_prev(v), v2 = lane_prev(v1), v3 = lane_prev(v2);
+            if (lane >= kStripPad && f < total && j >= 0)
+                *(float4 *)(dst + __mul24(r, RS) + 4 * j) = make_float4(v3, v2, v1, v);
         }
     }
-    {
-        int q = threadIdx.x / rows, r = threadIdx.x - (threadIdx.x / rows) * rows;
-        const int dq = NT / rows, dr = NT - (NT / rows) * rows;
-#pragma unroll 2
-        for (int t = threadIdx.x; t < n; t += NT) {
-            const int i = i0 + r, b = 2 * i - L + 1;
-            const float4 v = line_chunk(F + i, L, L, q, b * b - rr2, finite);
-            *(float4 *)(lds + kKindFloats + r * RS + 4 * q) = v;
-            r += dr;
-            q += dq;
-            if (r >= rows) {
-                r -= rows;
-                ++q;
-            }
-        }
-    }
-    if (!finite) bad = 1;
+    if (nf != 0.f) bad = 1;
 }
 
 // LDS offset (floats) of the four-element window starting at element e of
