@@ -100,9 +100,12 @@ typedef struct {
 
 /* Context: binds a device and owns scratch.  tune_json (host, nullable) is a
    path to a JSON file with optional keys: "tiles" (the table written by
-   sw_autotune) and "small_batch": calls on fewer images than this take the
+   sw_autotune), "small_batch": calls on fewer images than this take the
    split launches (several blocks per image; default: the number of compute
-   units).  Both change launch shapes only, never results. */
+   units), and "align_kernel": "generic", which keeps sw_align_batch on the
+   LDS-FFT pair kernel for n_angles = 128 instead of the register-FFT one
+   (the two agree to FP32 rounding).  The first two change launch shapes
+   only, never results. */
 sw_status sw_ctx_create(void **ctx, int device, const char *tune_json);
 sw_status sw_ctx_destroy(void *ctx);
 const char *sw_last_error(void);

@@ -37,6 +37,7 @@ struct Ctx {
     // batches of fewer images take the split (many blocks per image) launches;
     // -1: the number of compute units
     int small_batch = -1;
+    bool generic_align = false;  // never use the n = 128 register-FFT kernel
     bool small(int64_t N) const { return N < (small_batch >= 0 ? small_batch : cu_count); }
     void *scratch = nullptr;
     size_t scratch_bytes = 0;

@@ -303,6 +303,8 @@ sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
         std::smatch m;
         if (std::regex_search(txt, m, std::regex("\"small_batch\"\\s*:\\s*(\\d+)")))
             c->small_batch = std::stoi(m[1]);
+        if (std::regex_search(txt, m, std::regex("\"align_kernel\"\\s*:\\s*\"generic\"")))
+            c->generic_align = true;
     }
     *ctx = c;
     return SW_OK;
@@ -475,9 +477,12 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
         e = sw::launch_mfma_all_pairs(m, geo, *t, s);
         return e == hipSuccess ? SW_OK : hip_fail(e, "k_corr_mfma / k_rescore_tiles launch");
     }
-    const size_t spec_bytes = sizeof(float2) * (size_t)Wn * geo.Q * (size_t)b->n_ref;
+    const size_t spec_bytes =
+        (sizeof(float2) * (size_t)Wn * geo.Q * (size_t)b->n_ref + 255) & ~(size_t)255;
+    const bool fast128 = sw::align128_supported(geo) && !c->generic_align;
+    const size_t gam_bytes = fast128 ? sw::align128_scratch_bytes(geo, b->n_ref) : 0;
     void *spec;
-    if ((st = get_scratch(c, spec_bytes, s, &spec)) != SW_OK) return st;
+    if ((st = get_scratch(c, spec_bytes + gam_bytes, s, &spec)) != SW_OK) return st;
     hipError_t e = sw::launch_spectrum(b->ref_qt, b->n_ref, geo, *t, spec, 0, s);
     if (e != hipSuccess) return hip_fail(e, "k_spectrum launch");
     sw::PairArgs a;
@@ -495,6 +500,10 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
     a.top_k = top_k;
     a.out = (sw::Result *)out;
     a.curve = curve;
+    if (fast128) {
+        e = sw::launch_align128(a, geo, *t, (float2 *)((char *)spec + spec_bytes), s);
+        return e == hipSuccess ? SW_OK : hip_fail(e, "k_gamma128 / k_align128 launch");
+    }
     e = sw::launch_align_pairs(a, geo, *t, s);
     return e == hipSuccess ? SW_OK : hip_fail(e, "k_align_pairs launch");
 }

@@ -269,3 +269,67 @@ def test_all_pairs_mfma_same_set_sampled(api, ctx, oracle):
     o = oracle_results(oracle, oq, oa, oq, oa, L, pairs=pairs)
     sub = {k: v[pidx] for k, v in g.items()}
     parity.check(sub, o, L, parity.TAU_BF16, o["curve"])
+
+
+@pytest.fixture(scope="module")
+def ctx_generic(api, tmp_path_factory):
+    """Context that keeps n = 128 alignments on the LDS-FFT pair kernel."""
+    path = tmp_path_factory.mktemp("tune") / "generic.json"
+    path.write_text('{"align_kernel": "generic"}')
+    c = api.Context(0, tune_json=str(path))
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("Q", [48, 128, 256])
+@pytest.mark.parametrize("mode,prec,top_k", [(0, 0, 1), (1, 0, 3), (0, 1, 4), (0, 0, 8)])
+def test_align128_matches_oracle_and_generic(api, ctx, ctx_generic, oracle, Q, mode, prec, top_k):
+    """The n = 128 register-FFT kernel against the oracle (tie-aware parity)
+    and against the LDS-FFT kernel: same lags, distances and curves to FP32
+    rounding; pair lists with an out-of-range index and a self pair."""
+    L, n = 96, 128
+    ref, imgs = blob_stack(L, 13, 1100 + Q)
+    x = dev(np.concatenate([ref[None], imgs]))
+    q, a = api.tables(ctx, x, n, Q)
+    pairs = np.array([[0, i] for i in range(1, 14)] + [[3, 3], [5, 2], [0, 99]], np.int64)
+    r1, c1 = api.align_batch(ctx, q, a, q, a, L, pairs=dev(pairs), mode=mode, prec=prec,
+                             top_k=top_k, want_curve=True)
+    r2, c2 = api.align_batch(ctx_generic, q, a, q, a, L, pairs=dev(pairs), mode=mode, prec=prec,
+                             top_k=top_k, want_curve=True)
+    g1, g2 = api.unpack_results(r1), api.unpack_results(r2)
+    assert g1["status"][-1] == 3 and g2["status"][-1] == 3
+    ok = g1["status"] == 0
+    oq, oa = oracle.tables(np.concatenate([ref[None], imgs]), n, Q)
+    o = oracle.align(oq, oa, oq, oa, L, pairs=pairs[:-1], mode=mode, want_curve=True)
+    sub = {k: v[:-1] for k, v in g1.items()}
+    parity.check(sub, o, L, parity.TAU_FP32 if prec == 0 else parity.TAU_BF16, o["curve"])
+    if prec == 0:
+        assert np.array_equal(g1["rot_index"][ok], g2["rot_index"][ok])
+    same = ok & (g1["rot_index"] == g2["rot_index"])
+    assert same.sum() >= ok.sum() - 1
+    assert np.allclose(g1["sw2sq"][same], g2["sw2sq"][same], rtol=1e-5, atol=1e-9)
+    # the curves come from the spectral path (FP32 cross term cancelling the
+    # energies), so the floor scales with the largest value of each curve
+    c1, c2 = c1.cpu().numpy()[:-1], c2.cpu().numpy()[:-1]
+    if prec == 0:
+        floor = 1e-5 * np.abs(c2).max(axis=1, keepdims=True)
+        assert np.all(np.abs(c1 - c2) <= 1e-4 * np.abs(c2) + floor)
+    else:
+        # bf16 operands: the cross term is good to the bf16 epsilon of the
+        # energies, rounded differently by the two kernels
+        aa = a.cpu().numpy()
+        energy = (aa[pairs[:-1, 0], 1] + aa[pairs[:-1, 1], 1]) / (n * Q)
+        assert np.all(np.abs(c1 - c2) <= 2.0 ** -7 * energy[:, None])
+    assert g1["sw2sq"][13] == 0.0 and g1["rot_index"][13] == 0  # the self pair
+
+
+def test_align128_one_vs_many_batch_independent(api, ctx):
+    """Reference x image grid at n = 128: a pair's record does not depend on
+    the batch it is computed in."""
+    L, n = 128, 128
+    ref, imgs = blob_stack(L, 40, 1200)
+    rq, ra = api.tables(ctx, dev(ref[None]), n, n)
+    iq, ia = api.tables(ctx, dev(imgs), n, n)
+    r_all, _ = api.align_batch(ctx, rq, ra, iq, ia, L)
+    r_one, _ = api.align_batch(ctx, rq, ra, iq[17:18].contiguous(), ia[17:18].contiguous(), L)
+    assert np.array_equal(r_all.cpu().numpy()[17], r_one.cpu().numpy()[0])
