@@ -141,6 +141,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     __shared__ double D[n];
     __shared__ float red[NW][kMaxTopK];
     __shared__ int cand[kMaxTopK];
+    __shared__ float2 cs[kMaxTopK];  // 2 b(l) of every candidate, FP32
     const int Q = g.Q, P2 = Q / 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l8 = lane & 7, grp = lane >> 3;
@@ -319,38 +320,66 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
     __syncthreads();
 
-    // --- FP32 rescore of the candidates: direct residual sum
-    float sx[kMaxTopK], sy[kMaxTopK], part[kMaxTopK];
-    int lc[kMaxTopK];
-#pragma unroll
-    for (int c = 0; c < kMaxTopK; ++c) {
-        lc[c] = c < K ? cand[c] : 0;
+    // --- FP32 rescore of the candidates: direct residual sum.  Two
+    // candidates per pass, four consecutive elements per thread and step, two
+    // steps per iteration, so that the loads of an iteration are in flight
+    // together.  Q n is a multiple of 512, so a group of four elements is
+    // either wholly inside the table or wholly past its end.
+    if (threadIdx.x < K) {
+        const int c = threadIdx.x;
         double2 b = make_double2(0.0, 0.0);
-        if (a.mode == 0 && c < K) b = trans_moment(au, av, tw64[lc[c]]);
-        sx[c] = (float)(2.0 * b.x);
-        sy[c] = (float)(2.0 * b.y);
-        part[c] = 0.f;
+        if (a.mode == 0) b = trans_moment(au, av, tw64[cand[c]]);
+        cs[c] = make_float2((float)(2.0 * b.x), (float)(2.0 * b.y));
     }
-    for (int idx = threadIdx.x; idx < Q * n; idx += NT) {
-        const int j = idx >> 7, k = idx & (n - 1);
-        const float u = U[idx];
-        const float2 dk = tw[k];
-        const float *vrow = V + (int64_t)j * n;
+    __syncthreads();
+    for (int c0 = 0; c0 < K; c0 += 2) {
+        const int c1 = c0 + 1 < K ? c0 + 1 : c0;
+        const int la = cand[c0], lb = cand[c1];
+        const float ax = cs[c0].x, ay = cs[c0].y, bx = cs[c1].x, by = cs[c1].y;
+        float pa = 0.f, pb = 0.f;
+        for (int i0 = 4 * threadIdx.x; i0 < Q * n; i0 += 8 * NT) {
+            float4 u4[2];
+            float va[2][4], vb[2][4];
 #pragma unroll
-        for (int c = 0; c < kMaxTopK; ++c) {
-            if (c < K) {
-                const float e = u - vrow[(k + lc[c]) & (n - 1)] - (sx[c] * dk.x + sy[c] * dk.y);
-                part[c] += e * e;
+            for (int h = 0; h < 2; ++h) {
+                const int idx = i0 + 4 * NT * h;
+                u4[h] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) va[h][e] = vb[h][e] = 0.f;
+                if (idx < Q * n) {
+                    u4[h] = *(const float4 *)(U + idx);
+                    const float *vrow = V + (idx & ~(n - 1));
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        va[h][e] = vrow[(idx + e + la) & (n - 1)];
+                        vb[h][e] = vrow[(idx + e + lb) & (n - 1)];
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (i0 + 4 * NT * h < Q * n) {
+                    const int k0 = (i0 + 4 * NT * h) & (n - 1);
+                    const float uu[4] = {u4[h].x, u4[h].y, u4[h].z, u4[h].w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float2 dk = tw[k0 + e];
+                        const float da = uu[e] - va[h][e] - (ax * dk.x + ay * dk.y);
+                        const float db = uu[e] - vb[h][e] - (bx * dk.x + by * dk.y);
+                        pa += da * da;
+                        pb += db * db;
+                    }
+                }
             }
         }
-    }
 #pragma unroll
-    for (int c = 0; c < kMaxTopK; ++c) {
-        if (c < K) {
-            float v = part[c];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0) red[wave][c] = v;
+        for (int off = 32; off >= 1; off >>= 1) {
+            pa += __shfl_xor(pa, off, 64);
+            pb += __shfl_xor(pb, off, 64);
+        }
+        if (lane == 0) {
+            red[wave][c0] = pa;
+            if (c0 + 1 < K) red[wave][c0 + 1] = pb;
         }
     }
     __syncthreads();
@@ -361,11 +390,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
             float s = 0.f;
             for (int w = 0; w < NW; ++w) s += red[w][c];
             const float v = s / (float)nq;
-            if (c == 0 || v < best || (v == best && lc[c] < best_l)) {
+            if (c == 0 || v < best || (v == best && cand[c] < best_l)) {
                 best = v;
-                best_l = lc[c];
-                bsx = sx[c];
-                bsy = sy[c];
+                best_l = cand[c];
+                bsx = cs[c].x;
+                bsy = cs[c].y;
             }
         }
         const float L = (float)g.L;
