@@ -128,6 +128,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 constexpr int kA128Stride = 18;  // complex per lane row of the transpose buffer (16 + pad)
+constexpr int kA128VRow = 132;   // floats per staged table row (128 + pad)
 
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_align128(PairArgs a, Geo g, const float2 *__restrict__ gam,
@@ -184,11 +185,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = make_float2(0.f, 0.f);
     float2 *buf = xb + (wave * 8 + grp) * 8 * kA128Stride;
-    for (int p = wave * 8 + grp; p < P2; p += NG) {
-        float2 x[16];
-        const float *r0 = V + (int64_t)(2 * p) * n + l8;
+    // the wave stages the 16 table rows of its 8 packed rows into its part of
+    // the transpose buffer with coalesced 16-byte loads (rows kA128VRow
+    // floats apart, the two rows of a packed row adjacent), and each lane
+    // then reads its strided elements from LDS
+    float *varea = (float *)(xb + wave * 8 * 8 * kA128Stride);
+    const int iters = (P2 + NG - 1) / NG;
+    for (int it = 0; it < iters; ++it) {
+        const int pbase = wave * 8 + it * NG;
 #pragma unroll
-        for (int m = 0; m < 16; ++m) x[m] = make_float2(r0[8 * m], r0[n + 8 * m]);
+        for (int i = 0; i < 8; ++i) {
+            const int q = lane + 64 * i;          // 16-byte chunk, 32 per table row
+            const int row = q >> 5, c4 = q & 31;  // row = 2 (group) + (odd row)
+            const int gp = pbase + (row >> 1);
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gp < P2) v = *(const float4 *)(V + (int64_t)(2 * gp + (row & 1)) * n + 4 * c4);
+            *(float4 *)(varea + row * kA128VRow + 4 * c4) = v;
+        }
+        wave_lds_sync();
+        const int p = pbase + grp;
+        const bool active = p < P2;
+        float2 x[16];
+        const float *zr = varea + 2 * grp * kA128VRow + l8;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) x[m] = make_float2(zr[8 * m], zr[kA128VRow + 8 * m]);
+        wave_lds_sync();
         dft16(x);
 #pragma unroll
         for (int t = 1; t < 16; ++t) x[t] = cmul(x[t], tw[(l8 * t) & (n - 1)]);
@@ -208,6 +229,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         dft8(u0);
         dft8(u1);
         // lane l8 now holds Z[2 l8 + tau + 16 s] in u_tau[s]
+        if (!active) continue;
         const float4 *gp = (const float4 *)(G + (int64_t)p * kA128Slots + l8 * 16);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -320,66 +342,53 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
     __syncthreads();
 
-    // --- FP32 rescore of the candidates: direct residual sum.  Two
-    // candidates per pass, four consecutive elements per thread and step, two
-    // steps per iteration, so that the loads of an iteration are in flight
-    // together.  Q n is a multiple of 512, so a group of four elements is
-    // either wholly inside the table or wholly past its end.
+    // --- FP32 rescore of the candidates: direct residual sum.  V is staged
+    // through LDS in chunks of rows (coalesced 16-byte loads), so
+    // that the rotated reads V[j][(k + l) mod n] are LDS reads; consecutive
+    // lanes take consecutive k.  Two candidates per pass; the per-wave
+    // partial sums of every chunk are added in chunk order.
     if (threadIdx.x < K) {
         const int c = threadIdx.x;
         double2 b = make_double2(0.0, 0.0);
         if (a.mode == 0) b = trans_moment(au, av, tw64[cand[c]]);
         cs[c] = make_float2((float)(2.0 * b.x), (float)(2.0 * b.y));
     }
-    __syncthreads();
-    for (int c0 = 0; c0 < K; c0 += 2) {
-        const int c1 = c0 + 1 < K ? c0 + 1 : c0;
-        const int la = cand[c0], lb = cand[c1];
-        const float ax = cs[c0].x, ay = cs[c0].y, bx = cs[c1].x, by = cs[c1].y;
-        float pa = 0.f, pb = 0.f;
-        for (int i0 = 4 * threadIdx.x; i0 < Q * n; i0 += 8 * NT) {
-            float4 u4[2];
-            float va[2][4], vb[2][4];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int idx = i0 + 4 * NT * h;
-                u4[h] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) va[h][e] = vb[h][e] = 0.f;
-                if (idx < Q * n) {
-                    u4[h] = *(const float4 *)(U + idx);
-                    const float *vrow = V + (idx & ~(n - 1));
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        va[h][e] = vrow[(idx + e + la) & (n - 1)];
-                        vb[h][e] = vrow[(idx + e + lb) & (n - 1)];
-                    }
-                }
+    if (lane < K) red[wave][lane] = 0.f;
+    float *vl = (float *)xb;
+    // rows per chunk: the largest power of two that fits the transpose buffer
+    constexpr int RC = (NG * 8 * kA128Stride * 2) / n >= 128 ? 128 : 64;
+    static_assert(RC * n <= NG * 8 * kA128Stride * 2, "chunk fits the buffer");
+    for (int j0 = 0; j0 < Q; j0 += RC) {
+        const int rows = Q - j0 < RC ? Q - j0 : RC;
+        __syncthreads();
+        for (int q = threadIdx.x; q < rows * (n / 4); q += NT)
+            *(float4 *)(vl + 4 * q) = *(const float4 *)(V + (int64_t)j0 * n + 4 * q);
+        __syncthreads();
+        const float *Uc = U + (int64_t)j0 * n;
+        for (int c0 = 0; c0 < K; c0 += 2) {
+            const int c1 = c0 + 1 < K ? c0 + 1 : c0;
+            const int la = cand[c0], lb = cand[c1];
+            const float ax = cs[c0].x, ay = cs[c0].y, bx = cs[c1].x, by = cs[c1].y;
+            float pa = 0.f, pb = 0.f;
+#pragma unroll 4
+            for (int idx = threadIdx.x; idx < rows * n; idx += NT) {
+                const int jr = idx & ~(n - 1), k = idx & (n - 1);
+                const float u = Uc[idx];
+                const float2 dk = tw[k];
+                const float da = u - vl[jr + ((k + la) & (n - 1))] - (ax * dk.x + ay * dk.y);
+                const float db = u - vl[jr + ((k + lb) & (n - 1))] - (bx * dk.x + by * dk.y);
+                pa += da * da;
+                pb += db * db;
             }
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (i0 + 4 * NT * h < Q * n) {
-                    const int k0 = (i0 + 4 * NT * h) & (n - 1);
-                    const float uu[4] = {u4[h].x, u4[h].y, u4[h].z, u4[h].w};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const float2 dk = tw[k0 + e];
-                        const float da = uu[e] - va[h][e] - (ax * dk.x + ay * dk.y);
-                        const float db = uu[e] - vb[h][e] - (bx * dk.x + by * dk.y);
-                        pa += da * da;
-                        pb += db * db;
-                    }
-                }
+            for (int off = 32; off >= 1; off >>= 1) {
+                pa += __shfl_xor(pa, off, 64);
+                pb += __shfl_xor(pb, off, 64);
             }
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            pa += __shfl_xor(pa, off, 64);
-            pb += __shfl_xor(pb, off, 64);
-        }
-        if (lane == 0) {
-            red[wave][c0] = pa;
-            if (c0 + 1 < K) red[wave][c0 + 1] = pb;
+            if (lane == 0) {
+                red[wave][c0] += pa;
+                if (c0 + 1 < K) red[wave][c0 + 1] += pb;
+            }
         }
     }
     __syncthreads();
@@ -424,7 +433,7 @@ hipError_t launch_align128(const PairArgs &a, Geo g, const AngleTable &t, float2
                        a.n_ref, g.Q, gam, gamx);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    constexpr int NT = 512;
+    constexpr int NT = 256;  // 4 waves, four blocks per compute unit
     hipLaunchKernelGGL((k_align128<NT>), dim3((unsigned)P), dim3(NT), 0, s, a, g, gam, gamx, t.d32,
                        t.d64);
     return hipGetLastError();
