@@ -8,7 +8,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_spectrum(const float *__restrict__ qt, int64_t N, Geo g,
                                                  const float2 *__restrict__ tw32, void *spec,
                                                  int bf16) {
-    extern __shared__ float2 lds2[];
+    extern __shared__ __align__(16) float2 lds2[];
     const int64_t gi = blockIdx.x;
     if (gi >= N) return;
     const int Wn = g.n / 2 + 1;
@@ -21,7 +21,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_align_pairs(PairArgs a, Geo g,
                                                     const float2 *__restrict__ tw32,
                                                     const double2 *__restrict__ tw64) {
-    extern __shared__ float2 lds2[];
+    extern __shared__ __align__(16) float2 lds2[];
     const int n = g.n, Q = g.Q, Wn = n / 2 + 1;
     const int64_t pi = blockIdx.x;
     const int64_t P = a.pairs ? a.n_pairs : a.n_ref * a.n_img;

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
                                                    int16_t *__restrict__ cand) {
     constexpr int Wn = N / 2 + 1;
     constexpr int SS = 2 * Wn + 1;  // odd LDS row stride
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     float *Sl = lds;                           // [256 pairs][SS]
     float2 *tw = (float2 *)(lds + 256 * SS);  // [N]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     constexpr int Q = N;
     constexpr int EPT = Q * N / 64;
     constexpr int RS = 64 / N;  // rows per element step
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     float *U2 = lds;  // [Q][2N]: each row stored twice
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * 8 + 2 * wave;

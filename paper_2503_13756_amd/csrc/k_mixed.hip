@@ -5,6 +5,7 @@
 // lives in device memory, so a captured graph can be replayed with new
 // contents and live counts.  The per-image arithmetic is the same device code
 // as the single-geometry kernels (projection, CDF/quantiles, FFT alignment).
+#include "align128_dev.h"
 #include "align_dev.h"
 #include "proj_dev.h"
 #include "quant_dev.h"
@@ -38,11 +39,11 @@ __device__ __forceinline__ int64_t next_work(unsigned long long *counter, int64_
 // PMF slot of slot_floats per block, used by images whose PMF table does not
 // fit in LDS.
 template <int NT, int TPW>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_tables_mixed(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256 ? 2 : 4))) void k_tables_mixed(
     const MixGroup *__restrict__ G, unsigned long long *counter, float *scratch,
     int64_t slot_floats, int region_floats, int /*lmax*/, int nmax) {
     constexpr int NW = NT / 64;
-    extern __shared__ double ldsd[];
+    extern __shared__ __align__(16) double ldsd[];  // 16-byte aligned: ds_read_b128 on strips
     __shared__ int64_t wslot;
     float *region = (float *)ldsd;
     double *colS = ldsd + region_floats / 2;
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 // FP32 spectrum of the reference of every item: one block per item.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_refspec_mixed(const MixGroup *__restrict__ G) {
-    extern __shared__ float2 lds2[];
+    extern __shared__ __align__(16) float2 lds2[];
     const int i = blockIdx.x;
     if (i >= G->nitems) return;
     const MixItem &it = G->items[i];
@@ -87,15 +88,69 @@ __global__ __launch_bounds__(NT) void k_refspec_mixed(const MixGroup *__restrict
     spectrum_block<NT>(it.ref_qt, it.n, it.Q, it.ref_spec, 0, it.d32, lds2);
 }
 
-// Alignment of every image of every item against the item's reference.
+// Register-FFT coefficients of the references of the n = 128 items (after
+// k_refspec_mixed): one block per item.
+__global__ __launch_bounds__(256) void k_gamma_mixed(const MixGroup *__restrict__ G) {
+    const int i = blockIdx.x;
+    if (i >= G->nitems) return;
+    const MixItem &it = G->items[i];
+    if (!it.gam || it.count <= 0) return;
+    const int P2 = it.Q / 2;
+    for (int idx = threadIdx.x; idx < P2 * (kA128Slots + 2); idx += 256) {
+        const int p = idx / (kA128Slots + 2), slot = idx - p * (kA128Slots + 2);
+        const float2 c = gamma128_coef(it.ref_spec, it.Q, p, slot);
+        if (slot < kA128Slots) it.gam[p * kA128Slots + slot] = c;
+        else it.gam[P2 * kA128Slots + 2 * p + (slot - kA128Slots)] = c;
+    }
+}
+
+// n = 128 items (work items [0, split)): register-FFT alignment.
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_align128_mixed(
+    const MixGroup *__restrict__ G, unsigned long long *counter) {
+    __shared__ A128Lds<NT> sm;
+    __shared__ int64_t wslot;
+    const int64_t split = G->split;
+    for (;;) {
+        const int64_t w = next_work<NT>(counter, &wslot);
+        if (w >= split) break;
+        const MixItem &it = G->items[find_item(G, w)];
+        const int64_t gi = w - it.first;
+        const int P2 = it.Q / 2;
+        A128Job job;
+        job.U = it.ref_qt;
+        job.V = it.qt + gi * (int64_t)it.Q * 128;
+        job.au = it.ref_aux;
+        job.av = it.aux + 4 * gi;
+        job.G = it.gam;
+        job.GX = it.gam + (int64_t)P2 * kA128Slots;
+        job.d32 = it.d32;
+        job.d64 = it.d64;
+        job.res = it.out + gi;
+        job.curve = nullptr;
+        job.Q = it.Q;
+        job.L = it.L;
+        job.mode = it.mode;
+        job.bf16 = it.bf16;
+        job.top_k = it.top_k;
+        int status = 0;
+        if (isnan(job.au[0]) || isnan(job.av[0])) status = 2;
+        else if (!(job.au[0] > 0.0) || !(job.av[0] > 0.0)) status = 1;
+        job.status = status;
+        align128_pair<NT>(job, sm);
+    }
+}
+
+// Other items (work items [split, total)): LDS-FFT alignment of every image
+// against the item's reference.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_align_mixed(const MixGroup *__restrict__ G,
                                                     unsigned long long *counter) {
-    extern __shared__ float2 lds2[];
+    extern __shared__ __align__(16) float2 lds2[];
     __shared__ int64_t wslot;
-    const int64_t total = G->total;
+    const int64_t total = G->total, split = G->split;
     for (;;) {
-        const int64_t w = next_work<NT>(counter, &wslot);
+        const int64_t w = split + next_work<NT>(counter, &wslot);
         if (w >= total) break;
         const MixItem &it = G->items[find_item(G, w)];
         const int64_t gi = w - it.first;
@@ -119,7 +174,8 @@ __global__ __launch_bounds__(NT) void k_align_mixed(const MixGroup *__restrict__
 // LDS and scratch needs of a set of items; fills the per-item tile fields
 // (fused, TC) and returns the launch parameters.
 MixLaunch plan_mixed(MixItem *items, int nitems) {
-    constexpr int NT = 256;
+    constexpr int NT = 256;                         // align kernels
+    constexpr int NTT = kMixTablesThreads, TPW = kMixTablesTasks;  // tables kernel
     MixLaunch m{};
     int lmax = 8, nmax = 8, region = 0;
     int64_t slot = 0;
@@ -130,11 +186,11 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
         if (R > strip_rows_max(it.L)) R = strip_rows_max(it.L);
         if (R > it.L) R = it.L;
         if (R < 1) R = 1;
-        if (R > NT) R = NT;
+        if (R > NTT) R = NTT;
         it.R = R;
         const int slots = it.n / 8 + 1;
         const int ntasks = (slots * it.L + 63) / 64;
-        const bool one_group = ntasks <= (NT / 64) * 12;
+        const bool one_group = ntasks <= (NTT / 64) * TPW;
         const int strip = kStripFloats;
         const int pmf = it.n * it.L;
         // fused when a single task group and the PMF fits beside nothing else
@@ -150,7 +206,11 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
     }
     region = (region + 1) & ~1;
     const size_t fixed = sizeof(float) * region + sizeof(double) * 2 * nmax;
-    const size_t budget = fixed + 16 * 1024 <= 79 * 1024 ? 79 * 1024 : 150 * 1024;
+    // two blocks per compute unit whenever the narrowest quantile tile fits
+    int qbig = 8;
+    for (int i = 0; i < nitems; ++i) qbig = max(qbig, items[i].Q);
+    const size_t budget =
+        fixed + sizeof(float) * (size_t)qbig * 9 <= 79 * 1024 ? 79 * 1024 : 150 * 1024;
     int qmax = 8;
     for (int i = 0; i < nitems; ++i) {
         MixItem &it = items[i];
@@ -167,9 +227,9 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
 }
 
 void prepare_mixed() {
-    constexpr int NT = 256, TPW = 12;
+    constexpr int NT = 256, NTT = kMixTablesThreads, TPW = kMixTablesTasks;
     static const hipError_t a1 = hipFuncSetAttribute(
-        (const void *)k_tables_mixed<NT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (const void *)k_tables_mixed<NTT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize,
         150 * 1024);
     static const hipError_t a2 = hipFuncSetAttribute(
         (const void *)k_refspec_mixed<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
@@ -185,17 +245,21 @@ void prepare_mixed() {
 // replayed with new descriptor contents.
 hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const MixLaunch &m,
                         unsigned long long *counters, float *scratch, int grid, hipStream_t s) {
-    constexpr int NT = 256, TPW = 12;
+    constexpr int NT = 256, NTT = kMixTablesThreads, TPW = kMixTablesTasks;
     prepare_mixed();
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, 3);
-    hipLaunchKernelGGL((k_tables_mixed<NT, TPW>), dim3((unsigned)grid), dim3(NT), m.tables_lds, s,
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, 4);
+    hipLaunchKernelGGL((k_tables_mixed<NTT, TPW>), dim3((unsigned)grid), dim3(NTT), m.tables_lds, s,
                        d_refs, counters + 0, scratch, m.slot_floats, m.region_floats, m.lmax,
                        m.nmax);
     hipLaunchKernelGGL((k_refspec_mixed<NT>), dim3((unsigned)kMaxMix), dim3(NT),
                        sizeof(float2) * (kMaxN + 2 * kFftElems), s, d_imgs);
-    hipLaunchKernelGGL((k_tables_mixed<NT, TPW>), dim3((unsigned)grid), dim3(NT), m.tables_lds, s,
+    hipLaunchKernelGGL((k_tables_mixed<NTT, TPW>), dim3((unsigned)grid), dim3(NTT), m.tables_lds, s,
                        d_imgs, counters + 1, scratch, m.slot_floats, m.region_floats, m.lmax,
                        m.nmax);
+    hipLaunchKernelGGL(k_gamma_mixed, dim3((unsigned)kMaxMix), dim3(256), 0, s, d_imgs);
+    // four 40 KiB blocks of the register-FFT kernel per compute unit
+    hipLaunchKernelGGL((k_align128_mixed<NT>), dim3((unsigned)(2 * grid)), dim3(NT), 0, s, d_imgs,
+                       counters + 3);
     hipLaunchKernelGGL((k_align_mixed<NT>), dim3((unsigned)grid), dim3(NT), m.align_lds, s, d_imgs,
                        counters + 2);
     return hipGetLastError();

@@ -8,7 +8,7 @@ template <int NT, int TPW>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256 ? 2 : 4))) void k_project(const float *__restrict__ img, int64_t N,
                                                 ProjShape P, const float2 *__restrict__ dtab,
                                                 float *__restrict__ pmf) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     const int64_t g = blockIdx.x;
     if (g >= N) return;
     const float *F = img + g * (int64_t)P.L * P.L;
@@ -29,7 +29,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_project_split(const float *__restrict__ img, int64_t N,
                                                       ProjShape P, const float2 *__restrict__ dtab,
                                                       float *__restrict__ pmf) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     const int64_t g = blockIdx.x;
     if (g >= N) return;
     const float *F = img + g * (int64_t)P.L * P.L;

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256
                                                const double2 *__restrict__ d64,
                                                float *__restrict__ qt, double *__restrict__ aux) {
     constexpr int NW = NT / 64;
-    extern __shared__ double ldsd[];
+    extern __shared__ __align__(16) double ldsd[];  // 16-byte aligned: ds_read_b128 on strips
     const int64_t g = blockIdx.x;
     if (g >= N) return;
     const ProjShape &P = T.P;

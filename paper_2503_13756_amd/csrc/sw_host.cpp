@@ -173,9 +173,21 @@ sw_status run_stack_chunk(Ctx *c, const sw_stack *const *st, int n, int mode, in
     sw::MixGroup &gr = hg[0], &gi = hg[1];
     gr.nitems = gi.nitems = n;
     gr.total = gi.total = 0;
-    int64_t first = 0;
-    for (int i = 0; i < n; ++i) {
-        const sw_stack &k = *st[i];
+    // items aligned by the n = 128 register-FFT kernel first (work items
+    // [0, split)), the rest after
+    auto fast_geom = [&](const sw_stack &k) {
+        return k.geom.n_angles == 128 && !c->generic_align;
+    };
+    std::vector<int> order;
+    for (int i = 0; i < n; ++i)
+        if (fast_geom(*st[i])) order.push_back(i);
+    const int nfast = (int)order.size();
+    for (int i = 0; i < n; ++i)
+        if (!fast_geom(*st[i])) order.push_back(i);
+    int64_t first = 0, split = 0;
+    for (int ii = 0; ii < n; ++ii) {
+        const int i = ii;
+        const sw_stack &k = *st[order[ii]];
         sw::Geo geo{k.geom.L, k.geom.n_angles, k.geom.n_quantiles, k.geom.levels};
         const sw::AngleTable *t;
         if ((stt = get_table(c, geo.n, &t)) != SW_OK) return stt;
@@ -205,12 +217,17 @@ sw_status run_stack_chunk(Ctx *c, const sw_stack *const *st, int n, int mode, in
         a.out = (sw::Result *)k.out;
         a.first = first;
         a.count = k.N;
+        a.gam = nullptr;
+        r.gam = nullptr;
         first += k.N;
+        if (i < nfast) split = first;
         gr.items[i] = r;
         gi.items[i] = a;
     }
     gr.total = n;
     gi.total = first;
+    gr.split = 0;
+    gi.split = split;
     sw::MixLaunch m = sw::plan_mixed(gi.items, n);
     for (int i = 0; i < n; ++i) {
         gr.items[i].R = gi.items[i].R;
@@ -227,9 +244,12 @@ sw_status run_stack_chunk(Ctx *c, const sw_stack *const *st, int n, int mode, in
     };
     const size_t o_groups = take(2 * sizeof(sw::MixGroup));
     const size_t o_cnt = take(4 * sizeof(unsigned long long));
-    std::vector<size_t> o_spec(n);
-    for (int i = 0; i < n; ++i)
+    std::vector<size_t> o_spec(n), o_gam(n);
+    for (int i = 0; i < n; ++i) {
+        const sw::Geo gg{gi.items[i].L, gi.items[i].n, gi.items[i].Q, gi.items[i].levels};
         o_spec[i] = take(sizeof(float2) * (size_t)(gi.items[i].n / 2 + 1) * gi.items[i].Q);
+        o_gam[i] = i < nfast ? take(sw::align128_scratch_bytes(gg, 1)) : 0;
+    }
     const size_t o_slots = take(sizeof(float) * (size_t)m.slot_floats * grid);
     void *scr;
     if ((stt = get_scratch(c, off, s, &scr)) != SW_OK) return stt;
@@ -237,6 +257,7 @@ sw_status run_stack_chunk(Ctx *c, const sw_stack *const *st, int n, int mode, in
     for (int i = 0; i < n; ++i) {
         gi.items[i].ref_spec = (float2 *)(base + o_spec[i]);
         gr.items[i].ref_spec = gi.items[i].ref_spec;
+        if (i < nfast) gi.items[i].gam = (float2 *)(base + o_gam[i]);
     }
     sw::MixGroup *d_groups = (sw::MixGroup *)(base + o_groups);
     hipError_t e = hipMemcpyAsync(d_groups, hg, 2 * sizeof(sw::MixGroup), hipMemcpyHostToDevice, s);

@@ -108,7 +108,9 @@ bool mfma_path_supported(Geo g);
 hipError_t launch_mfma_all_pairs(const MfmaArgs &a, Geo g, const AngleTable &t, hipStream_t s);
 
 // ---- mixed-geometry persistent launches (uneven stacks, serving) ----
-constexpr int kMaxMix = 64;  // stacks (or requests) per launch
+constexpr int kMaxMix = 64;
+// block size and tasks per wave of the persistent tables kernel
+constexpr int kMixTablesThreads = 512, kMixTablesTasks = 6;  // stacks (or requests) per launch
 
 // One stack of images of one geometry aligned against one reference.
 struct MixItem {
@@ -127,9 +129,12 @@ struct MixItem {
     int TC;     // quantile column tile
     int fused;  // PMF kept in LDS
     int mode, bf16, top_k;
+    float2 *gam;  // n = 128 register-FFT alignment: coefficients [Q/2][130] of the
+                  // reference (written by the launch), or null for the LDS-FFT path
 };
 struct MixGroup {
     int64_t total;
+    int64_t split;  // work items [0, split) belong to items with gam (listed first)
     int nitems;
     int pad;
     MixItem items[kMaxMix];

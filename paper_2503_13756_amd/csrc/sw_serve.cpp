@@ -101,8 +101,8 @@ struct Req {
     RState state = RState::Pending;
     bool cancel = false;
     size_t off = 0, bytes = 0;  // own arena region
-    size_t o_img = 0, o_ref = 0, o_qt = 0, o_aux = 0, o_out = 0, o_spec = 0, o_rqt = 0,
-           o_raux = 0;          // absolute arena offsets
+    size_t o_img = 0, o_ref = 0, o_qt = 0, o_aux = 0, o_out = 0, o_spec = 0, o_gam = 0,
+           o_rqt = 0, o_raux = 0;  // absolute arena offsets
     uint64_t ref_key = 0;       // cache entry used (0 = own tables)
     bool ref_compute = false;   // this request's step computes the reference tables
     sw_result *host_out = nullptr;
@@ -147,10 +147,15 @@ sw_status require_server(Ctx *c, Server **s) {
     return SW_OK;
 }
 
+// register-FFT coefficients of the reference (n = 128 only)
+size_t gam_bytes(const sw::Geo &g) {
+    return sw::align128_supported(g) ? sw::align128_scratch_bytes(g, 1) : 0;
+}
+
 size_t request_bytes(const sw_request &r, const sw::Geo &g, bool own_ref_tables) {
     const size_t N = (size_t)r.N, L2 = (size_t)g.L * g.L, T = (size_t)g.Q * g.n;
     size_t b = up(4 * N * L2) + up(4 * N * T) + up(32 * N) + up(24 * N) + up(4 * L2) +
-               up(8 * (size_t)(g.n / 2 + 1) * g.Q);
+               up(8 * (size_t)(g.n / 2 + 1) * g.Q) + up(gam_bytes(g));
     if (own_ref_tables) b += up(4 * T) + up(32);
     return b;
 }
@@ -235,6 +240,8 @@ void admit(Server *s, std::vector<Req *> &fresh) {
         o += up(4 * L2);
         q->o_spec = o;
         o += up(8 * (size_t)(g.n / 2 + 1) * g.Q);
+        q->o_gam = o;
+        o += up(gam_bytes(g));
         if (own_ref) {
             q->o_rqt = o;
             o += up(4 * T);
@@ -294,6 +301,8 @@ hipError_t issue_step(Server *s, const std::vector<Req *> &rs, hipEvent_t done) 
     st = get_table(c, g.n, &t);
     if (st != SW_OK) return hipErrorUnknown;
     std::vector<uint64_t> keys_done;
+    // a step holds one geometry: all items take the same alignment kernel
+    const bool fast = sw::align128_supported(g) && !c->generic_align;
     for (size_t i = 0; i < rs.size(); ++i) {
         Req *q = rs[i];
         sw::MixItem a{};
@@ -311,6 +320,7 @@ hipError_t issue_step(Server *s, const std::vector<Req *> &rs, hipEvent_t done) 
         a.ref_qt = (const float *)(s->base + q->o_rqt);
         a.ref_aux = (const double *)(s->base + q->o_raux);
         a.ref_spec = (float2 *)(s->base + q->o_spec);
+        a.gam = fast ? (float2 *)(s->base + q->o_gam) : nullptr;
         a.img = (const float *)(s->base + q->o_img);
         a.qt = (float *)(s->base + q->o_qt);
         a.aux = (double *)(s->base + q->o_aux);
@@ -328,12 +338,15 @@ hipError_t issue_step(Server *s, const std::vector<Req *> &rs, hipEvent_t done) 
             r.aux = (double *)(s->base + q->o_raux);
             r.first = gr.nitems;
             r.count = 1;
+            r.gam = nullptr;
             gr.items[gr.nitems++] = r;
             if (q->ref_key) keys_done.push_back(q->ref_key);
         }
     }
     gr.total = gr.nitems;
     gi.total = first;
+    gr.split = 0;
+    gi.split = fast ? first : 0;
     sw::MixLaunch m = sw::plan_mixed(gi.items, gi.nitems);
     for (int i = 0; i < gr.nitems; ++i) {
         gr.items[i].R = gi.items[0].R;
