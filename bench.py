@@ -89,7 +89,9 @@ def parse():
     p.add_argument("--out", default=None, help="also write the JSON line to this file")
     p.add_argument("--skip-extra", action="store_true",
                    help="only the 1-vs-10,000 workload (for profiling runs)")
-    p.add_argument("--requests", type=int, default=400, help="serving trace length")
+    p.add_argument("--requests", type=int, default=400, help="serving trace length (L = 128)")
+    p.add_argument("--requests-mixed", type=int, default=300,
+                   help="serving trace length (L in {64, 128, 256})")
     return p.parse_args()
 
 
@@ -231,15 +233,24 @@ def main():
         line["all_pairs"], extra_res["all_pairs"] = bench_all_pairs(api, ctx, torch)
         torch.cuda.empty_cache()
         log("uneven stacks")
-        line["uneven_stacks"] = bench_uneven(api, ctx, torch)
+        line["uneven_stacks"], extra_res["uneven"] = bench_uneven(api, ctx, torch)
         torch.cuda.empty_cache()
+        log("single pair")
+        line["single_pair"] = single_pair(api, ctx, torch)
         log("serving trace")
         line["serving"] = bench_serving(api, torch, args.requests)
+        torch.cuda.empty_cache()
+        log("serving trace, mixed L")
+        line["serving_mixed_L"] = bench_serving(api, torch, args.requests_mixed, Ls=(64, 128, 256),
+                                                distinct=1000)
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, res32, res16, L, n, Q)
         if "all_pairs" in extra_res:
             line["cpu_baseline"]["all_pairs_error"] = all_pairs_error(*extra_res["all_pairs"])
+        if "uneven" in extra_res:
+            log("uneven stacks parity (oracle)")
+            line["cpu_baseline"]["uneven_parity"] = uneven_parity(*extra_res["uneven"])
 
     s = json.dumps(line)
     print(s, flush=True)
@@ -323,6 +334,9 @@ def bench_uneven(api, ctx, torch, total=50000, distinct=64):
         reps = (size + len(imgs) - 1) // len(imgs)
         dev.append((torch.from_numpy(ref).cuda(), x.repeat(reps, 1, 1)[:size].contiguous()))
     ms = timed(torch, lambda: api.align_stacks(ctx, dev, prec=1), 3)
+    outs = api.align_stacks(ctx, dev, prec=1)
+    torch.cuda.synchronize()
+    res = [api.unpack_results(o["res"]) for o in outs]
     per_L = {}
     for L in sorted({s[0] for s in stacks}):
         sub = [d for d, s in zip(dev, stacks) if s[0] == L]
@@ -330,25 +344,83 @@ def bench_uneven(api, ctx, torch, total=50000, distinct=64):
         t = timed(torch, lambda: api.align_stacks(ctx, sub, prec=1), 3)
         per_L[str(L)] = {"images": nimg, "ms": t, "alignments_per_s": nimg / (t * 1e-3)}
     n = sum(int(d[1].shape[0]) for d in dev)
-    return {"workload": f"{len(stacks)} stacks, {n} images, L in {{64,96,128,192,256}}, sizes "
-                        "U[100,5000], own reference each, FP32 tables, bf16 correlation, top-4 "
-                        "FP32 rescore", "images": n, "ms_per_step": ms,
-            "value": n / (ms * 1e-3), "unit": "alignments/s", "per_L": per_L}
+    return ({"workload": f"{len(stacks)} stacks, {n} images, L in {{64,96,128,192,256}}, sizes "
+                         "U[100,5000], own reference each, FP32 tables, bf16 correlation, top-4 "
+                         "FP32 rescore", "images": n, "ms_per_step": ms,
+             "value": n / (ms * 1e-3), "unit": "alignments/s", "per_L": per_L},
+            (stacks, res))
 
 
-def _pool(L, N, seed):
+def uneven_parity(stacks, res, S=50):
+    """GPU results of the uneven stacks against the FP64 oracle on the first
+    S images of every stack (the distinct rendered copies)."""
+    from oracle import oracle as O
+    from tests import parity
+
+    ok, total, worst = 0, 0, 0.0
+    fails = []
+    for (L, ref, imgs, size), r in zip(stacks, res):
+        m = min(S, len(imgs), size)
+        o = O.align_images(ref, imgs[:m], L, L, want_curve=True)
+        sub = {k: v[:m] for k, v in r.items()}
+        try:
+            parity.check(sub, o, L, parity.TAU_BF16, o["curve"])
+            ok += m
+        except AssertionError as e:
+            fails.append(f"L={L}: " + str(e)[:120])
+        rel = np.abs(sub["sw2sq"] - o["sw2sq"]) / np.maximum(o["sw2sq"], 1e-12)
+        worst = max(worst, float(rel.max()))
+        total += m
+    return {"pairs": total, "parity_ok_pairs": ok, "max_rel_err_sw2sq": worst,
+            "failures": fails[:3]}
+
+
+def single_pair(api, ctx, torch, reps=50):
+    """The single-pair workload (L = 64, n = Q = 64): images to result, one
+    call sequence per pair, synchronised; mean latency."""
+    w = synth.workload(0)
+    L = 64
+    r = torch.from_numpy(w["ref"][None].copy()).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(w["imgs"])).cuda()
+
+    def one():
+        rq, ra = api.tables(ctx, r, L, L)
+        iq, ia = api.tables(ctx, x, L, L)
+        res, _ = api.align_batch(ctx, rq, ra, iq, ia, L)
+        return res
+
+    for _ in range(5):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one()
+        torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    g = api.unpack_results(one())
+    return {"workload": "1 pair, L=64, n=Q=64 (images to result, synchronised per pair)",
+            "latency_ms": dt * 1e3, "rot_index": int(g["rot_index"][0]),
+            "shift_px": [float(v) for v in g["shift_px"][0]], "sw2sq": float(g["sw2sq"][0]),
+            "paper_context": "0.0027 s per pair at L=64 on CPU (Table 3)"}
+
+
+def _pool(L, N, seed, distinct=None):
     """Rendered copies for the serving trace, in pinned (page-locked) host
     memory as a serving front end would hold request buffers, so host to
-    device copies run at DMA speed for both forms."""
+    device copies run at DMA speed for both forms.  With `distinct`, that
+    many copies are rendered and tiled to N."""
     import torch
 
-    ref, imgs, _, _ = synth.make_stack(seed, L, N)
+    m = N if distinct is None else min(N, distinct)
+    ref, imgs, _, _ = synth.make_stack(seed, L, m)
+    if m < N:
+        imgs = np.ascontiguousarray(np.tile(imgs, ((N + m - 1) // m, 1, 1))[:N])
     ref_p = torch.from_numpy(ref).pin_memory()
     imgs_p = torch.from_numpy(imgs).pin_memory()
     return ref_p, imgs_p
 
 
-def bench_serving(api, torch, n_req, Ls=(128,), pool_n=5000, seed=1004):
+def bench_serving(api, torch, n_req, Ls=(128,), pool_n=5000, seed=1004, distinct=None):
     """Poisson trace of requests (1 reference + N images, N log-uniform in
     [1, 5000]); served bf16 form (continuous batching) against the plain FP32
     path serving one request at a time.  Images come from a pool of rendered
@@ -360,7 +432,7 @@ def bench_serving(api, torch, n_req, Ls=(128,), pool_n=5000, seed=1004):
     import threading
 
     rng = np.random.Generator(np.random.PCG64(seed))
-    pools = {L: _pool(L, pool_n, 3000 + L) for L in Ls}
+    pools = {L: _pool(L, pool_n, 3000 + L, distinct) for L in Ls}
     reqs = []
     for _ in range(n_req):
         L = int(rng.choice(Ls))
