@@ -17,9 +17,9 @@
 // is summed directly (no E_a + E_b - 2C cancellation), and the translation is
 // added in closed form, R0/(nQ) - 2|b(l)|^2, which is the exact minimum over
 // s of the residual with the shift s.d_k removed from every column (the same
-// algebra as the correction above, using sum_k d_k d_k^T = (n/2) I).  V tables
-// of TG images sit in registers while reference tables stream through LDS as
-// duplicated rows, so every lag is a fixed-offset LDS read.
+// algebra as the correction above, using sum_k d_k d_k^T = (n/2) I).  Image
+// tables sit in registers while reference tables stream through LDS as four
+// rotated copies, so every lag is a run of aligned 16-byte LDS reads.
 #include "sw_internal.h"
 
 namespace sw {
@@ -150,103 +150,185 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
     for (int c = 0; c < top_k; ++c) out[c] = (int16_t)bl[c];
 }
 
-// Rescore: grid (ceil(n_img / 8), ceil(n_ref / TR)), 256 threads.  Wave w
-// holds the V tables of images g0 + 2w and g0 + 2w + 1 in registers: lane l
-// owns elements e = l + 64 m (m < EPT), i.e. column k = l % N and rows
-// j = l / N + m (64 / N) (N divides 64).  Reference tables stream through LDS.
+// Sum over the 64 lanes: butterflies inside each row of 16 lanes on DPP,
+// then the four row totals.  Fixed order, so the result is deterministic.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+    v += dpp_f<0xb1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4e>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x141>(v);  // row_half_mirror
+    v += dpp_f<0x140>(v);  // row_mirror
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+// Rescore: grid (ceil(n_img / 8), ceil(n_ref / TR)), 512 threads; wave w owns
+// image g0 + w and walks the references r0 .. r1 - 1.  Lane layout: chunk
+// p = lane % CPR of four columns (CPR = N / 4 chunks per row) in rows
+// jr + RPS m (jr = lane / CPR, RPS = 64 / CPR), so the image's table is
+// STEPS float4 registers per lane.  Each reference table is staged in LDS as
+// four rotated copies C_s[j][i] = U[j][(i - s) mod N], s = 0..3: the lag
+// l = 4a + s pairs the lane's chunk with the aligned 16 bytes
+// C_s[j][4((p - a) mod CPR) ..], one conflict-free b128 read per four
+// elements at a fixed offset per row step.  Lane c < top_k carries candidate
+// c (its lag, translation and objective); the next reference's table and
+// candidates are fetched into registers while this one is summed.
 template <int N, int KMAX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_rescore_tiles(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rescore_tiles(
     const float *__restrict__ ref_qt, const double *__restrict__ ref_aux, int64_t n_ref,
     const float *__restrict__ img_qt, const double *__restrict__ img_aux, int64_t n_img, int TR,
     int mode, int top_k, int L, const int16_t *__restrict__ cand, const double2 *__restrict__ tw64,
     Result *__restrict__ out) {
-    constexpr int Q = N;
-    constexpr int EPT = Q * N / 64;
-    constexpr int RS = 64 / N;  // rows per element step
-    extern __shared__ __align__(16) float lds[];
-    float *U2 = lds;  // [Q][2N]: each row stored twice
+    constexpr int Q = N, CPR = N / 4, RPS = 64 / CPR, STEPS = Q / RPS;
+    constexpr int COPY = Q * N, NCH = Q * N / 4, CH = (NCH + 511) / 512;
+    static_assert(KMAX <= 64 && STEPS * RPS == Q, "rescore layout");
+    extern __shared__ __align__(16) float lds[];  // [4][Q][N]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t g0 = (int64_t)blockIdx.x * 8 + 2 * wave;
+    const int64_t g = (int64_t)blockIdx.x * 8 + wave;
+    const bool live = g < n_img;  // wave-uniform
+    const int64_t gc = live ? g : n_img - 1;
     const int64_t r0 = (int64_t)blockIdx.y * TR;
-    const int64_t r1 = min((int64_t)r0 + TR, n_ref);
-    const int kcol = lane % N, jrow = lane / N;
-    float vv[2][EPT];
+    const int64_t r1 = min(r0 + (int64_t)TR, n_ref);
+    const int p = lane % CPR, jr = lane / CPR;
+    float4 vv[STEPS];
+    {
+        const float *V = img_qt + gc * (int64_t)COPY;
 #pragma unroll
-    for (int gi = 0; gi < 2; ++gi) {
-        const int64_t g = g0 + gi < n_img ? g0 + gi : n_img - 1;
-        const float *V = img_qt + g * (int64_t)Q * N;
-#pragma unroll
-        for (int m = 0; m < EPT; ++m) vv[gi][m] = V[lane + 64 * m];
+        for (int m = 0; m < STEPS; ++m)
+            vv[m] = *(const float4 *)(V + (jr + RPS * m) * N + 4 * p);
     }
-    const int base = jrow * 2 * N + kcol + N;  // U2 index of (jrow, kcol) shifted by N
+    const double av0 = img_aux[4 * gc], av1 = img_aux[4 * gc + 2], av2 = img_aux[4 * gc + 3];
     const double nq = (double)N * (double)Q;
+    // prefetch registers: this thread's chunks of the next reference table
+    // and, unless a row is one DPP row of 16 lanes, the chunks one column
+    // group to their left (same row, cyclic)
+    constexpr bool kRor = CPR == 16;
+    float4 ucur[CH], uprev[kRor ? 1 : CH];
+    int lnext = 0;
+    auto fetch = [&](int64_t r) {
+        const float4 *U = (const float4 *)(ref_qt + r * (int64_t)COPY);
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int c = t + 512 * i;
+            if (c < NCH) {
+                ucur[i] = U[c];
+                if constexpr (!kRor) {
+                    const int j = c / CPR, q = c % CPR;
+                    uprev[i] = U[j * CPR + (q + CPR - 1) % CPR];
+                }
+            }
+        }
+        lnext = lane < top_k ? (int)cand[(r * n_img + gc) * top_k + lane] : 0;
+    };
+    if (r0 < r1) fetch(r0);
     for (int64_t r = r0; r < r1; ++r) {
-        __syncthreads();
-        const float *U = ref_qt + r * (int64_t)Q * N;
-        for (int e = t; e < Q * N; e += 256) {
-            const float u = U[e];
-            const int j = e / N, k = e % N;
-            U2[j * 2 * N + k] = u;
-            U2[j * 2 * N + k + N] = u;
+        const int lmine = lnext;
+        const double au0 = ref_aux[4 * r], au1 = ref_aux[4 * r + 2], au2 = ref_aux[4 * r + 3];
+        __syncthreads();  // every wave is done with the previous table
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int c = t + 512 * i;
+            if (c < NCH) {
+                const float4 u = ucur[i];
+                float4 v;
+                if constexpr (kRor) {
+                    // chunk q - 1 (mod 16) of the same row sits one lane down
+                    // in this DPP row: row_ror:1
+                    v.x = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(u.x), 0x121, 0xf, 0xf, false));
+                    v.y = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(u.y), 0x121, 0xf, 0xf, false));
+                    v.z = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(u.z), 0x121, 0xf, 0xf, false));
+                    v.w = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(u.w), 0x121, 0xf, 0xf, false));
+                } else {
+                    v = uprev[i];
+                }
+                float *d = lds + 4 * c;
+                *(float4 *)(d) = u;
+                *(float4 *)(d + COPY) = make_float4(v.w, u.x, u.y, u.z);
+                *(float4 *)(d + 2 * COPY) = make_float4(v.z, v.w, u.x, u.y);
+                *(float4 *)(d + 3 * COPY) = make_float4(v.y, v.z, v.w, u.x);
+            }
         }
         __syncthreads();
-        const double *au = ref_aux + 4 * r;
+        if (r + 1 < r1) fetch(r + 1);
+        if (!live) continue;  // wave-uniform, after both barriers
+        // translation at this lane's candidate lag (mode 0), Sec. 2.3
+        double bx = 0.0, by = 0.0;
+        if (mode == 0) {
+            const double2 d = tw64[lmine];
+            const double cs = d.x, sn = -d.y;
+            bx = au1 - (cs * av1 - sn * av2);
+            by = au2 - (sn * av1 + cs * av2);
+        }
+        // lane c takes candidate c's residual
+        float sc = 0.f;
+#pragma unroll 1
+        for (int c = 0; c < KMAX; ++c) {
+            if (c >= top_k) break;
+            const int l = __builtin_amdgcn_readlane(lmine, c);
+            const float *src = lds + (l & 3) * COPY + jr * N + 4 * ((p - (l >> 2)) & (CPR - 1));
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+            // reads run PIPE row steps ahead of the arithmetic
+            constexpr int PIPE = STEPS < 4 ? STEPS : 4;
+            float4 ub[STEPS];
 #pragma unroll
-        for (int gi = 0; gi < 2; ++gi) {
-            const int64_t g = g0 + gi;
-            if (g >= n_img) continue;  // wave-uniform
-            const int64_t p = r * n_img + g;
-            float best = 0.f;
-            int bl = 0;
-            double bxb = 0.0, byb = 0.0;
-            const double *av = img_aux + 4 * g;
-            for (int c = 0; c < top_k; ++c) {
-                const int l = cand[p * top_k + c];
-                // element (j, k) of V pairs with U[j][k - l]
-                const float *u2 = U2 + base - l;
-                float acc = 0.f;
+            for (int m = 0; m < PIPE; ++m) ub[m] = *(const float4 *)(src + m * RPS * N);
 #pragma unroll
-                for (int m = 0; m < EPT; ++m) {
-                    const float e = u2[m * RS * 2 * N] - vv[gi][m];
-                    acc = fmaf(e, e, acc);
-                }
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-                double bx = 0.0, by = 0.0;
-                if (mode == 0) {
-                    const double2 d = tw64[l];
-                    const double cs = d.x, sn = -d.y;
-                    bx = au[2] - (cs * av[2] - sn * av[3]);
-                    by = au[3] - (sn * av[2] + cs * av[3]);
-                }
-                const float D = (float)((double)acc / nq - 2.0 * (bx * bx + by * by));
-                if (c == 0 || D < best || (D == best && l < bl)) {
-                    best = D;
-                    bl = l;
-                    bxb = bx;
-                    byb = by;
-                }
+            for (int m = 0; m < STEPS; ++m) {
+                if (m + PIPE < STEPS) ub[m + PIPE] = *(const float4 *)(src + (m + PIPE) * RPS * N);
+                __builtin_amdgcn_sched_barrier(0);
+                const float4 u = ub[m];
+                const float4 v = vv[m];
+                const float e0 = u.x - v.x, e1 = u.y - v.y, e2 = u.z - v.z, e3 = u.w - v.w;
+                a0 = fmaf(e0, e0, a0);
+                a1 = fmaf(e1, e1, a1);
+                a2 = fmaf(e2, e2, a2);
+                a3 = fmaf(e3, e3, a3);
+                __builtin_amdgcn_sched_barrier(0);
             }
-            if (lane == 0) {
-                int st = 0;
-                if (isnan(au[0]) || isnan(av[0])) st = 2;
-                else if (!(au[0] > 0.0) || !(av[0] > 0.0)) st = 1;
-                Result res;
-                res.status = st;
-                if (st) {
-                    res.rot_index = 0;
-                    res.theta_rad = 0.f;
-                    res.shift_px[0] = res.shift_px[1] = 0.f;
-                    res.sw2sq = __int_as_float(0x7fc00000);
-                } else {
-                    res.rot_index = bl;
-                    res.theta_rad = (float)(6.283185307179586 * (double)bl / (double)N);
-                    res.shift_px[0] = (float)(bxb * (double)L);  // s* = 2b, in pixels s*/h
-                    res.shift_px[1] = (float)(byb * (double)L);
-                    res.sw2sq = best;
-                }
-                out[p] = res;
+            const float sum = wave_sum_f((a0 + a1) + (a2 + a3));
+            if (lane == c) sc = sum;
+        }
+        const float D = (float)((double)sc / nq - 2.0 * (bx * bx + by * by));
+        // smallest objective, ties to the smaller lag
+        int bc = 0;
+        float bd = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(D), 0));
+        int bl = __builtin_amdgcn_readlane(lmine, 0);
+#pragma unroll
+        for (int c = 1; c < KMAX; ++c) {
+            if (c >= top_k) break;
+            const float dc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(D), c));
+            const int lc = __builtin_amdgcn_readlane(lmine, c);
+            if (dc < bd || (dc == bd && lc < bl)) {
+                bd = dc;
+                bl = lc;
+                bc = c;
             }
+        }
+        if (lane == bc) {
+            int st = 0;
+            if (isnan(au0) || isnan(av0)) st = 2;
+            else if (!(au0 > 0.0) || !(av0 > 0.0)) st = 1;
+            Result res;
+            res.status = st;
+            if (st) {
+                res.rot_index = 0;
+                res.theta_rad = 0.f;
+                res.shift_px[0] = res.shift_px[1] = 0.f;
+                res.sw2sq = __int_as_float(0x7fc00000);
+            } else {
+                res.rot_index = bl;
+                res.theta_rad = (float)(6.283185307179586 * (double)bl / (double)N);
+                res.shift_px[0] = (float)(bx * (double)L);  // s* = 2b, in pixels s*/h
+                res.shift_px[1] = (float)(by * (double)L);
+                res.sw2sq = bd;
+            }
+            out[r * n_img + g] = res;
         }
     }
 }
@@ -266,14 +348,34 @@ static hipError_t launch_mfma_t(const MfmaArgs &a, Geo g, const AngleTable &t, h
                        a.n_ref, a.n_img, g.Q, a.mode, a.top_k, a.ref_aux, a.img_aux, t.d32, a.cand);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int gx = (int)((a.n_img + 7) / 8);
-    int gy = (1024 + gx - 1) / gx;  // about four blocks per CU in total
-    if (gy > a.n_ref) gy = (int)a.n_ref;
-    if (gy < 1) gy = 1;
-    const int TR = (int)((a.n_ref + gy - 1) / gy);
-    gy = (int)((a.n_ref + TR - 1) / TR);
-    const size_t lds2 = sizeof(float) * g.Q * 2 * N;
-    hipLaunchKernelGGL((k_rescore_tiles<N, KMAX>), dim3(gx, gy), dim3(256), lds2, s, a.ref_qt,
+    // blocks of eight images x TR references; TR chosen so that the grid
+    // fills the resident slots in as few, as full, rounds as possible
+    static const int slots = [] {
+        (void)hipFuncSetAttribute((const void *)k_rescore_tiles<N, KMAX>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 4 * N * N * 4);
+        int dev = 0, cus = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_rescore_tiles<N, KMAX>,
+                                                        512, sizeof(float) * 4 * N * N);
+        return (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
+    }();
+    const int64_t gx = (a.n_img + 7) / 8;
+    int64_t best_gy = 1;
+    double best_eff = -1.0;
+    for (int64_t gy = 1; gy <= a.n_ref && (gy == 1 || gx * gy <= 4 * (int64_t)slots); ++gy) {
+        const int64_t tr = (a.n_ref + gy - 1) / gy;
+        const int64_t rounds = (gx * gy + slots - 1) / slots;
+        const double eff = (double)(a.n_ref * gx) / ((double)rounds * slots * tr);
+        if (eff > best_eff * 1.01) {
+            best_eff = eff;
+            best_gy = gy;
+        }
+    }
+    const int TR = (int)((a.n_ref + best_gy - 1) / best_gy);
+    const int gy = (int)((a.n_ref + TR - 1) / TR);
+    const size_t lds2 = sizeof(float) * 4 * N * N;
+    hipLaunchKernelGGL((k_rescore_tiles<N, KMAX>), dim3((unsigned)gx, (unsigned)gy), dim3(512), lds2, s, a.ref_qt,
                        a.ref_aux, a.n_ref, a.img_qt, a.img_aux, a.n_img, TR, a.mode, a.top_k, g.L,
                        a.cand, t.d64, a.out);
     return hipGetLastError();
