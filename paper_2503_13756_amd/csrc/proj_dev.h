@@ -113,6 +113,9 @@ __device__ __forceinline__ int window_pos(int e, int rowoff) {
     return rowoff + 4 * (e + kStripPad);
 }
 
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(3))) f32x4v LdsF4;
+
 // Per-lane constants of one task (slot angle, bin).
 struct LaneTask {
     float c, r, A;
@@ -145,34 +148,41 @@ __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const LaneT
                                                  const float *lds, int i0, int rows,
                                                  float (&acc)[TPW][4], int my_tasks) {
     const int L = P.L;
-    const float hi = (float)L + 0.5f;
+    const float hi = (float)L + 2.5f;  // clamp bounds of u + 2
+    // LDS byte address of the strip buffer
+    const int lbase = (int)(uintptr_t)(const __attribute__((address_space(3))) float *)lds;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         if (t < my_tasks) {  // wave-uniform
             const LaneTask tk = tasks[t];
             const float omc = 1.f - tk.c, om2c = 1.f - 2.f * tk.c;
+            const float A2 = tk.A + 2.f;
             float s0 = acc[t][0], s1 = acc[t][1], s2 = acc[t][2], s3 = acc[t][3];
             float fi = (float)i0;  // row index, exact in FP32
 #pragma unroll 2
             for (int rr = 0; rr < rows; ++rr, fi += 1.f) {
-                float u = fmaf(fi, tk.r, tk.A);
-                u = __builtin_amdgcn_fmed3f(u, -1.5f, hi);
-                const float fr = __builtin_amdgcn_fractf(u);  // u - floor(u), exact
-                const int jA = (int)floorf(u);
+                // u + 2 > 0 once clamped, so truncation is the floor
+                float u2 = fmaf(fi, tk.r, A2);
+                u2 = __builtin_amdgcn_fmed3f(u2, 0.5f, hi);
+                const float fr = __builtin_amdgcn_fractf(u2);  // fractional part, exact
+                const int jA2 = (int)u2;                       // floor(u) + 2
                 const float cf = tk.c * fr;
                 const float w0 = __builtin_amdgcn_fmed3f(omc - cf, 0.f, 1.f);   // column jA - 1
                 const float w1 = 1.f - cf;                                       // column jA
                 const float w2 = omc + cf;                                       // column jA + 1
                 const float w3 = __builtin_amdgcn_fmed3f(om2c + cf, 0.f, 1.f);  // column jA + 2
-                // window jA-1 .. jA+2 of this row (and of the transposed
-                // column), and the mirrored window L-3-jA .. L-jA
-                const int rowoff = rr * P.RS;
-                const int pa = window_pos(jA - 1, rowoff);
-                const int pc = window_pos(L - 3 - jA, rowoff);
-                const float4 A = *(const float4 *)(lds + pa);
-                const float4 B = *(const float4 *)(lds + kKindFloats + pa);
-                const float4 C = *(const float4 *)(lds + pc);
-                const float4 D = *(const float4 *)(lds + kKindFloats + pc);
+                // LDS byte addresses of the window jA-1 .. jA+2 of this row
+                // (and of the transposed column) and of the mirrored window
+                // L-3-jA .. L-jA: one shift-add, and the mirror as one
+                // subtraction from the sum of the two row constants
+                const int ka = lbase + 4 * window_pos(-3, rr * P.RS);  // + 16 (jA + 2)
+                const int kc = lbase + 4 * window_pos(L - 1, rr * P.RS);
+                const int pa = (jA2 << 4) + ka;
+                const int pc = (ka + kc) - pa;  // kc - 16 (jA + 2)
+                const f32x4v A = *(const LdsF4 *)(uintptr_t)pa;
+                const f32x4v B = *(const LdsF4 *)(uintptr_t)(pa + 4 * kKindFloats);
+                const f32x4v C = *(const LdsF4 *)(uintptr_t)pc;
+                const f32x4v D = *(const LdsF4 *)(uintptr_t)(pc + 4 * kKindFloats);
                 s0 = fmaf(w3, A.w, fmaf(w2, A.z, fmaf(w1, A.y, fmaf(w0, A.x, s0))));
                 s1 = fmaf(w3, B.w, fmaf(w2, B.z, fmaf(w1, B.y, fmaf(w0, B.x, s1))));
                 s2 = fmaf(w3, C.x, fmaf(w2, C.y, fmaf(w1, C.z, fmaf(w0, C.w, s2))));
