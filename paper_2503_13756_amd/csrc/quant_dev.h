@@ -7,9 +7,9 @@
 // sums are accumulated in FP64 (lane-local sums, then a wave-wide DPP scan of
 // the lane totals), so each lane holds the normalised CDF at the right edges
 // of its own bins.  Levels are then assigned from the bins' side rather than
-// searched for: level z_j falls in bin b exactly when C[b] < z_j <= C[b+1]
-// (the first bin whose CDF reaches z_j), so a lane counts the levels at or
-// below each of its edges and interpolates the levels in between.  Quantiles
+// searched for: level z_j falls in the first bin whose right-edge CDF reaches
+// it, so a lane counts the levels at or below each of its edges and
+// interpolates the levels in between.  Quantiles
 // are gathered in an LDS tile [Q][TC] and written out as rows of the [Q][n]
 // table (angle fastest).  The per-image scalars (mass, E = sum of squares,
 // translation moment a) are reduced in FP64 on the way.
@@ -56,53 +56,54 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return read_lane_d(wave_inclusive_scan_d(v), 63);
 }
 
-// Quantile level z_j: midpoint (j + 1/2)/Q or left j/Q.
-__device__ __forceinline__ double level_z(int j, int levels, double invQ) {
-    return ((double)j + (levels ? 0.0 : 0.5)) * invQ;
+// Number of levels z_j <= c, for z_j = (j + 1/2)/Q (midpoint) or j/Q
+// (left): floor(c Q + 1/2) or floor(c Q) + 1, clamped to [0, Q].  Monotone
+// in c, so the counts at consecutive bin edges partition the levels; a level
+// that ties an edge to within rounding lands on either side of it, where the
+// interpolated quantile is the same edge value.
+__device__ __forceinline__ int levels_at_or_below(double c, int Q, double zshift) {
+    const int j = (int)fma(c, (double)Q, zshift);  // truncation = floor for c >= 0
+    return min(max(j, 0), Q);
 }
 
-// Number of levels z_j <= c (levels increase with j): an estimate from c Q,
-// corrected with the same comparisons that define the assignment.
-__device__ __forceinline__ int levels_at_or_below(double c, int Q, int levels, double invQ) {
-    double est = c * (double)Q - (levels ? 0.0 : 0.5);
-    est = est < -1.0 ? -1.0 : (est > (double)Q ? (double)Q : est);
-    int j = (int)floor(est) + 1;
-    j = j < 0 ? 0 : (j > Q ? Q : j);
-    if (j > 0 && level_z(j - 1, levels, invQ) > c) --j;
-    if (j < Q && level_z(j, levels, invQ) <= c) ++j;
-    return j;
+// h / den for den > 0: hardware reciprocal and two Newton steps (FP64).
+__device__ __forceinline__ double div_by(double h, double den) {
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    return h * r;
 }
 
-// Invert one column.  `col` reads bin b of the column (FP32).  Writes the
-// quantile of every level j into Ut[j * ldt + kl] and returns the lane's
-// partial (sum of quantiles, sum of squares) in *su, *sq, and the column
-// mass (same value on all lanes).
-template <typename ColFn>
-__device__ double invert_column(ColFn col, int L, int Q, int levels, float *Ut, int ldt, int kl,
-                                int lane, double *su, double *sq) {
-    const int m = (L + 63) >> 6;  // bins per lane, <= 4
-    double v[4];
+// Invert one column, M bins per lane (M = ceil(L / 64)).  `col` reads bin b
+// of the column (FP32).  Writes the quantile of every level j into
+// Ut[j * ldt + kl] and returns the lane's partial (sum of quantiles, sum of
+// squares) in *su, *sq, and the column mass (same value on all lanes).
+template <int M, typename ColFn>
+__device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut, int ldt, int kl,
+                                  int lane, double *su, double *sq) {
+    double v[M];
     double run = 0.0;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int b = lane * m + t;
+    for (int t = 0; t < M; ++t) {
+        const int b = lane * M + t;
         double x = 0.0;
-        if (t < m && b < L) x = (double)col(b);
+        if (b < L) x = (double)col(b);
         run += x;
         v[t] = run;  // lane-local inclusive sums
     }
     const double excl = wave_inclusive_scan_d(run) - run;
-    // mass = cumulative sum at the last bin, taken from the lane holding it,
-    // so that the CDF at the right edge is exactly 1
-    const int last_lane = (L - 1) / m;
-    const int last_t = (L - 1) - last_lane * m;
+    // mass = cumulative sum at the last bin, taken from the lane holding it
+    const int last_lane = (L - 1) / M;
+    const int last_t = (L - 1) - last_lane * M;
     double lastv = v[0];
 #pragma unroll
-    for (int t = 1; t < 4; ++t)
+    for (int t = 1; t < M; ++t)
         if (t == last_t) lastv = v[t];
     const double mass = read_lane_d(excl + lastv, last_lane);
     const double h = 2.0 / (double)L;
     const double invQ = 1.0 / (double)Q;
+    const double z0 = levels ? 0.0 : 0.5 * invQ;       // z_j = j / Q + z0
+    const double zshift = levels ? 1.0 : 0.5;           // level count offset
     double s1 = 0.0, s2 = 0.0;
     if (!(mass > 0.0)) {
         // empty (or non-finite) column: the inverse of a zero CDF, as in the
@@ -115,35 +116,38 @@ __device__ double invert_column(ColFn col, int L, int Q, int levels, float *Ut, 
             s2 += (double)uf * (double)uf;
         }
     } else {
-        double c[4];
+        const double invm = 1.0 / mass;
+        double c[M];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) c[t] = (excl + v[t]) / mass;  // C at the right edge of bin
-        double cm = c[0];
+        for (int t = 0; t < M; ++t) c[t] = (excl + v[t]) * invm;  // C at the right edge of bin
+        // the CDF reaches exactly 1 at the right edge of the last bin
 #pragma unroll
-        for (int t = 1; t < 4; ++t)
-            if (t == m - 1) cm = c[t];
+        for (int t = 0; t < M; ++t)
+            if (lane * M + t == L - 1) c[t] = 1.0;
         // C at the left edge of this lane's first bin: the previous lane's
         // last right edge (0 on lane 0)
+        const double cm = c[M - 1];
         const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(cm), 0x138, 0xf, 0xf, false);
         const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(cm), 0x138, 0xf, 0xf, false);
         double cl = __hiloint2double(hi, lo);  // wave_shr:1
-        int jl = lane == 0 ? 0 : levels_at_or_below(cl, Q, levels, invQ);
+        int jl = lane == 0 ? 0 : levels_at_or_below(cl, Q, zshift);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int b = lane * m + t;
-            if (t < m && b < L) {
+        for (int t = 0; t < M; ++t) {
+            const int b = lane * M + t;
+            if (b < L) {
                 const double cr = c[t];
-                const int jr = levels_at_or_below(cr, Q, levels, invQ);
-                const double tl = -1.0 + (double)b * h, tr = -1.0 + (double)(b + 1) * h;
+                const int jr = levels_at_or_below(cr, Q, zshift);
+                const double tl = fma((double)b, h, -1.0), tr = tl + h;
                 const double den = cr - cl;
-                const double slope = den > 0.0 ? h / den : 0.0;
+                const double slope = den > 0.0 ? div_by(h, den) : 0.0;
                 for (int j = jl; j < jr; ++j) {
-                    double u = tl + (level_z(j, levels, invQ) - cl) * slope;
+                    const double z = fma((double)j, invQ, z0);
+                    double u = fma(z - cl, slope, tl);
                     u = u < tl ? tl : (u > tr ? tr : u);
                     const float uf = (float)u;
                     Ut[j * ldt + kl] = uf;
                     s1 += (double)uf;
-                    s2 += (double)uf * (double)uf;
+                    s2 = fma((double)uf, (double)uf, s2);
                 }
                 cl = cr;
                 jl = jr;
@@ -154,6 +158,17 @@ __device__ double invert_column(ColFn col, int L, int Q, int levels, float *Ut, 
     *sq = s2;
     __builtin_amdgcn_wave_barrier();
     return mass;
+}
+
+template <typename ColFn>
+__device__ __forceinline__ double invert_column(ColFn col, int L, int Q, int levels, float *Ut,
+                                                int ldt, int kl, int lane, double *su,
+                                                double *sq) {
+    const int m = (L + 63) >> 6;  // bins per lane, <= 4 (wave-uniform)
+    if (m == 1) return invert_column_m<1>(col, L, Q, levels, Ut, ldt, kl, lane, su, sq);
+    if (m == 2) return invert_column_m<2>(col, L, Q, levels, Ut, ldt, kl, lane, su, sq);
+    if (m == 3) return invert_column_m<3>(col, L, Q, levels, Ut, ldt, kl, lane, su, sq);
+    return invert_column_m<4>(col, L, Q, levels, Ut, ldt, kl, lane, su, sq);
 }
 
 // The whole CDF/quantile phase of one image, shared by the stand-alone,
