@@ -33,6 +33,7 @@ struct Ctx {
     int cu_count = 256;
     std::mutex mu;
     std::map<int, sw::AngleTable> tables;
+    std::map<int, sw::ProjPlan> plans;  // key L * 4096 + n
     std::map<int, int> tile_R;  // projection strip rows per L (autotuner)
     // batches of fewer images take the split (many blocks per image) launches;
     // -1: the number of compute units
@@ -61,6 +62,7 @@ struct DeviceGuard {
 
 sw_status check_geom(const sw_geom *g, sw::Geo *out);
 sw_status get_table(Ctx *ctx, int n, const sw::AngleTable **out);
+sw_status get_plan(Ctx *ctx, int L, int n, const sw::ProjPlan **out);
 void stop_server(Ctx *c);
 
 }  // namespace swh

@@ -39,7 +39,7 @@ __device__ __forceinline__ int64_t next_work(unsigned long long *counter, int64_
 // PMF slot of slot_floats per block, used by images whose PMF table does not
 // fit in LDS.
 template <int NT, int TPW>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256 ? 2 : 4))) void k_tables_mixed(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWaves<NT, TPW>, NT <= 256 ? 2 : 4))) void k_tables_mixed(
     const MixGroup *__restrict__ G, unsigned long long *counter, float *scratch,
     int64_t slot_floats, int region_floats, int /*lmax*/, int nmax) {
     constexpr int NW = NT / 64;
@@ -62,6 +62,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256
         P.R = it.R;
         P.slots = it.n / 8 + 1;
         P.items = P.slots * it.L;
+        P.ntasks = proj_ntasks(it.L, it.n);
+        P.perm = it.perm;
+        P.trow = it.trow;
         const int L = P.L, n = P.n, Q = it.Q;
         float *pmf = it.fused ? region : scratch + (int64_t)blockIdx.x * slot_floats;
         const float *F = it.img + gi * (int64_t)L * L;
@@ -188,8 +191,7 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
         if (R < 1) R = 1;
         if (R > NTT) R = NTT;
         it.R = R;
-        const int slots = it.n / 8 + 1;
-        const int ntasks = (slots * it.L + 63) / 64;
+        const int ntasks = proj_ntasks(it.L, it.n);
         const bool one_group = ntasks <= (NTT / 64) * TPW;
         const int strip = kStripFloats;
         const int pmf = it.n * it.L;

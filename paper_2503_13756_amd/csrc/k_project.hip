@@ -5,7 +5,7 @@
 namespace sw {
 
 template <int NT, int TPW>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256 ? 2 : 4))) void k_project(const float *__restrict__ img, int64_t N,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWaves<NT, TPW>, NT <= 256 ? 2 : 4))) void k_project(const float *__restrict__ img, int64_t N,
                                                 ProjShape P, const float2 *__restrict__ dtab,
                                                 float *__restrict__ pmf) {
     extern __shared__ __align__(16) float lds[];
@@ -53,13 +53,16 @@ static hipError_t launch_project_t(const float *img, int64_t N, const ProjShape 
     return hipGetLastError();
 }
 
-hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &t, float *pmf,
-                          hipStream_t s, bool split) {
+hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &t,
+                          const ProjPlan &pp, float *pmf, hipStream_t s, bool split) {
     if (N <= 0) return hipSuccess;
     ProjShape P = proj_shape(g.L, g.n);  // 64 KiB of strips: two blocks per CU
+    if (pp.L != g.L || pp.n != g.n || pp.ntasks != P.ntasks) return hipErrorInvalidValue;
+    P.perm = pp.perm;
+    P.trow = pp.trow;
     if (split) {
         constexpr int NT = 128;
-        const int groups = (P.items + 64 * (NT / 64) - 1) / (64 * (NT / 64));
+        const int groups = (P.ntasks + NT / 64 - 1) / (NT / 64);
         const size_t lds = sizeof(float) * kStripFloats;
         static const hipError_t attr = hipFuncSetAttribute(
             (const void *)k_project_split<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -69,12 +72,12 @@ hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &
                            lds, s, img, N, P, t.d32, pmf);
         return hipGetLastError();
     }
-    const int w512 = tasks_per_wave(P.items, 512);
+    const int w512 = tasks_per_wave(P.ntasks, 512);
     if (w512 <= 2) return launch_project_t<512, 2>(img, N, P, t.d32, pmf, s);
     if (w512 <= 4) return launch_project_t<512, 4>(img, N, P, t.d32, pmf, s);
     if (w512 <= 6) return launch_project_t<512, 6>(img, N, P, t.d32, pmf, s);
     if (w512 <= 9) return launch_project_t<512, 9>(img, N, P, t.d32, pmf, s);
-    const int w1024 = tasks_per_wave(P.items, 1024);
+    const int w1024 = tasks_per_wave(P.ntasks, 1024);
     if (w1024 <= 9) return launch_project_t<1024, 9>(img, N, P, t.d32, pmf, s);
     if (w1024 <= 12) return launch_project_t<1024, 12>(img, N, P, t.d32, pmf, s);
     // larger task counts run in several task groups

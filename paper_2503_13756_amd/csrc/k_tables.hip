@@ -16,7 +16,7 @@ struct TablesShape {
 };
 
 template <int NT, int TPW>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, NT <= 256 ? 2 : 4))) void k_tables(const float *__restrict__ img, int64_t N,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWaves<NT, TPW>, NT <= 256 ? 2 : 4))) void k_tables(const float *__restrict__ img, int64_t N,
                                                TablesShape T, const float2 *__restrict__ d32,
                                                const double2 *__restrict__ d64,
                                                float *__restrict__ qt, double *__restrict__ aux) {
@@ -47,7 +47,7 @@ size_t tables_lds_bytes(Geo g, int nt, TablesShape *out) {
     T.Q = g.Q;
     T.levels = g.levels;
     // all tasks in one group: the PMF table is written over the strip buffers
-    if (tasks_per_wave(T.P.items, nt) > (nt >= 512 ? 9 : 20)) return 0;
+    if (tasks_per_wave(T.P.ntasks, nt) > (nt >= 512 ? 9 : 20)) return 0;
     int region = kStripFloats;
     if (region < g.n * g.L) region = g.n * g.L;
     region = (region + 1) & ~1;
@@ -75,13 +75,17 @@ static hipError_t launch_tables_t(const float *img, int64_t N, const TablesShape
     return hipGetLastError();
 }
 
-hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t, float *qt,
-                         double *aux, hipStream_t s) {
+hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t,
+                         const ProjPlan &pp, float *qt, double *aux, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     TablesShape T;
     size_t lds = tables_lds_bytes(g, 512, &T);
+    if (pp.L != g.L || pp.n != g.n || pp.ntasks != proj_ntasks(g.L, g.n))
+        return hipErrorInvalidValue;
+    T.P.perm = pp.perm;
+    T.P.trow = pp.trow;
     if (lds != 0 && lds <= 79 * 1024) {
-        const int w = tasks_per_wave(T.P.items, 512);
+        const int w = tasks_per_wave(T.P.ntasks, 512);
         if (w <= 2) return launch_tables_t<512, 2>(img, N, T, lds, t, qt, aux, s);
         if (w <= 4) return launch_tables_t<512, 4>(img, N, T, lds, t, qt, aux, s);
         if (w <= 6) return launch_tables_t<512, 6>(img, N, T, lds, t, qt, aux, s);
@@ -89,7 +93,9 @@ hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t
     }
     lds = tables_lds_bytes(g, 256, &T);
     if (lds == 0) return hipErrorInvalidValue;  // caller checks tables_fused_fits first
-    const int tpw = tasks_per_wave(T.P.items, 256);
+    T.P.perm = pp.perm;
+    T.P.trow = pp.trow;
+    const int tpw = tasks_per_wave(T.P.ntasks, 256);
     if (tpw <= 4) return launch_tables_t<256, 4>(img, N, T, lds, t, qt, aux, s);
     if (tpw <= 8) return launch_tables_t<256, 8>(img, N, T, lds, t, qt, aux, s);
     if (tpw <= 12) return launch_tables_t<256, 12>(img, N, T, lds, t, qt, aux, s);

@@ -6,9 +6,9 @@
 // of one "slot" angle theta in [0, pi/4] and walks the image rows.  In row i
 // the line of bin b crosses the row at column u = (b - c0 + s (i - c0))/c + c0
 // (c = cos theta >= s = sin theta), and the pixels with non-zero weight are
-// the four columns floor(u) - 1 .. floor(u) + 2 (at most three of them are
-// non-zero because the pixel spacing along the detector is c >= 1/sqrt 2
-// bins).  The four hat weights are shared by four angles of the same orbit
+// at most three consecutive columns (the hat has half-width 1/c <= sqrt 2
+// columns, because the pixel spacing along the detector is c >= 1/sqrt 2
+// bins).  The three hat weights are shared by four angles of the same orbit
 // under the symmetries of the square pixel grid:
 //   theta        : F[i][j]            -> bin b
 //   pi/2 - theta : F[j][i]            -> bin L-1-b
@@ -36,6 +36,9 @@ __device__ __forceinline__ bool in_disk(int L, int i, int j) {
 
 struct ProjShape {
     int L, n, S, RS, R, slots, items;  // S chunks, RS floats per strip row
+    int ntasks;                        // tasks of 64 lanes (proj_ntasks)
+    const int *perm;                   // work order (ProjPlan)
+    const int2 *trow;
 };
 
 // R: requested strip rows (0: as many as fit).
@@ -49,6 +52,9 @@ __host__ inline ProjShape proj_shape(int L, int n, int R = 0) {
     p.R = (R > 0 && R < rmax) ? R : rmax;
     p.slots = n / 8 + 1;
     p.items = p.slots * L;
+    p.ntasks = proj_ntasks(L, n);
+    p.perm = nullptr;
+    p.trow = nullptr;
     return p;
 }
 
@@ -116,26 +122,47 @@ __device__ __forceinline__ int window_pos(int e, int rowoff) {
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(3))) f32x4v LdsF4;
 
-// Per-lane constants of one task (slot angle, bin).
+// Per-lane constants of one task (slot angle, bin): c = cos theta, the
+// column step r = tan theta per row, A3 = u(0) - 1/c + 3 (u(i) = A3' + i r is
+// the column where the line of bin b crosses row i) and k1 = 2 - 1/c; A3 and
+// k1 are rounded once from FP64.
 struct LaneTask {
-    float c, r, A;
+    float c, r, A3, k1;
+    int rlo, rhi;  // rows the task reads (wave-uniform)
 };
 
-__device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *dtab, int item) {
+// Item of lane `lane` of task `task` in the work order, or -1.
+__device__ __forceinline__ int task_item(const ProjShape &P, int task, int lane) {
+    return task < P.ntasks ? P.perm[task * 64 + lane] : -1;
+}
+
+__device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *dtab, int task,
+                                              int lane) {
     LaneTask t;
-    if (item < P.items) {
+    const int item = task_item(P, task, lane);
+    if (task < P.ntasks) {
+        const int2 rr = P.trow[task];
+        t.rlo = __builtin_amdgcn_readfirstlane(rr.x);
+        t.rhi = __builtin_amdgcn_readfirstlane(rr.y);
+    } else {
+        t.rlo = 1;
+        t.rhi = 0;
+    }
+    if (item >= 0) {
         const int slot = item / P.L, b = item - slot * P.L;
         const float2 d = dtab[slot];
         const float c = d.x, s = -d.y;
-        const float c0 = 0.5f * (float)(P.L - 1);
+        const double c0 = 0.5 * (double)(P.L - 1);
         t.c = c;
         t.r = s / c;
-        // u(i) = A + i * r
-        t.A = ((float)b - c0) / c + c0 - c0 * t.r;
+        const double ic = 1.0 / (double)c;
+        t.A3 = (float)(((double)b - c0 - 1.0) * ic + c0 + 3.0 - c0 * (double)t.r);
+        t.k1 = (float)(2.0 - ic);
     } else {
         t.c = 1.f;
         t.r = 0.f;
-        t.A = -100.f;  // clamps to the zero padding
+        t.A3 = -100.f;  // clamps to the zero padding
+        t.k1 = 1.f;
     }
     return t;
 }
@@ -148,45 +175,52 @@ __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const LaneT
                                                  const float *lds, int i0, int rows,
                                                  float (&acc)[TPW][4], int my_tasks) {
     const int L = P.L;
-    const float hi = (float)L + 2.5f;  // clamp bounds of u + 2
+    const float hi3 = (float)L + 2.f;
     // LDS byte address of the strip buffer
     const int lbase = (int)(uintptr_t)(const __attribute__((address_space(3))) float *)lds;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         if (t < my_tasks) {  // wave-uniform
             const LaneTask tk = tasks[t];
-            const float omc = 1.f - tk.c, om2c = 1.f - 2.f * tk.c;
-            const float A2 = tk.A + 2.f;
+            // The hat of half-width 1/c (in columns) around u covers at most
+            // three columns, j0 = floor(u - 1/c) + 1 .. j0 + 2.  With
+            // f = frac(u - 1/c) their weights are
+            //   c (1 - f),   1 - c |2 - 1/c - f|,   max(0, 2 - 3c + c f)
+            // (c = cos theta in [1/sqrt 2, 1]).  u - 1/c is carried shifted by
+            // 3 and clamped to [0.5, L + 2], so that truncation is the floor
+            // and j0 stays in [-2, L]: a line clamped there has its whole hat
+            // on columns <= 0 or >= L - 1, outside the disk, and so does the
+            // clamped position.
+            const float k1 = tk.k1, k2 = 2.f - 3.f * tk.c;
             float s0 = acc[t][0], s1 = acc[t][1], s2 = acc[t][2], s3 = acc[t][3];
-            float fi = (float)i0;  // row index, exact in FP32
+            // only the rows of this strip that the task's lines cross
+            const int ra = max(tk.rlo - i0, 0), rb = min(tk.rhi - i0 + 1, rows);
+            float fi = (float)(i0 + ra);  // row index, exact in FP32
 #pragma unroll 2
-            for (int rr = 0; rr < rows; ++rr, fi += 1.f) {
-                // u + 2 > 0 once clamped, so truncation is the floor
-                float u2 = fmaf(fi, tk.r, A2);
-                u2 = __builtin_amdgcn_fmed3f(u2, 0.5f, hi);
-                const float fr = __builtin_amdgcn_fractf(u2);  // fractional part, exact
-                const int jA2 = (int)u2;                       // floor(u) + 2
-                const float cf = tk.c * fr;
-                const float w0 = __builtin_amdgcn_fmed3f(omc - cf, 0.f, 1.f);   // column jA - 1
-                const float w1 = 1.f - cf;                                       // column jA
-                const float w2 = omc + cf;                                       // column jA + 1
-                const float w3 = __builtin_amdgcn_fmed3f(om2c + cf, 0.f, 1.f);  // column jA + 2
-                // LDS byte addresses of the window jA-1 .. jA+2 of this row
-                // (and of the transposed column) and of the mirrored window
-                // L-3-jA .. L-jA: one shift-add, and the mirror as one
+            for (int rr = ra; rr < rb; ++rr, fi += 1.f) {
+                float um = fmaf(fi, tk.r, tk.A3);
+                um = __builtin_amdgcn_fmed3f(um, 0.5f, hi3);
+                const float fr = __builtin_amdgcn_fractf(um);  // fractional part, exact
+                const int j2 = (int)um;                        // j0 + 2
+                const float w0 = fmaf(-tk.c, fr, tk.c);                                // column j0
+                const float w1 = fmaf(-tk.c, fabsf(k1 - fr), 1.f);                      // j0 + 1
+                const float w2 = __builtin_amdgcn_fmed3f(fmaf(tk.c, fr, k2), 0.f, 1.f);  // j0 + 2
+                // LDS byte addresses of the window j0 .. j0+3 of this row (and
+                // of the transposed column) and of the mirrored window
+                // L-3-j0 .. L-j0: one shift-add, and the mirror as one
                 // subtraction from the sum of the two row constants
-                const int ka = lbase + 4 * window_pos(-3, rr * P.RS);  // + 16 (jA + 2)
+                const int ka = lbase + 4 * window_pos(-2, rr * P.RS);  // + 16 j2
                 const int kc = lbase + 4 * window_pos(L - 1, rr * P.RS);
-                const int pa = (jA2 << 4) + ka;
-                const int pc = (ka + kc) - pa;  // kc - 16 (jA + 2)
+                const int pa = (j2 << 4) + ka;
+                const int pc = (ka + kc) - pa;  // kc - 16 j2
                 const f32x4v A = *(const LdsF4 *)(uintptr_t)pa;
                 const f32x4v B = *(const LdsF4 *)(uintptr_t)(pa + 4 * kKindFloats);
                 const f32x4v C = *(const LdsF4 *)(uintptr_t)pc;
                 const f32x4v D = *(const LdsF4 *)(uintptr_t)(pc + 4 * kKindFloats);
-                s0 = fmaf(w3, A.w, fmaf(w2, A.z, fmaf(w1, A.y, fmaf(w0, A.x, s0))));
-                s1 = fmaf(w3, B.w, fmaf(w2, B.z, fmaf(w1, B.y, fmaf(w0, B.x, s1))));
-                s2 = fmaf(w3, C.x, fmaf(w2, C.y, fmaf(w1, C.z, fmaf(w0, C.w, s2))));
-                s3 = fmaf(w3, D.x, fmaf(w2, D.y, fmaf(w1, D.z, fmaf(w0, D.w, s3))));
+                s0 = fmaf(w2, A.z, fmaf(w1, A.y, fmaf(w0, A.x, s0)));
+                s1 = fmaf(w2, B.z, fmaf(w1, B.y, fmaf(w0, B.x, s1)));
+                s2 = fmaf(w2, C.x, fmaf(w1, C.y, fmaf(w0, C.z, s2)));
+                s3 = fmaf(w2, D.x, fmaf(w1, D.y, fmaf(w0, D.z, s3)));
             }
             acc[t][0] = s0;
             acc[t][1] = s1;
@@ -205,8 +239,8 @@ __device__ __forceinline__ void emit_outputs(const ProjShape &P, int tg0, int wa
     const int L = P.L, n = P.n, q = n / 4, h = n / 2, o = n / 8;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-        const int item = (tg0 + wave + t * nwaves) * 64 + lane;
-        if (item >= P.items) continue;
+        const int item = task_item(P, tg0 + wave + t * nwaves, lane);
+        if (item < 0) continue;
         const int k = item / L, b = item - k * L;
         // variant 0: angle k, bin b
         emit(k, b, acc[t][0]);
@@ -238,13 +272,12 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
     float acc[TPW][4];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0.f;
-    const int ntasks = (P.items + 63) / 64;
-    const int mine = ntasks - tg0 - wave;
+    const int mine = P.ntasks - tg0 - wave;
     const int my_tasks = mine > 0 ? min(TPW, (mine + NW - 1) / NW) : 0;
     // per-lane constants of this wave's tasks, set up once for all strips
     LaneTask tasks[TPW];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) tasks[t] = make_task(P, dtab, (tg0 + wave + t * NW) * 64 + lane);
+    for (int t = 0; t < TPW; ++t) tasks[t] = make_task(P, dtab, tg0 + wave + t * NW, lane);
     int bad = 0;
     for (int i0 = 0; i0 < P.L; i0 += P.R) {
         const int rows = min(P.R, P.L - i0);
@@ -265,20 +298,24 @@ __device__ void project_image(const float *__restrict__ F, const ProjShape &P,
                               const float2 *__restrict__ dtab, float *lds, int &bad_out,
                               Emit emit) {
     constexpr int NW = NT / 64;
-    const int ntasks = (P.items + 63) / 64;
     bad_out = 0;
-    for (int tg0 = 0; tg0 < ntasks; tg0 += NW * TPW) {
+    for (int tg0 = 0; tg0 < P.ntasks; tg0 += NW * TPW) {
         int bad = 0;
         project_group<NT, TPW>(F, P, dtab, lds, tg0, bad, emit);
         bad_out |= bad;
     }
 }
 
-// Tasks (64 consecutive work items) per wave for a block of nt threads.
-inline int tasks_per_wave(int items, int nt) {
-    const int tasks = (items + 63) / 64;
+// Waves per SIMD that a projection kernel of NT threads and TPW tasks per
+// wave is compiled for: two 512-thread blocks per compute unit (128 VGPRs)
+// while the accumulators and task constants of TPW <= 6 fit.
+template <int NT, int TPW>
+constexpr int kProjMinWaves = (NT == 512 && TPW <= 6) ? 4 : 1;
+
+// Tasks per wave for a block of nt threads.
+inline int tasks_per_wave(int ntasks, int nt) {
     const int nw = nt / 64;
-    return (tasks + nw - 1) / nw;
+    return (ntasks + nw - 1) / nw;
 }
 
 }  // namespace sw

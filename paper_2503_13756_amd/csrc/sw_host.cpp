@@ -126,6 +126,102 @@ sw_status get_table(Ctx *ctx, int n, const sw::AngleTable **out) {
     return SW_OK;
 }
 
+// Work order of the projection for (L, n): every (slot, bin) item gets the
+// range of image rows where a pixel inside the disk has non-zero weight for
+// its line (pixel (i, j) weighs 1 - c |j - u(i)| with u(i) the column where
+// the line crosses row i; a small margin keeps the range conservative under
+// FP32 rounding).  Units of 16 consecutive bins of one slot take the union of
+// their items' ranges, units are ordered by the centre of their range, and
+// each run of four forms a task.  Rows outside a task's range only ever add
+// zeros, so skipping them leaves every sum unchanged.
+static void build_plan(int L, int n, std::vector<int> &perm, std::vector<int2> &trow) {
+    std::vector<double> c, s;
+    angle_values(n, c, s);
+    const int slots = n / 8 + 1, upr = (L + 15) / 16, ntasks = sw::proj_ntasks(L, n);
+    const double c0 = 0.5 * (L - 1);
+    const int r = L - 2;
+    struct Unit {
+        int slot, b0, lo, hi;
+    };
+    std::vector<Unit> units;
+    for (int k = 0; k < slots; ++k) {
+        const double ck = c[k], sk = s[k], half = 1.0 / ck + 1e-3;
+        for (int u0 = 0; u0 < upr; ++u0) {
+            int lo = L, hi = -1;
+            for (int b = 16 * u0; b < std::min(L, 16 * u0 + 16); ++b) {
+                for (int i = 0; i < L; ++i) {
+                    if (i >= lo && i <= hi) continue;  // already in the unit's range
+                    const double u = (b - c0 + sk * (i - c0)) / ck + c0;
+                    const int ja = std::max(0, (int)std::floor(u - half));
+                    const int jb = std::min(L - 1, (int)std::ceil(u + half));
+                    const int bb = 2 * i - L + 1;
+                    for (int j = ja; j <= jb; ++j) {
+                        const int a = 2 * j - L + 1;
+                        if (a * a + bb * bb <= r * r && ck * std::fabs(j - u) < 1.0 + 1e-3) {
+                            lo = std::min(lo, i);
+                            hi = std::max(hi, i);
+                            break;
+                        }
+                    }
+                }
+            }
+            units.push_back(Unit{k, 16 * u0, lo, hi});
+        }
+    }
+    // units whose lines miss the disk first, then by the centre of the range
+    std::stable_sort(units.begin(), units.end(), [](const Unit &x, const Unit &y) {
+        const int kx = x.lo <= x.hi ? x.lo + x.hi : -1, ky = y.lo <= y.hi ? y.lo + y.hi : -1;
+        return kx < ky;
+    });
+    perm.assign((size_t)ntasks * 64, -1);
+    trow.assign(ntasks, make_int2(1, 0));
+    for (size_t q = 0; q < units.size(); ++q) {
+        const Unit &x = units[q];
+        const int t = (int)(q / 4), l0 = (int)(q % 4) * 16;
+        for (int l = 0; l < 16 && x.b0 + l < L; ++l) perm[(size_t)t * 64 + l0 + l] = x.slot * L + x.b0 + l;
+        if (x.lo <= x.hi) {
+            int2 &tr = trow[t];
+            if (tr.x > tr.y) tr = make_int2(x.lo, x.hi);
+            else tr = make_int2(std::min(tr.x, x.lo), std::max(tr.y, x.hi));
+        }
+    }
+}
+
+sw_status get_plan(Ctx *ctx, int L, int n, const sw::ProjPlan **out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int key = L * 4096 + n;
+    auto f = ctx->plans.find(key);
+    if (f != ctx->plans.end()) {
+        *out = &f->second;
+        return SW_OK;
+    }
+    std::vector<int> perm;
+    std::vector<int2> trow;
+    build_plan(L, n, perm, trow);
+    sw::ProjPlan p;
+    p.L = L;
+    p.n = n;
+    p.ntasks = (int)trow.size();
+    hipError_t e = hipMalloc(&p.perm, sizeof(int) * perm.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(projection plan)");
+    e = hipMalloc(&p.trow, sizeof(int2) * trow.size());
+    if (e != hipSuccess) {
+        (void)hipFree(p.perm);
+        return hip_fail(e, "hipMalloc(projection plan)");
+    }
+    e = hipMemcpy(p.perm, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p.trow, trow.data(), sizeof(int2) * trow.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p.perm);
+        (void)hipFree(p.trow);
+        return hip_fail(e, "hipMemcpy(projection plan)");
+    }
+    auto res = ctx->plans.emplace(key, p);
+    *out = &res.first->second;
+    return SW_OK;
+}
+
 sw_status get_scratch(Ctx *ctx, size_t bytes, hipStream_t stream, void **out) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (bytes > ctx->scratch_bytes) {
@@ -191,7 +287,11 @@ sw_status run_stack_chunk(Ctx *c, const sw_stack *const *st, int n, int mode, in
         sw::Geo geo{k.geom.L, k.geom.n_angles, k.geom.n_quantiles, k.geom.levels};
         const sw::AngleTable *t;
         if ((stt = get_table(c, geo.n, &t)) != SW_OK) return stt;
+        const sw::ProjPlan *pp;
+        if ((stt = get_plan(c, geo.L, geo.n, &pp)) != SW_OK) return stt;
         sw::MixItem a{};
+        a.perm = pp->perm;
+        a.trow = pp->trow;
         a.L = geo.L;
         a.n = geo.n;
         a.Q = geo.Q;
@@ -342,6 +442,10 @@ sw_status sw_ctx_destroy(void *ctx) {
             (void)hipFree(kv.second.d32);
             (void)hipFree(kv.second.d64);
         }
+        for (auto &kv : c->plans) {
+            (void)hipFree(kv.second.perm);
+            (void)hipFree(kv.second.trow);
+        }
         if (c->scratch) (void)hipFree(c->scratch);
         for (int i = 0; i < DescRing::kSlots; ++i)
             if (c->ring.ev[i]) (void)hipEventDestroy(c->ring.ev[i]);
@@ -365,7 +469,9 @@ sw_status sw_project(void *ctx, const float *img, int64_t N, const sw_geom *g, f
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
     const sw::AngleTable *t;
     if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
-    hipError_t e = sw::launch_project(img, N, geo, *t, pmf, (hipStream_t)stream,
+    const sw::ProjPlan *pp;
+    if ((st = get_plan(c, geo.L, geo.n, &pp)) != SW_OK) return st;
+    hipError_t e = sw::launch_project(img, N, geo, *t, *pp, pmf, (hipStream_t)stream,
                                       c->small(N));
     return e == hipSuccess ? SW_OK : hip_fail(e, "k_project launch");
 }
@@ -403,13 +509,15 @@ sw_status sw_tables(void *ctx, const float *img, int64_t N, const sw_geom *g, fl
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
     const sw::AngleTable *t;
     if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
+    const sw::ProjPlan *pp;
+    if ((st = get_plan(c, geo.L, geo.n, &pp)) != SW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     // Fewer images than compute units: one block per image would leave most
     // of the device idle, so project with one block per (image, task group)
     // and invert with 16 waves per image, through scratch.
     const bool small = c->small(N);
     if (!small && sw::tables_fused_fits(geo)) {
-        hipError_t e = sw::launch_tables(img, N, geo, *t, qt, aux, s);
+        hipError_t e = sw::launch_tables(img, N, geo, *t, *pp, qt, aux, s);
         return e == hipSuccess ? SW_OK : hip_fail(e, "k_tables launch");
     }
     // Otherwise the PMF table of one image does not fit in LDS: project and
@@ -422,7 +530,7 @@ sw_status sw_tables(void *ctx, const float *img, int64_t N, const sw_geom *g, fl
     if ((st = get_scratch(c, per * (size_t)chunk, s, &pmf)) != SW_OK) return st;
     for (int64_t i0 = 0; i0 < N; i0 += chunk) {
         const int64_t m = N - i0 < chunk ? N - i0 : chunk;
-        hipError_t e = sw::launch_project(img + i0 * (int64_t)geo.L * geo.L, m, geo, *t,
+        hipError_t e = sw::launch_project(img + i0 * (int64_t)geo.L * geo.L, m, geo, *t, *pp,
                                           (float *)pmf, s, small);
         if (e != hipSuccess) return hip_fail(e, "k_project launch");
         e = sw::launch_quantiles((const float *)pmf, m, geo, *t, qt + i0 * (int64_t)geo.Q * geo.n,

@@ -23,10 +23,28 @@ constexpr int kMaxTopK = 8;
 constexpr int kStripPad = 3;
 constexpr int kKindFloats = 8192;
 constexpr int kStripFloats = 2 * kKindFloats;  // 64 KiB
-// chunks per strip row: windows start at elements -3 .. L-1
-__host__ __device__ inline int strip_stride(int L) { return (L + kStripPad) | 1; }
+// chunks per strip row: windows start at elements -3 .. L
+__host__ __device__ inline int strip_stride(int L) { return (L + kStripPad + 1) | 1; }
 __host__ __device__ inline int strip_row_floats(int L) { return 4 * strip_stride(L); }
 __host__ __device__ inline int strip_rows_max(int L) { return kKindFloats / strip_row_floats(L); }
+
+// Projection work order of one geometry (L, n).  The projection's work
+// items are (slot angle, bin) pairs, item = slot * L + bin, in units of 16
+// consecutive bins of one slot (the last unit of a slot padded); a task is
+// four units, one item per lane, so that each 16-lane quarter of a wave
+// reads evenly spaced LDS windows.  perm lists the items of task t at
+// [64 t, 64 t + 64) (-1 for padding), units grouped so that the lines of a
+// task cross nearly the same image rows inside the disk, and trow[t] =
+// (first, last) is the range of rows where any of them has a pixel of
+// non-zero weight (first > last: none).  Device memory, owned by the context.
+__host__ __device__ inline int proj_ntasks(int L, int n) {
+    return ((n / 8 + 1) * ((L + 15) / 16) + 3) / 4;
+}
+struct ProjPlan {
+    int L = 0, n = 0, ntasks = 0;
+    int *perm = nullptr;   // [ntasks * 64]
+    int2 *trow = nullptr;  // [ntasks]
+};
 
 struct Geo {
     int L, n, Q, levels;
@@ -53,15 +71,15 @@ static_assert(sizeof(Result) == 24, "sw_result is 24 bytes");
 // ---- launchers (each returns hipGetLastError() after its launches) ----
 // split: one block per (image, task group), for batches too small to fill the
 // device with one block per image
-hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &t, float *pmf,
-                          hipStream_t s, bool split = false);
+hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &t,
+                          const ProjPlan &pp, float *pmf, hipStream_t s, bool split = false);
 hipError_t launch_quantiles(const float *pmf, int64_t N, Geo g, const AngleTable &t, float *qt,
                             double *aux, hipStream_t s, bool small = false);
 // Fused image -> quantile table; only for geometries where
 // tables_fused_fits() holds (the PMF table must fit in LDS).
 bool tables_fused_fits(Geo g);
-hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t, float *qt,
-                         double *aux, hipStream_t s);
+hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t,
+                         const ProjPlan &pp, float *qt, double *aux, hipStream_t s);
 // Angle spectra of quantile tables: spec[g][w][j] complex, w in [0, n/2],
 // j in [0, Q); bf16 != 0 stores bfloat16 pairs instead of float pairs.
 hipError_t launch_spectrum(const float *qt, int64_t N, Geo g, const AngleTable &t, void *spec,
@@ -123,6 +141,8 @@ struct MixItem {
     Result *out;        // [count]
     const float2 *d32;  // angle table of n
     const double2 *d64;
+    const int *perm;    // projection work order of (L, n)
+    const int2 *trow;
     int64_t first, count;  // work-index range
     int L, n, Q, levels;
     int R;      // projection strip rows (tile)

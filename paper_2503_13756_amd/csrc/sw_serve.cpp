@@ -300,6 +300,9 @@ hipError_t issue_step(Server *s, const std::vector<Req *> &rs, hipEvent_t done) 
     const sw::AngleTable *t;
     st = get_table(c, g.n, &t);
     if (st != SW_OK) return hipErrorUnknown;
+    const sw::ProjPlan *pp;
+    st = get_plan(c, g.L, g.n, &pp);
+    if (st != SW_OK) return hipErrorUnknown;
     std::vector<uint64_t> keys_done;
     // a step holds one geometry: all items take the same alignment kernel
     const bool fast = sw::align128_supported(g) && !c->generic_align;
@@ -314,6 +317,8 @@ hipError_t issue_step(Server *s, const std::vector<Req *> &rs, hipEvent_t done) 
         a.R = tr != c->tile_R.end() ? tr->second : 0;
         a.d32 = t->d32;
         a.d64 = t->d64;
+        a.perm = pp->perm;
+        a.trow = pp->trow;
         a.mode = s->cfg.mode;
         a.bf16 = s->cfg.prec == SW_PREC_BF16_SPLIT;
         a.top_k = s->cfg.top_k;
