@@ -52,7 +52,16 @@ def _load():
         lib.oracle_align.argtypes = [P, P, i64, P, P, i64, P, i64, i32, i32, i32, i32,
                                      P, P, P, P, P]
         lib.oracle_align.restype = None
-        lib.oracle_objective_at.argtypes = [P, P, i32, i32, i32, dbl, dbl]
+        lib.oracle_align_rows.argtypes = [P, P, i64, P, P, i64, P, i64, i32, i32, i32, i32, i32,
+                                          P, P, P, P, P]
+        lib.oracle_align_rows.restype = None
+        lib.oracle_ramp.argtypes = [P, i64, i32, i32, P]
+        lib.oracle_ramp.restype = None
+        lib.oracle_ramp_kernel.argtypes = [i32, P]
+        lib.oracle_ramp_kernel.restype = None
+        lib.oracle_quantiles_rf.argtypes = [P, i64, i32, i32, i32, i32, P, P, P]
+        lib.oracle_quantiles_rf.restype = None
+        lib.oracle_objective_at.argtypes = [P, P, i32, i32, i32, i32, dbl, dbl]
         lib.oracle_objective_at.restype = dbl
         lib.oracle_angle_table.argtypes = [i32, P, P]
         lib.oracle_angle_table.restype = None
@@ -105,19 +114,57 @@ def quantiles(pmf: np.ndarray, Q: int, levels: int = LEVELS_MIDPOINT, nonfinite=
     return qt, aux
 
 
-def tables(img: np.ndarray, n: int, Q: int, levels: int = LEVELS_MIDPOINT):
-    """Image stack -> (qt, aux): projection followed by quantiles."""
+def ramp_kernel(L: int):
+    """The ramp filter's cyclic kernel h[m], m < 2L (explicit cosine sum)."""
+    hk = np.zeros(2 * L, np.float64)
+    _load().oracle_ramp_kernel(L, _ptr(hk))
+    return hk
+
+
+def ramp(pmf: np.ndarray):
+    """Ramp-filtered projections: pmf [N, n, L] -> signed [N, n, L]."""
+    pmf = np.ascontiguousarray(pmf, dtype=np.float64)
+    if pmf.ndim == 2:
+        pmf = pmf[None]
+    N, n, L = pmf.shape
+    out = np.zeros_like(pmf)
+    _load().oracle_ramp(_ptr(pmf), N, L, n, _ptr(out))
+    return out
+
+
+def quantiles_rf(pf: np.ndarray, Q: int, levels: int = LEVELS_MIDPOINT, nonfinite=None):
+    """Signed filtered projections [N, n, L] -> stacked tables [N, 2Q, n]
+    (positive part, then negative part) and aux [N, 4] (smallest part mass,
+    E, Re a, Im a of the stacked table)."""
+    pf = np.ascontiguousarray(pf, dtype=np.float64)
+    if pf.ndim == 2:
+        pf = pf[None]
+    N, n, L = pf.shape
+    qt = np.zeros((N, 2 * Q, n), np.float64)
+    aux = np.zeros((N, 4), np.float64)
+    nf = None if nonfinite is None else np.ascontiguousarray(nonfinite, dtype=np.int32)
+    _load().oracle_quantiles_rf(_ptr(pf), N, L, n, Q, levels, _ptr(nf), _ptr(qt), _ptr(aux))
+    return qt, aux
+
+
+def tables(img: np.ndarray, n: int, Q: int, levels: int = LEVELS_MIDPOINT, ramp: bool = False):
+    """Image stack -> (qt, aux): projection followed by quantiles; with
+    ramp=True the projections are ramp-filtered and the stacked signed-part
+    tables [N, 2Q, n] are returned."""
     pmf, bad = project(img, n)
+    if ramp:
+        return quantiles_rf(globals()["ramp"](pmf), Q, levels, bad)
     return quantiles(pmf, Q, levels, bad)
 
 
 def align(ref_qt, ref_aux, img_qt, img_aux, L: int, pairs=None, mode: int = MODE_ROT_TRANS,
-          want_curve: bool = False):
+          want_curve: bool = False, ramp: bool = False):
     """Exhaustive rotation scan with the closed-form translation.
 
     Returns a dict with rot_index [P], shift_px [P, 2], sw2sq [P], status [P],
     and curve [P, n] when requested.  Pairs default to all ref x img in
-    row-major order."""
+    row-major order.  ramp=True: the tables are the stacked [2Q, n] tables of
+    the ramp-filtered distance, whose objective sums the two parts."""
     ref_qt = np.ascontiguousarray(ref_qt, dtype=np.float64)
     img_qt = np.ascontiguousarray(img_qt, dtype=np.float64)
     ref_aux = np.ascontiguousarray(ref_aux, dtype=np.float64)
@@ -126,7 +173,8 @@ def align(ref_qt, ref_aux, img_qt, img_aux, L: int, pairs=None, mode: int = MODE
         ref_qt, ref_aux = ref_qt[None], ref_aux[None]
     if img_qt.ndim == 2:
         img_qt, img_aux = img_qt[None], img_aux[None]
-    nr, Q, n = ref_qt.shape
+    nr, rows, n = ref_qt.shape
+    Q = rows // 2 if ramp else rows
     ni = img_qt.shape[0]
     if pairs is not None:
         pairs = np.ascontiguousarray(pairs, dtype=np.int64).reshape(-1, 2)
@@ -138,9 +186,9 @@ def align(ref_qt, ref_aux, img_qt, img_aux, L: int, pairs=None, mode: int = MODE
     out_d = np.zeros(P, np.float64)
     st = np.zeros(P, np.int32)
     curve = np.zeros((P, n), np.float64) if want_curve else None
-    _load().oracle_align(_ptr(ref_qt), _ptr(ref_aux), nr, _ptr(img_qt), _ptr(img_aux), ni,
-                         _ptr(pairs), P, L, n, Q, mode, _ptr(out_l), _ptr(out_s), _ptr(out_d),
-                         _ptr(st), _ptr(curve))
+    _load().oracle_align_rows(_ptr(ref_qt), _ptr(ref_aux), nr, _ptr(img_qt), _ptr(img_aux), ni,
+                              _ptr(pairs), P, L, n, Q, rows, mode, _ptr(out_l), _ptr(out_s),
+                              _ptr(out_d), _ptr(st), _ptr(curve))
     res = {"rot_index": out_l, "shift_px": out_s, "sw2sq": out_d, "status": st,
            "theta_rad": 2.0 * np.pi * out_l / n}
     if want_curve:
@@ -148,18 +196,20 @@ def align(ref_qt, ref_aux, img_qt, img_aux, L: int, pairs=None, mode: int = MODE
     return res
 
 
-def objective_at(U, V, l: int, sx: float, sy: float) -> float:
-    """D(l, s) for one pair of tables (s in unit-disk coordinates)."""
+def objective_at(U, V, l: int, sx: float, sy: float, ramp: bool = False) -> float:
+    """D(l, s) for one pair of tables (s in unit-disk coordinates); ramp=True
+    for stacked [2Q, n] tables (normalised by nQ)."""
     U = np.ascontiguousarray(U, dtype=np.float64)
     V = np.ascontiguousarray(V, dtype=np.float64)
-    Q, n = U.shape
-    return _load().oracle_objective_at(_ptr(U), _ptr(V), n, Q, l, sx, sy)
+    rows, n = U.shape
+    Q = rows // 2 if ramp else rows
+    return _load().oracle_objective_at(_ptr(U), _ptr(V), n, Q, rows, l, sx, sy)
 
 
 def align_images(ref_img, imgs, n: int, Q: int, levels: int = LEVELS_MIDPOINT,
-                 mode: int = MODE_ROT_TRANS, want_curve: bool = False):
+                 mode: int = MODE_ROT_TRANS, want_curve: bool = False, ramp: bool = False):
     """Whole path from images: one reference image against a stack."""
     L = imgs.shape[-1]
-    rq, ra = tables(ref_img, n, Q, levels)
-    iq, ia = tables(imgs, n, Q, levels)
-    return align(rq, ra, iq, ia, L, mode=mode, want_curve=want_curve)
+    rq, ra = tables(ref_img, n, Q, levels, ramp=ramp)
+    iq, ia = tables(imgs, n, Q, levels, ramp=ramp)
+    return align(rq, ra, iq, ia, L, mode=mode, want_curve=want_curve, ramp=ramp)

@@ -147,62 +147,173 @@ void oracle_project(const float *img, int64_t N, int L, int n, double *pmf, int3
    aux[g][1] = E = sum_{j,k} U[j][k]^2
    aux[g][2..3] = a = (1/n) sum_k ubar_k d_k, with ubar_k = (1/Q) sum_j U[j][k]
    pmf: [N][n][L], qt: [N][Q][n], aux: [N][4] (nullable). */
+/* Quantiles of one nonnegative column P[0..L) at the Q levels, written to
+   U[j * ldu] (j < Q); returns the column mass m.  C: L + 1 doubles of
+   scratch (C[b+1] holds the CDF at the right edge of bin b). */
+static double oracle_invert_column(const double *P, int L, int Q, int levels, double *U,
+                                   int64_t ldu, double *C)
+{
+    const double h = 2.0 / (double)L;
+    double m = 0.0;
+    for (int b = 0; b < L; ++b) m += P[b];
+    C[0] = 0.0;
+    double run = 0.0;
+    for (int b = 0; b < L; ++b) {
+        run += P[b];
+        C[b + 1] = (m > 0.0) ? run / m : 0.0;
+    }
+    for (int j = 0; j < Q; ++j) {
+        double z = (levels == 1) ? (double)j / (double)Q : ((double)j + 0.5) / (double)Q;
+        int bs = L - 1;
+        for (int b = 0; b < L; ++b)
+            if (C[b + 1] >= z) {
+                bs = b;
+                break;
+            }
+        double tl = -1.0 + (double)bs * h, tr = -1.0 + (double)(bs + 1) * h;
+        double den = C[bs + 1] - C[bs];
+        double u = (den > 0.0) ? tl + h * (z - C[bs]) / den : tl;
+        if (u < tl) u = tl;
+        if (u > tr) u = tr;
+        U[(int64_t)j * ldu] = u;
+    }
+    return m;
+}
+
+/* E = sum of squares of a [rows][n] table and a = (1/n) sum_k ubar_k d_k with
+   ubar_k the mean of column k over the rows. */
+static void oracle_table_scalars(const double *U, int rows, int n, const double *cs,
+                                 const double *sn, double *A)
+{
+    double E = 0.0, ar = 0.0, ai = 0.0;
+    for (int j = 0; j < rows; ++j)
+        for (int k = 0; k < n; ++k) E += U[(int64_t)j * n + k] * U[(int64_t)j * n + k];
+    for (int k = 0; k < n; ++k) {
+        double ub = 0.0;
+        for (int j = 0; j < rows; ++j) ub += U[(int64_t)j * n + k];
+        ub /= (double)rows;
+        ar += ub * cs[k];
+        ai += ub * (-sn[k]);
+    }
+    A[1] = E;
+    A[2] = ar / (double)n;
+    A[3] = ai / (double)n;
+}
+
 void oracle_quantiles(const double *pmf, int64_t N, int L, int n, int Q, int levels,
                       const int32_t *nonfinite, double *qt, double *aux)
 {
     double *cs = (double *)malloc(sizeof(double) * n);
     double *sn = (double *)malloc(sizeof(double) * n);
     oracle_angles(n, cs, sn);
-    const double h = 2.0 / (double)L;
 #pragma omp parallel for schedule(dynamic)
     for (int64_t g = 0; g < N; ++g) {
         const double *P = pmf + g * (int64_t)n * L;
         double *U = qt + g * (int64_t)Q * n;
-        double *C = (double *)malloc(sizeof(double) * (L + 1)); /* C[b+1] holds C[k][b] */
+        double *C = (double *)malloc(sizeof(double) * (L + 1));
         double mass0 = 0.0;
         for (int k = 0; k < n; ++k) {
-            double m = 0.0;
-            for (int b = 0; b < L; ++b) m += P[(int64_t)k * L + b];
+            double m = oracle_invert_column(P + (int64_t)k * L, L, Q, levels, U + k, n, C);
             if (k == 0) mass0 = m;
-            C[0] = 0.0;
-            double run = 0.0;
-            for (int b = 0; b < L; ++b) {
-                run += P[(int64_t)k * L + b];
-                C[b + 1] = (m > 0.0) ? run / m : 0.0;
-            }
-            for (int j = 0; j < Q; ++j) {
-                double z = (levels == 1) ? (double)j / (double)Q : ((double)j + 0.5) / (double)Q;
-                int bs = L - 1;
-                for (int b = 0; b < L; ++b)
-                    if (C[b + 1] >= z) {
-                        bs = b;
-                        break;
-                    }
-                double tl = -1.0 + (double)bs * h, tr = -1.0 + (double)(bs + 1) * h;
-                double den = C[bs + 1] - C[bs];
-                double u = (den > 0.0) ? tl + h * (z - C[bs]) / den : tl;
-                if (u < tl) u = tl;
-                if (u > tr) u = tr;
-                U[(int64_t)j * n + k] = u;
-            }
         }
         free(C);
         if (aux) {
-            double E = 0.0, ar = 0.0, ai = 0.0;
-            for (int j = 0; j < Q; ++j)
-                for (int k = 0; k < n; ++k) E += U[(int64_t)j * n + k] * U[(int64_t)j * n + k];
-            for (int k = 0; k < n; ++k) {
-                double ub = 0.0;
-                for (int j = 0; j < Q; ++j) ub += U[(int64_t)j * n + k];
-                ub /= (double)Q;
-                ar += ub * cs[k];
-                ai += ub * (-sn[k]);
-            }
             double *A = aux + 4 * g;
+            oracle_table_scalars(U, Q, n, cs, sn, A);
             A[0] = (nonfinite && nonfinite[g]) ? NAN : mass0;
-            A[1] = E;
-            A[2] = ar / (double)n;
-            A[3] = ai / (double)n;
+        }
+    }
+    free(cs);
+    free(sn);
+}
+
+/* Ramp filter (Sec. 2.2, optional high-pass step: the slice is multiplied by
+   |xi| in the Fourier domain before the inverse transform).  Discretised as
+   the filter |xi| sampled on the M = 2L point frequency grid of the detector
+   (DC term zero) and applied to each column zero-padded to length M, i.e. the
+   cyclic convolution with the kernel
+     h[m] = (1/M) sum_{w=0}^{M-1} min(w, M - w) cos(2 pi w m / M)
+   read on the L detector bins:
+     Pf[k][b] = sum_{b'} h[(b - b') mod M] P[k][b'].
+   Any positive scale of the filter drops out when each signed part is
+   normalised.  pmf, out: [N][n][L]. */
+void oracle_ramp(const double *pmf, int64_t N, int L, int n, double *out)
+{
+    const int M = 2 * L;
+    double *hk = (double *)malloc(sizeof(double) * M);
+    for (int m = 0; m < M; ++m) {
+        double acc = 0.0;
+        for (int w = 0; w < M; ++w) {
+            int a = w < M - w ? w : M - w;
+            acc += (double)a * cos(2.0 * OR_PI * (double)((int64_t)w * m % M) / (double)M);
+        }
+        hk[m] = acc / (double)M;
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t c = 0; c < N * (int64_t)n; ++c) {
+        const double *P = pmf + c * L;
+        double *R = out + c * L;
+        for (int b = 0; b < L; ++b) {
+            double acc = 0.0;
+            for (int bp = 0; bp < L; ++bp) acc += hk[((b - bp) % M + M) % M] * P[bp];
+            R[b] = acc;
+        }
+    }
+    free(hk);
+}
+
+/* The filter kernel itself, for tests against its closed form. */
+void oracle_ramp_kernel(int L, double *hk)
+{
+    const int M = 2 * L;
+    for (int m = 0; m < M; ++m) {
+        double acc = 0.0;
+        for (int w = 0; w < M; ++w) {
+            int a = w < M - w ? w : M - w;
+            acc += (double)a * cos(2.0 * OR_PI * (double)((int64_t)w * m % M) / (double)M);
+        }
+        hk[m] = acc / (double)M;
+    }
+}
+
+/* Quantile tables of ramp-filtered projections (ramp-filtered SW of Sec. 2.3
+   and its appendix): each filtered column is split into its positive part
+   max(Pf, 0) and its (absolute) negative part max(-Pf, 0), each part is
+   normalised to unit mass and inverted like a plain projection.  The two
+   tables are stacked: rows 0..Q-1 positive part, rows Q..2Q-1 negative part.
+   aux[g][0] = the smallest part mass over all columns (0 when a part is empty
+   somewhere; NaN for a non-finite image), aux[1..3] = E and a of the stacked
+   [2Q][n] table.  pf: [N][n][L], qt: [N][2Q][n]. */
+void oracle_quantiles_rf(const double *pf, int64_t N, int L, int n, int Q, int levels,
+                         const int32_t *nonfinite, double *qt, double *aux)
+{
+    double *cs = (double *)malloc(sizeof(double) * n);
+    double *sn = (double *)malloc(sizeof(double) * n);
+    oracle_angles(n, cs, sn);
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t g = 0; g < N; ++g) {
+        const double *P = pf + g * (int64_t)n * L;
+        double *U = qt + g * (int64_t)2 * Q * n;
+        double *C = (double *)malloc(sizeof(double) * (L + 1));
+        double *part = (double *)malloc(sizeof(double) * L);
+        double mmin = INFINITY;
+        for (int k = 0; k < n; ++k) {
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                for (int b = 0; b < L; ++b) {
+                    double v = P[(int64_t)k * L + b];
+                    part[b] = sgn == 0 ? (v > 0.0 ? v : 0.0) : (v < 0.0 ? -v : 0.0);
+                }
+                double m = oracle_invert_column(part, L, Q, levels, U + (int64_t)sgn * Q * n + k,
+                                                n, C);
+                if (m < mmin) mmin = m;
+            }
+        }
+        free(C);
+        free(part);
+        if (aux) {
+            double *A = aux + 4 * g;
+            oracle_table_scalars(U, 2 * Q, n, cs, sn, A);
+            A[0] = (nonfinite && nonfinite[g]) ? NAN : mmin;
         }
     }
     free(cs);
@@ -213,15 +324,17 @@ void oracle_quantiles(const double *pmf, int64_t N, int L, int n, int Q, int lev
    the discrete SW2 of Sec. 2.3 between f and T_s R_{theta_l} g: a cyclic
    column shift is a rotation (Sec. 2.3, fast computation over rotations) and
    a translation adds s.d_k to every quantile of column k (proof of Thm 3.2,
-   App. B). */
-static double oracle_objective(const double *U, const double *V, int n, int Q, int l,
+   App. B).  j runs over the `rows` rows of the tables: Q for SW2, 2Q for the
+   stacked tables of the ramp-filtered distance, whose objective is the sum
+   of the two parts' objectives (each normalised by nQ). */
+static double oracle_objective(const double *U, const double *V, int n, int Q, int rows, int l,
                                double sx, double sy, const double *cs, const double *sn)
 {
     double acc = 0.0;
     for (int k = 0; k < n; ++k) {
         int kl = (k + l) % n;
         double shift = sx * cs[k] + sy * (-sn[k]);
-        for (int j = 0; j < Q; ++j) {
+        for (int j = 0; j < rows; ++j) {
             double r = U[(int64_t)j * n + k] - V[(int64_t)j * n + kl] - shift;
             acc += r * r;
         }
@@ -237,15 +350,19 @@ static double oracle_objective(const double *U, const double *V, int n, int Q, i
      s*(l) = 2 b(l)       (minimiser of D(l, .), using sum_k d_k d_k^T = (n/2) I)
      D*(l) = D(l, s*(l))  (mode 0, rotation + translation)
      D*(l) = D(l, 0)      (mode 1, rotation only: the paper's own objective)
+   (With `rows` table rows and the 1/(nQ) normalisation,
+   D(l, s) = D(l, 0) - (2 rows/Q) s.b(l) + (rows/(2Q)) |s|^2, so s*(l) = 2 b(l)
+   for the stacked ramp-filtered tables as well.)
    l* = argmin D*(l), ties to the smallest l.
    Outputs per pair: out_l[p] = l*, out_s[p][2] = s*(l*) in pixels (x along
    +column, y along +row), out_d[p] = D*(l*), status[p], curve[p][n] = D*(.)
    (nullable).  pairs: [P][2] (ref index, img index) or NULL for all ref x img
    in row-major order (p = r * n_img + g). */
-void oracle_align(const double *ref_qt, const double *ref_aux, int64_t n_ref,
-                  const double *img_qt, const double *img_aux, int64_t n_img,
-                  const int64_t *pairs, int64_t n_pairs, int L, int n, int Q, int mode,
-                  int32_t *out_l, double *out_s, double *out_d, int32_t *status, double *curve)
+void oracle_align_rows(const double *ref_qt, const double *ref_aux, int64_t n_ref,
+                       const double *img_qt, const double *img_aux, int64_t n_img,
+                       const int64_t *pairs, int64_t n_pairs, int L, int n, int Q, int rows,
+                       int mode, int32_t *out_l, double *out_s, double *out_d, int32_t *status,
+                       double *curve)
 {
     double *cs = (double *)malloc(sizeof(double) * n);
     double *sn = (double *)malloc(sizeof(double) * n);
@@ -256,8 +373,8 @@ void oracle_align(const double *ref_qt, const double *ref_aux, int64_t n_ref,
     for (int64_t p = 0; p < P; ++p) {
         int64_t r = pairs ? pairs[2 * p] : p / n_img;
         int64_t g = pairs ? pairs[2 * p + 1] : p % n_img;
-        const double *U = ref_qt + r * (int64_t)Q * n;
-        const double *V = img_qt + g * (int64_t)Q * n;
+        const double *U = ref_qt + r * (int64_t)rows * n;
+        const double *V = img_qt + g * (int64_t)rows * n;
         double mr = ref_aux[4 * r], mg = img_aux[4 * g];
         int st = OR_STATUS_OK;
         if (isnan(mr) || isnan(mg)) st = OR_STATUS_NONFINITE;
@@ -275,12 +392,12 @@ void oracle_align(const double *ref_qt, const double *ref_aux, int64_t n_ref,
         double *vb = (double *)malloc(sizeof(double) * n);
         for (int k = 0; k < n; ++k) {
             double su = 0.0, sv = 0.0;
-            for (int j = 0; j < Q; ++j) {
+            for (int j = 0; j < rows; ++j) {
                 su += U[(int64_t)j * n + k];
                 sv += V[(int64_t)j * n + k];
             }
-            ub[k] = su / (double)Q;
-            vb[k] = sv / (double)Q;
+            ub[k] = su / (double)rows;
+            vb[k] = sv / (double)rows;
         }
         int best = -1;
         double bestd = 0.0, bsx = 0.0, bsy = 0.0;
@@ -296,7 +413,7 @@ void oracle_align(const double *ref_qt, const double *ref_aux, int64_t n_ref,
                 sx = 2.0 * bx / (double)n;
                 sy = 2.0 * by / (double)n;
             }
-            double d = oracle_objective(U, V, n, Q, l, sx, sy, cs, sn);
+            double d = oracle_objective(U, V, n, Q, rows, l, sx, sy, cs, sn);
             if (curve) curve[p * n + l] = d;
             if (best < 0 || d < bestd) {
                 best = l;
@@ -316,16 +433,25 @@ void oracle_align(const double *ref_qt, const double *ref_aux, int64_t n_ref,
     free(sn);
 }
 
+void oracle_align(const double *ref_qt, const double *ref_aux, int64_t n_ref,
+                  const double *img_qt, const double *img_aux, int64_t n_img,
+                  const int64_t *pairs, int64_t n_pairs, int L, int n, int Q, int mode,
+                  int32_t *out_l, double *out_s, double *out_d, int32_t *status, double *curve)
+{
+    oracle_align_rows(ref_qt, ref_aux, n_ref, img_qt, img_aux, n_img, pairs, n_pairs, L, n, Q, Q,
+                      mode, out_l, out_s, out_d, status, curve);
+}
+
 /* D(l, s) for one table pair at arbitrary (l, s), s in unit coordinates:
    exposed so that tests can minimise over s numerically and compare with the
    closed form above. */
-double oracle_objective_at(const double *U, const double *V, int n, int Q, int l, double sx,
-                           double sy)
+double oracle_objective_at(const double *U, const double *V, int n, int Q, int rows, int l,
+                           double sx, double sy)
 {
     double *cs = (double *)malloc(sizeof(double) * n);
     double *sn = (double *)malloc(sizeof(double) * n);
     oracle_angles(n, cs, sn);
-    double d = oracle_objective(U, V, n, Q, l, sx, sy, cs, sn);
+    double d = oracle_objective(U, V, n, Q, rows, l, sx, sy, cs, sn);
     free(cs);
     free(sn);
     return d;

@@ -374,3 +374,130 @@ def test_status_codes(oracle):
 def test_view_stability_constant():
     """The golden constant of Thm 3.1 at p = 2 is 1 - 4/(3 pi)."""
     assert abs(GOLD["view_stability_constant_p2"]["value"] - (1 - 4 / (3 * math.pi))) < 1e-9
+
+
+# ---------------------------------------------------------------- ramp-filtered SW2
+def test_ramp_kernel_closed_form(oracle):
+    """The |xi| filter sampled on M = 2L frequencies (DC zero) has the cyclic
+    kernel h[0] = M/4, h[m] = -1/(M sin^2(pi m / M)) for odd m and 0 for even
+    m != 0 (sum of a triangle wave's cosine series).  Catches a wrong frequency
+    grid (|w| over M instead of min(w, M - w)), a missing 1/M or a DC term."""
+    for L in (8, 13, 64):
+        M = 2 * L
+        hk = oracle.ramp_kernel(L)
+        m = np.arange(M)
+        cf = np.where(m == 0, M / 4.0,
+                      np.where(m % 2 == 1, -1.0 / (M * np.sin(np.pi * m / M) ** 2 + (m == 0)), 0.0))
+        assert np.max(np.abs(hk - cf)) < 1e-11 * M
+
+
+def test_ramp_filter_equals_fft_route(oracle):
+    """The oracle's direct cyclic convolution equals the route the method
+    describes: zero-pad the column to M = 2L, multiply its DFT by |xi|, invert,
+    keep the L detector bins.  Independent of the oracle's arithmetic (numpy
+    FFT here).  Catches a reversed convolution index or a shifted output."""
+    L, n = 40, 16
+    pmf, _ = oracle.project(blob_img(L, seed=9), n)
+    pf = oracle.ramp(pmf)
+    M = 2 * L
+    w = np.arange(M)
+    ramp = np.minimum(w, M - w).astype(np.float64)
+    X = np.fft.fft(np.concatenate([pmf[0], np.zeros((n, L))], axis=1), axis=1)
+    ref = np.real(np.fft.ifft(X * ramp, axis=1))[:, :L]
+    assert np.max(np.abs(pf[0] - ref)) < 1e-12 * np.max(np.abs(ref))
+    # an asymmetric input pins the direction of the shift: a delta at b0 gives h[b - b0]
+    d = np.zeros((1, 1, L))
+    d[0, 0, 7] = 1.0
+    hk = oracle.ramp_kernel(L)
+    assert np.allclose(oracle.ramp(d)[0, 0], hk[(np.arange(L) - 7) % M], rtol=0, atol=1e-13)
+
+
+def test_ramp_filtered_half_turn_reversal(oracle):
+    """The filter is symmetric, so theta + pi still reverses the detector:
+    Pf[k + n/2][b] = Pf[k][L-1-b]; and the filtered slice of a nonnegative
+    image has a non-empty negative part in every column."""
+    L, n = 32, 16
+    pmf, _ = oracle.project(blob_img(L, seed=3), n)
+    pf = oracle.ramp(pmf)[0]
+    assert np.max(np.abs(pf[n // 2:] - pf[: n // 2, ::-1])) < 1e-12 * np.max(np.abs(pf))
+    assert np.all((pf < 0).any(axis=1)) and np.all((pf > 0).any(axis=1))
+
+
+def test_ramp_tables_parts_and_normalisation(oracle):
+    """Each part is normalised on its own: the stacked table's rows 0..Q-1 are
+    the plain quantiles of max(Pf, 0) and rows Q..2Q-1 those of max(-Pf, 0),
+    whatever the filter's scale; the stacked objective is the sum of the two
+    parts' objectives, each normalised by nQ."""
+    L, n, Q = 32, 16, 20
+    f, g = blob_img(L, seed=11), blob_img(L, seed=12)
+    pmf, bad = oracle.project(np.stack([f, g]), n)
+    pf = oracle.ramp(pmf)
+    qt, aux = oracle.quantiles_rf(pf, Q)
+    qp, _ = oracle.quantiles(np.maximum(pf, 0.0), Q)
+    qn, _ = oracle.quantiles(np.maximum(-pf, 0.0), Q)
+    assert np.array_equal(qt[:, :Q], qp) and np.array_equal(qt[:, Q:], qn)
+    qt3, aux3 = oracle.quantiles_rf(3.0 * pf, Q)
+    assert np.max(np.abs(qt3 - qt)) < 1e-13 and abs(aux3[0, 0] / aux[0, 0] - 3.0) < 1e-12
+    # aux[0] is the smallest part mass over the columns
+    masses = np.concatenate([np.maximum(pf, 0).sum(-1), np.maximum(-pf, 0).sum(-1)], axis=1)
+    assert np.allclose(aux[:, 0], masses.min(axis=1), rtol=1e-12)
+    for l, sx, sy in ((0, 0.0, 0.0), (5, 0.03, -0.02)):
+        d = oracle.objective_at(qt[0], qt[1], l, sx, sy, ramp=True)
+        dp = oracle.objective_at(qp[0], qp[1], l, sx, sy)
+        dn = oracle.objective_at(qn[0], qn[1], l, sx, sy)
+        assert abs(d - (dp + dn)) < 1e-14
+
+
+def test_ramp_translation_theorem(oracle):
+    """Translation equivariance of the ramp-filtered distance (appendix on
+    RFSW): RFSW2^2(f, T_t f) = |t|^2, twice the unfiltered constant of
+    Thm 3.2.  Smooth blobs re-rendered at moved centres, rotation-only D0(0).
+    The filtered slices have tails beyond the detector, which the discrete
+    definition cuts at [-1, 1]; that cut, not the grid, sets the few-percent
+    error, so the pin is a band around the constant (and the ratio to the
+    unfiltered value), not a convergence in L.  A factor-of-two error in the
+    part normalisation or the stacked objective fails it."""
+    t = np.array([0.07, -0.04])
+    for L in (32, 64, 128):
+        rng = np.random.Generator(np.random.PCG64(4))
+        cen, sig, amp = synth.blob_params(rng, 3, L, spread=0.3, sig_px=(2, 4))
+        sig = np.full(3, 0.09)
+        f = synth.finish(synth.render(cen, sig, amp, L), L)
+        g = synth.finish(synth.render(cen + t, sig, amp, L), L)
+        rf = oracle.align_images(f, g[None], L, L, mode=oracle.MODE_ROT_ONLY, want_curve=True,
+                                 ramp=True)["curve"][0, 0]
+        sw = oracle.align_images(f, g[None], L, L, mode=oracle.MODE_ROT_ONLY,
+                                 want_curve=True)["curve"][0, 0]
+        want = GOLD["rfsw_translation_constant_p2"]["value"] * (t @ t)
+        assert abs(rf - want) < 0.05 * want, (L, rf, want)
+        assert 1.9 < rf / sw < 2.1, (L, rf / sw)
+
+
+def test_ramp_closed_form_translation_is_the_minimiser(oracle):
+    """Brute force on the stacked tables: the numeric minimum over s of the
+    ramp-filtered objective at every lag equals the closed form s* = 2 b(l)
+    (b from column means over both parts) with D* = D(l, s*)."""
+    L, n = 12, 12
+    f = blob_img(L, seed=41, K=3, spread=0.4)
+    g = np.ascontiguousarray(np.rot90(blob_img(L, seed=42, K=3, spread=0.4)))
+    rq, ra = oracle.tables(f, n, n, ramp=True)
+    iq, ia = oracle.tables(g, n, n, ramp=True)
+    r = oracle.align(rq, ra, iq, ia, L, want_curve=True, ramp=True)
+    for l in range(n):
+        fun = lambda s: oracle.objective_at(rq[0], iq[0], l, s[0], s[1], ramp=True)
+        res = minimize(fun, np.zeros(2), method="Nelder-Mead",
+                       options=dict(xatol=1e-12, fatol=1e-16, maxiter=4000))
+        assert abs(res.fun - r["curve"][0, l]) < 1e-12
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_ramp_quarter_turns_recovered_exactly(oracle, m):
+    """Filtering acts on each column alone, so a 90-degree image rotation is
+    still an exact column shift of the stacked tables: l* = m n/4, D* = 0."""
+    L, n = 32, 16
+    f = blob_img(L, seed=21)
+    g = np.ascontiguousarray(np.rot90(f, m))
+    r = oracle.align_images(f, g[None], n, n, ramp=True)
+    assert r["status"][0] == 0
+    assert r["rot_index"][0] == (m * n // 4) % n or r["rot_index"][0] == (-m * n // 4) % n
+    assert r["sw2sq"][0] < 1e-20
