@@ -75,6 +75,12 @@ typedef enum { SW_MODE_ROT_TRANS = 0, SW_MODE_ROT_ONLY = 1 } sw_mode;
    and an FP32 rescore of the top_k lags. */
 typedef enum { SW_PREC_FP32 = 0, SW_PREC_BF16_SPLIT = 1 } sw_precision;
 
+/* Projection filter of the alignment: none (SW2) or the ramp filter |xi|
+   of Sec. 2.2 (ramp-filtered SW2 of Sec. 2.3: each filtered slice split into
+   its positive and negative parts, each normalised and compared on its own,
+   the two distances summed). */
+typedef enum { SW_FILTER_NONE = 0, SW_FILTER_RAMP = 1 } sw_filter;
+
 /* Per-result status: zero mass after clipping and masking, a non-finite
    input value, or a pair index outside the table sets. */
 enum { SW_RESULT_OK = 0, SW_RESULT_ZERO_MASS = 1, SW_RESULT_NONFINITE = 2, SW_RESULT_BAD_PAIR = 3 };
@@ -139,6 +145,36 @@ sw_status sw_quantiles(void *ctx, const float *pmf, int64_t N, const sw_geom *g 
 sw_status sw_tables(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/, float *qt,
                     double *aux, void *stream);
 
+/* Ramp filter of projections (Sec. 2.2, optional high-pass step; the
+   ramp-filtered distance of Sec. 2.3).  The filter |xi| is sampled on the
+   2L-point frequency grid of the detector with the DC term zero and applied
+   to each column zero-padded to 2L, i.e. the cyclic convolution
+     out[g][k][b] = sum_{b'} h[(b - b') mod 2L] pmf[g][k][b'],
+     h[0] = L/2, h[m] = -1/(2L sin^2(pi m / 2L)) for odd m, 0 for even m != 0,
+   kept on the L detector bins; any positive scale of the filter cancels in
+   the normalised parts.  Computed in FP32 on the matrix cores.
+   pmf, out: [N][n][L] float32 (out may equal pmf).  NaN columns stay NaN. */
+sw_status sw_ramp(void *ctx, const float *pmf, int64_t N, const sw_geom *g /*host*/, float *out,
+                  void *stream);
+
+/* Step 2 for ramp-filtered projections: each column of pf is split into its
+   positive part max(pf, 0) and its absolute negative part max(-pf, 0), each
+   part is inverted as in sw_quantiles (normalised on its own), and the two
+   tables are stacked: qt[g][j][k] for j < Q is the positive part, j >= Q the
+   negative part.  2 * n_quantiles must not exceed 512.
+   pf: [N][n][L] float32, qt: [N][2Q][n] float32.
+   aux (nullable): [N][4] float64 = { the smallest part mass over all columns
+   (0 when a part is empty somewhere: such an image aligns with status
+   SW_RESULT_ZERO_MASS; NaN if a value is NaN), E and Re a, Im a of the
+   stacked table }. */
+sw_status sw_quantiles_rf(void *ctx, const float *pf, int64_t N, const sw_geom *g /*host*/,
+                          float *qt, double *aux, void *stream);
+
+/* Images to stacked ramp-filtered tables: sw_project, sw_ramp and
+   sw_quantiles_rf in one call (through a bounded scratch buffer). */
+sw_status sw_tables_rf(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/,
+                       float *qt, double *aux, void *stream);
+
 /* Steps 3-5: alignment of table pairs.
    For each pair (r, g): the angle spectra of both tables, the correlation
    C(l) = sum_{j,k} U[j][k] V[j][(k+l) mod n] for all l by FFT along the angle
@@ -163,6 +199,13 @@ typedef struct {
     int32_t mode;          /* sw_mode */
     int32_t prec;          /* sw_precision */
     int32_t top_k;         /* 1..8; 0 means 1 for FP32 and 4 for BF16_SPLIT */
+    int32_t filter;        /* sw_filter; SW_FILTER_RAMP: the tables are the stacked
+                              [2Q][n] tables of sw_tables_rf (geom.n_quantiles = Q,
+                              2Q <= 512), and sw2sq and the curve are the
+                              ramp-filtered distance: the sum over both parts of
+                              (1/(nQ)) sum_{j,k} (U - V - s.d_k)^2.  The rotation
+                              and the shift minimise that sum; s* = 2 b(l) with
+                              b from the column means of the stacked tables. */
 } sw_batch;
 
 sw_status sw_align_batch(void *ctx, const sw_batch *b /*host*/, sw_result *out, float *curve,

@@ -15,6 +15,7 @@ SW_OK, SW_NOT_READY, SW_E_INVALID, SW_E_NOMEM, SW_E_DEVICE, SW_E_UNSUPPORTED, SW
 LEVELS_MIDPOINT, LEVELS_LEFT = 0, 1
 MODE_ROT_TRANS, MODE_ROT_ONLY = 0, 1
 PREC_FP32, PREC_BF16_SPLIT = 0, 1
+FILTER_NONE, FILTER_RAMP = 0, 1
 RESULT_OK, RESULT_ZERO_MASS, RESULT_NONFINITE = 0, 1, 2
 
 STATUS_NAMES = {0: "SW_OK", 1: "SW_NOT_READY", -1: "SW_E_INVALID", -2: "SW_E_NOMEM",
@@ -38,7 +39,7 @@ class sw_batch(ctypes.Structure):
                 ("img_aux", ctypes.c_void_p), ("n_img", ctypes.c_int64),
                 ("pairs", ctypes.c_void_p), ("n_pairs", ctypes.c_int64),
                 ("geom", sw_geom), ("mode", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("top_k", ctypes.c_int32)]
+                ("top_k", ctypes.c_int32), ("filter", ctypes.c_int32)]
 
 
 class sw_stack(ctypes.Structure):
@@ -83,6 +84,9 @@ SIGNATURES = [
     ("sw_project", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P]),
     ("sw_quantiles", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
     ("sw_tables", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
+    ("sw_ramp", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P]),
+    ("sw_quantiles_rf", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
+    ("sw_tables_rf", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
     ("sw_align_batch", I32, [P, ctypes.POINTER(sw_batch), P, P, P]),
     ("sw_align_stacks", I32, [P, ctypes.POINTER(sw_stack), I32, I32, I32, I32, P]),
     ("sw_autotune", I32, [P, ctypes.POINTER(ctypes.c_int32), I32, I64, ctypes.c_char_p]),

@@ -75,39 +75,56 @@ def project(ctx: Context, imgs: torch.Tensor, n: int, stream=None, out=None):
     return pmf
 
 
+def ramp(ctx: Context, pmf: torch.Tensor, stream=None, out=None):
+    """sw_ramp: [N, n, L] projections -> ramp-filtered (signed) [N, n, L]."""
+    _need(pmf, torch.float32, "pmf")
+    N, n, L = pmf.shape
+    g = geom(L, n, 8)
+    o = out if out is not None else torch.empty_like(pmf)
+    check(ctx._lib.sw_ramp(ctx.handle, _ptr(pmf), N, ctypes.byref(g), _ptr(o), _stream(stream)))
+    return o
+
+
 def quantiles(ctx: Context, pmf: torch.Tensor, Q: int, levels=_abi.LEVELS_MIDPOINT, stream=None,
-              out=None, aux=None):
-    """sw_quantiles: [N, n, L] -> ([N, Q, n] float32, [N, 4] float64)."""
+              out=None, aux=None, ramp=False):
+    """sw_quantiles: [N, n, L] -> ([N, Q, n] float32, [N, 4] float64).
+    ramp=True: sw_quantiles_rf on ramp-filtered projections -> [N, 2Q, n]."""
     _need(pmf, torch.float32, "pmf")
     N, n, L = pmf.shape
     g = geom(L, n, Q, levels)
-    qt = out if out is not None else torch.empty((N, Q, n), dtype=torch.float32, device=pmf.device)
+    rows = 2 * Q if ramp else Q
+    qt = out if out is not None else torch.empty((N, rows, n), dtype=torch.float32,
+                                                 device=pmf.device)
     ax = aux if aux is not None else torch.empty((N, 4), dtype=torch.float64, device=pmf.device)
-    check(ctx._lib.sw_quantiles(ctx.handle, _ptr(pmf), N, ctypes.byref(g), _ptr(qt), _ptr(ax),
-                                _stream(stream)))
+    fn = ctx._lib.sw_quantiles_rf if ramp else ctx._lib.sw_quantiles
+    check(fn(ctx.handle, _ptr(pmf), N, ctypes.byref(g), _ptr(qt), _ptr(ax), _stream(stream)))
     return qt, ax
 
 
 def tables(ctx: Context, imgs: torch.Tensor, n: int, Q: int, levels=_abi.LEVELS_MIDPOINT,
-           stream=None, out=None, aux=None):
-    """sw_tables: images straight to quantile tables (fused projection)."""
+           stream=None, out=None, aux=None, ramp=False):
+    """sw_tables: images straight to quantile tables (fused projection).
+    ramp=True: sw_tables_rf, stacked ramp-filtered tables [N, 2Q, n]."""
     _need(imgs, torch.float32, "imgs")
     N, L = imgs.shape[0], imgs.shape[-1]
     g = geom(L, n, Q, levels)
-    qt = out if out is not None else torch.empty((N, Q, n), dtype=torch.float32, device=imgs.device)
+    rows = 2 * Q if ramp else Q
+    qt = out if out is not None else torch.empty((N, rows, n), dtype=torch.float32,
+                                                 device=imgs.device)
     ax = aux if aux is not None else torch.empty((N, 4), dtype=torch.float64, device=imgs.device)
-    check(ctx._lib.sw_tables(ctx.handle, _ptr(imgs), N, ctypes.byref(g), _ptr(qt), _ptr(ax),
-                             _stream(stream)))
+    fn = ctx._lib.sw_tables_rf if ramp else ctx._lib.sw_tables
+    check(fn(ctx.handle, _ptr(imgs), N, ctypes.byref(g), _ptr(qt), _ptr(ax), _stream(stream)))
     return qt, ax
 
 
 def make_batch(ref_qt, ref_aux, img_qt, img_aux, L, pairs=None, mode=_abi.MODE_ROT_TRANS,
-               prec=_abi.PREC_FP32, top_k=0, levels=_abi.LEVELS_MIDPOINT):
+               prec=_abi.PREC_FP32, top_k=0, levels=_abi.LEVELS_MIDPOINT, ramp=False):
     _need(ref_qt, torch.float32, "ref_qt")
     _need(img_qt, torch.float32, "img_qt")
     _need(ref_aux, torch.float64, "ref_aux")
     _need(img_aux, torch.float64, "img_aux")
-    nr, Q, n = ref_qt.shape
+    nr, rows, n = ref_qt.shape
+    Q = rows // 2 if ramp else rows
     ni = img_qt.shape[0]
     b = sw_batch()
     b.ref_qt, b.ref_aux, b.n_ref = ref_qt.data_ptr(), ref_aux.data_ptr(), nr
@@ -121,15 +138,19 @@ def make_batch(ref_qt, ref_aux, img_qt, img_aux, L, pairs=None, mode=_abi.MODE_R
         P = nr * ni
     b.geom = geom(L, n, Q, levels)
     b.mode, b.prec, b.top_k = int(mode), int(prec), int(top_k)
+    b.filter = _abi.FILTER_RAMP if ramp else _abi.FILTER_NONE
     return b, P
 
 
 def align_batch(ctx: Context, ref_qt, ref_aux, img_qt, img_aux, L, pairs=None,
                 mode=_abi.MODE_ROT_TRANS, prec=_abi.PREC_FP32, top_k=0, want_curve=False,
-                levels=_abi.LEVELS_MIDPOINT, stream=None, out=None):
+                levels=_abi.LEVELS_MIDPOINT, stream=None, out=None, ramp=False):
     """sw_align_batch.  Returns the raw [P, 6] int32 result records (see
-    `unpack_results`) and the [P, n] curve when requested."""
-    b, P = make_batch(ref_qt, ref_aux, img_qt, img_aux, L, pairs, mode, prec, top_k, levels)
+    `unpack_results`) and the [P, n] curve when requested.  ramp=True: the
+    tables are stacked ramp-filtered tables and sw2sq is the ramp-filtered
+    distance."""
+    b, P = make_batch(ref_qt, ref_aux, img_qt, img_aux, L, pairs, mode, prec, top_k, levels,
+                      ramp)
     dev = img_qt.device
     res = out if out is not None else torch.empty((P, 6), dtype=torch.int32, device=dev)
     curve = torch.empty((P, b.geom.n_angles), dtype=torch.float32, device=dev) if want_curve else None

@@ -34,6 +34,7 @@ struct Ctx {
     std::mutex mu;
     std::map<int, sw::AngleTable> tables;
     std::map<int, sw::ProjPlan> plans;  // key L * 4096 + n
+    std::map<int, float *> ramp_tables;  // ramp filter kernel per L
     std::map<int, int> tile_R;  // projection strip rows per L (autotuner)
     // batches of fewer images take the split (many blocks per image) launches;
     // -1: the number of compute units

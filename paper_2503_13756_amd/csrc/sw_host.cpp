@@ -222,6 +222,45 @@ sw_status get_plan(Ctx *ctx, int L, int n, const sw::ProjPlan **out) {
     return SW_OK;
 }
 
+// Cyclic kernel of the ramp filter |w| sampled on M = 2L frequencies (DC
+// zero): h[0] = M/4, h[m] = -1/(M sin^2(pi m / M)) for odd m, 0 for even
+// m != 0.  Stored as hx[t] = h[t - (LP - 1)] for |t - (LP - 1)| < L, zero
+// elsewhere, t < 2 LP - 1 (the layout launch_ramp reads).
+static sw_status get_ramp_table(Ctx *ctx, int L, const float **out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto f = ctx->ramp_tables.find(L);
+    if (f != ctx->ramp_tables.end()) {
+        *out = f->second;
+        return SW_OK;
+    }
+    const int LP = sw::ramp_padded_length(L), M = 2 * L;
+    std::vector<float> hx(2 * LP - 1, 0.f);
+    const double pi = 3.141592653589793238462643383279502884;
+    for (int t = 0; t < 2 * LP - 1; ++t) {
+        const int m = t - (LP - 1);
+        if (m <= -L || m >= L) continue;
+        const int mm = ((m % M) + M) % M;
+        double v = 0.0;
+        if (mm == 0) v = M / 4.0;
+        else if (mm & 1) {
+            const double sn = std::sin(pi * mm / M);
+            v = -1.0 / (M * sn * sn);
+        }
+        hx[t] = (float)v;
+    }
+    float *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(float) * hx.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(ramp table)");
+    e = hipMemcpy(d, hx.data(), sizeof(float) * hx.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "hipMemcpy(ramp table)");
+    }
+    ctx->ramp_tables.emplace(L, d);
+    *out = d;
+    return SW_OK;
+}
+
 sw_status get_scratch(Ctx *ctx, size_t bytes, hipStream_t stream, void **out) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (bytes > ctx->scratch_bytes) {
@@ -446,6 +485,7 @@ sw_status sw_ctx_destroy(void *ctx) {
             (void)hipFree(kv.second.perm);
             (void)hipFree(kv.second.trow);
         }
+        for (auto &kv : c->ramp_tables) (void)hipFree(kv.second);
         if (c->scratch) (void)hipFree(c->scratch);
         for (int i = 0; i < DescRing::kSlots; ++i)
             if (c->ring.ev[i]) (void)hipEventDestroy(c->ring.ev[i]);
@@ -540,6 +580,88 @@ sw_status sw_tables(void *ctx, const float *img, int64_t N, const sw_geom *g, fl
     return SW_OK;
 }
 
+sw_status sw_ramp(void *ctx, const float *pmf, int64_t N, const sw_geom *g, float *out,
+                  void *stream) {
+    if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
+    sw::Geo geo;
+    sw_status st = check_geom(g, &geo);
+    if (st != SW_OK) return st;
+    if (N < 0) return fail(SW_E_INVALID, "N = %lld is negative", (long long)N);
+    if (N == 0) return SW_OK;
+    if (!pmf || !out) return fail(SW_E_INVALID, "pmf or out is NULL");
+    Ctx *c = as_ctx(ctx);
+    DeviceGuard dg(c->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    const float *hx;
+    if ((st = get_ramp_table(c, geo.L, &hx)) != SW_OK) return st;
+    hipError_t e = sw::launch_ramp(pmf, out, N * (int64_t)geo.n, geo.L, hx, (hipStream_t)stream);
+    return e == hipSuccess ? SW_OK : hip_fail(e, "k_ramp launch");
+}
+
+sw_status sw_quantiles_rf(void *ctx, const float *pf, int64_t N, const sw_geom *g, float *qt,
+                          double *aux, void *stream) {
+    if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
+    sw::Geo geo;
+    sw_status st = check_geom(g, &geo);
+    if (st != SW_OK) return st;
+    if (2 * geo.Q > 512) return fail(SW_E_INVALID, "2 n_quantiles = %d exceeds 512", 2 * geo.Q);
+    if (N < 0) return fail(SW_E_INVALID, "N = %lld is negative", (long long)N);
+    if (N == 0) return SW_OK;
+    if (!pf || !qt) return fail(SW_E_INVALID, "pf or qt is NULL");
+    Ctx *c = as_ctx(ctx);
+    DeviceGuard dg(c->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    const sw::AngleTable *t;
+    if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
+    hipError_t e = sw::launch_quantiles_rf(pf, N, geo, *t, qt, aux, (hipStream_t)stream,
+                                           c->small(N));
+    return e == hipSuccess ? SW_OK : hip_fail(e, "k_quantile_rf launch");
+}
+
+sw_status sw_tables_rf(void *ctx, const float *img, int64_t N, const sw_geom *g, float *qt,
+                       double *aux, void *stream) {
+    if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
+    sw::Geo geo;
+    sw_status st = check_geom(g, &geo);
+    if (st != SW_OK) return st;
+    if (2 * geo.Q > 512) return fail(SW_E_INVALID, "2 n_quantiles = %d exceeds 512", 2 * geo.Q);
+    if (N < 0) return fail(SW_E_INVALID, "N = %lld is negative", (long long)N);
+    if (N == 0) return SW_OK;
+    if (!img || !qt) return fail(SW_E_INVALID, "img or qt is NULL");
+    Ctx *c = as_ctx(ctx);
+    DeviceGuard dg(c->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    const sw::AngleTable *t;
+    if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
+    const sw::ProjPlan *pp;
+    if ((st = get_plan(c, geo.L, geo.n, &pp)) != SW_OK) return st;
+    const float *hx;
+    if ((st = get_ramp_table(c, geo.L, &hx)) != SW_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const bool small = c->small(N);
+    // projections of a chunk of images in scratch, filtered in place, then
+    // split and inverted
+    const size_t per = sizeof(float) * (size_t)geo.n * geo.L;
+    int64_t chunk = (int64_t)((size_t)256 << 20) / (int64_t)per;
+    if (chunk < 1) chunk = 1;
+    if (chunk > N) chunk = N;
+    void *pmf;
+    if ((st = get_scratch(c, per * (size_t)chunk, s, &pmf)) != SW_OK) return st;
+    for (int64_t i0 = 0; i0 < N; i0 += chunk) {
+        const int64_t m = N - i0 < chunk ? N - i0 : chunk;
+        hipError_t e = sw::launch_project(img + i0 * (int64_t)geo.L * geo.L, m, geo, *t, *pp,
+                                          (float *)pmf, s, small);
+        if (e != hipSuccess) return hip_fail(e, "k_project launch");
+        e = sw::launch_ramp((const float *)pmf, (float *)pmf, m * (int64_t)geo.n, geo.L, hx, s);
+        if (e != hipSuccess) return hip_fail(e, "k_ramp launch");
+        e = sw::launch_quantiles_rf((const float *)pmf, m, geo, *t,
+                                    qt + i0 * (int64_t)2 * geo.Q * geo.n,
+                                    aux ? aux + 4 * i0 : nullptr, s, small);
+        if (e != hipSuccess) return hip_fail(e, "k_quantile_rf launch");
+    }
+    return SW_OK;
+}
+
 sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *curve,
                          void *stream) {
     if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
@@ -547,6 +669,15 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
     sw::Geo geo;
     sw_status st = check_geom(&b->geom, &geo);
     if (st != SW_OK) return st;
+    if (b->filter != SW_FILTER_NONE && b->filter != SW_FILTER_RAMP)
+        return fail(SW_E_INVALID, "filter = %d is not a sw_filter value", b->filter);
+    const bool ramp = b->filter == SW_FILTER_RAMP;
+    if (ramp) {
+        // the stacked tables align as one table of 2Q rows; the distance of
+        // the two parts is twice that table's objective
+        if (2 * geo.Q > 512) return fail(SW_E_INVALID, "2 n_quantiles = %d exceeds 512", 2 * geo.Q);
+        geo.Q *= 2;
+    }
     if (b->n_ref < 0 || b->n_img < 0 || b->n_pairs < 0)
         return fail(SW_E_INVALID, "negative count");
     const int64_t P = b->pairs ? b->n_pairs : b->n_ref * b->n_img;
@@ -604,7 +735,12 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
         m.cand = cand;
         m.out = (sw::Result *)out;
         e = sw::launch_mfma_all_pairs(m, geo, *t, s);
-        return e == hipSuccess ? SW_OK : hip_fail(e, "k_corr_mfma / k_rescore_tiles launch");
+        if (e != hipSuccess) return hip_fail(e, "k_corr_mfma / k_rescore_tiles launch");
+        if (ramp) {
+            e = sw::launch_scale_results((sw::Result *)out, P, nullptr, geo.n, 2.f, s);
+            if (e != hipSuccess) return hip_fail(e, "k_scale_results launch");
+        }
+        return SW_OK;
     }
     const size_t spec_bytes =
         (sizeof(float2) * (size_t)Wn * geo.Q * (size_t)b->n_ref + 255) & ~(size_t)255;
@@ -631,10 +767,16 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
     a.curve = curve;
     if (fast128) {
         e = sw::launch_align128(a, geo, *t, (float2 *)((char *)spec + spec_bytes), s);
-        return e == hipSuccess ? SW_OK : hip_fail(e, "k_gamma128 / k_align128 launch");
+        if (e != hipSuccess) return hip_fail(e, "k_gamma128 / k_align128 launch");
+    } else {
+        e = sw::launch_align_pairs(a, geo, *t, s);
+        if (e != hipSuccess) return hip_fail(e, "k_align_pairs launch");
     }
-    e = sw::launch_align_pairs(a, geo, *t, s);
-    return e == hipSuccess ? SW_OK : hip_fail(e, "k_align_pairs launch");
+    if (ramp) {
+        e = sw::launch_scale_results((sw::Result *)out, P, curve, geo.n, 2.f, s);
+        if (e != hipSuccess) return hip_fail(e, "k_scale_results launch");
+    }
+    return SW_OK;
 }
 
 sw_status sw_align_stacks(void *ctx, const sw_stack *stacks, int32_t n_stacks, int32_t mode,

@@ -75,6 +75,19 @@ hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &
                           const ProjPlan &pp, float *pmf, hipStream_t s, bool split = false);
 hipError_t launch_quantiles(const float *pmf, int64_t N, Geo g, const AngleTable &t, float *qt,
                             double *aux, hipStream_t s, bool small = false);
+// Ramp-filtered projections: the stacked [2Q][n] tables of the positive and
+// negative parts (per image) from signed [n][L] columns.
+hipError_t launch_quantiles_rf(const float *pf, int64_t N, Geo g, const AngleTable &t, float *qt,
+                               double *aux, hipStream_t s, bool small = false);
+// Ramp filter of C columns of L bins (src may equal dst).  hx: the filter's
+// cyclic kernel as a table of 2 LP - 1 floats, hx[t] = h[t - (LP - 1)] for
+// |t - (LP - 1)| < L and 0 otherwise, LP = ramp_padded_length(L).
+int ramp_padded_length(int L);
+hipError_t launch_ramp(const float *src, float *dst, int64_t C, int L, const float *hx,
+                       hipStream_t s);
+// sw2sq of the valid results, and the curve, times f.
+hipError_t launch_scale_results(Result *out, int64_t P, float *curve, int n, float f,
+                                hipStream_t s);
 // Fused image -> quantile table; only for geometries where
 // tables_fused_fits() holds (the PMF table must fit in LDS).
 bool tables_fused_fits(Geo g);

@@ -51,6 +51,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(_abi.sw_geom) == 16
     assert ctypes.sizeof(_abi.sw_result) == 24
     assert _abi.sw_batch.geom.offset == 64
+    assert _abi.sw_batch.filter.offset == 92
     assert ctypes.sizeof(_abi.sw_batch) == 96
 
 
