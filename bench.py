@@ -227,6 +227,9 @@ def main():
 
     extra_res = {}
     if not args.skip_extra:
+        log("ramp-filtered SW2")
+        line["ramp_filtered"], extra_res["ramp"] = bench_ramp(api, ctx, torch, ref, imgs, L, n, Q,
+                                                              ms32)
         del pmf, iq, ia, res
         torch.cuda.empty_cache()
         log("all pairs")
@@ -251,6 +254,9 @@ def main():
         if "uneven" in extra_res:
             log("uneven stacks parity (oracle)")
             line["cpu_baseline"]["uneven_parity"] = uneven_parity(*extra_res["uneven"])
+        if "ramp" in extra_res:
+            log("ramp-filtered parity (oracle)")
+            line["cpu_baseline"]["ramp_parity"] = ramp_parity(w, *extra_res["ramp"], L, n, Q)
 
     s = json.dumps(line)
     print(s, flush=True)
@@ -271,6 +277,72 @@ def timed(torch, fn, K, W=1):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / K
+
+
+def bench_ramp(api, ctx, torch, ref, imgs, L, n, Q, ms_sw2, K=5):
+    """Ramp-filtered SW2 on the 1-vs-many workload: stacked signed-part tables
+    of the reference and of every image (projection, ramp filter, two
+    inversions), then the alignment of the 2Q-row tables, FP32 and BF16."""
+    N = imgs.shape[0]
+    dev = imgs.device
+    rq = torch.empty((1, 2 * Q, n), dtype=torch.float32, device=dev)
+    ra = torch.empty((1, 4), dtype=torch.float64, device=dev)
+    iq = torch.empty((N, 2 * Q, n), dtype=torch.float32, device=dev)
+    ia = torch.empty((N, 4), dtype=torch.float64, device=dev)
+    res = torch.empty((N, 6), dtype=torch.int32, device=dev)
+    E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def step(prec, ev):
+        ev[0].record()
+        api.tables(ctx, ref, n, Q, out=rq, aux=ra, ramp=True)
+        api.tables(ctx, imgs, n, Q, out=iq, aux=ia, ramp=True)
+        ev[1].record()
+        api.align_batch(ctx, rq, ra, iq, ia, L, prec=prec, out=res, ramp=True)
+        ev[2].record()
+
+    out = {"workload": f"1 reference vs {N} images, L=128, n=Q=128 (images as in the main line), "
+                       "ramp-filtered SW2: stacked 2Q-row tables, images to results"}
+    results = {}
+    for prec, name in ((0, "fp32"), (1, "bf16_split")):
+        step(prec, [E(), E(), E()])
+        torch.cuda.synchronize()
+        evs = [[E(), E(), E()] for _ in range(K)]
+        t0 = time.perf_counter()
+        for k in range(K):
+            step(prec, evs[k])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / K * 1e3
+        tab = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+        ali = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+        out[name] = {"value": N / (wall * 1e-3), "ms_per_step": wall, "tables_ms": tab,
+                     "align_ms": ali}
+        results[name] = api.unpack_results(res)
+    out["unit"] = "alignments/s"
+    out["cost_vs_sw2_fp32"] = out["fp32"]["ms_per_step"] / ms_sw2
+    out["paper_context"] = "RFSW2 costs 1.3-1.4x SW2 on CPU (Table 4: 0.831 s vs 0.586 s)"
+    return out, (results["fp32"], results["bf16_split"])
+
+
+def ramp_parity(w, r32, r16, L, n, Q, S=1000):
+    """Oracle ramp-filtered alignment of the first S images against the GPU's
+    FP32 and BF16 results of the timed run."""
+    from oracle import oracle as O
+    from tests import parity
+
+    S = min(S, len(w["imgs"]))
+    o = O.align_images(w["ref"], w["imgs"][:S], n, Q, want_curve=True, ramp=True)
+    out = {"pairs": S}
+    for name, r, tau in (("fp32", r32, parity.TAU_FP32), ("bf16_split", r16, parity.TAU_BF16)):
+        sub = {k: v[:S] for k, v in r.items()}
+        try:
+            rep = parity.check(sub, o, L, tau, o["curve"])
+            out[name] = f"{rep['pairs']} pairs ok, exact rotation {rep['exact_rot']}"
+        except AssertionError as e:
+            out[name] = "FAILED: " + str(e)[:300]
+    truth = w["truth_theta"][:S]
+    d = (r32["theta_rad"][:S] - truth + math.pi) % (2 * math.pi) - math.pi
+    out["gpu_within_15deg_of_truth"] = float(np.mean(np.abs(d) <= math.radians(15)))
+    return out
 
 
 def bench_all_pairs(api, ctx, torch, N=2000, L=64):
