@@ -362,19 +362,25 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
         for (int q = threadIdx.x; q < rows * (n / 4); q += NT)
             *(float4 *)(vl + 4 * q) = *(const float4 *)(V + (int64_t)j0 * n + 4 * q);
         __syncthreads();
-        const float *Uc = U + (int64_t)j0 * n;
+        // a thread keeps one column k (NT is a multiple of n) and walks
+        // rows kRows apart, so the angle, the shift terms and the rotated
+        // column offsets are per-thread constants
+        constexpr int kRows = NT / n;
+        const int k = threadIdx.x & (n - 1), jt = threadIdx.x / n;
+        const float2 dk = tw[k];
+        const float *Uc = U + (int64_t)j0 * n + k;
         for (int c0 = 0; c0 < K; c0 += 2) {
             const int c1 = c0 + 1 < K ? c0 + 1 : c0;
-            const int la = cand[c0], lb = cand[c1];
-            const float ax = cs[c0].x, ay = cs[c0].y, bx = cs[c1].x, by = cs[c1].y;
+            const float *va = vl + ((k + cand[c0]) & (n - 1));
+            const float *vb = vl + ((k + cand[c1]) & (n - 1));
+            const float sa = cs[c0].x * dk.x + cs[c0].y * dk.y;
+            const float sb = cs[c1].x * dk.x + cs[c1].y * dk.y;
             float pa = 0.f, pb = 0.f;
-#pragma unroll 4
-            for (int idx = threadIdx.x; idx < rows * n; idx += NT) {
-                const int jr = idx & ~(n - 1), k = idx & (n - 1);
-                const float u = Uc[idx];
-                const float2 dk = tw[k];
-                const float da = u - vl[jr + ((k + la) & (n - 1))] - (ax * dk.x + ay * dk.y);
-                const float db = u - vl[jr + ((k + lb) & (n - 1))] - (bx * dk.x + by * dk.y);
+#pragma unroll 8
+            for (int jr = jt; jr < rows; jr += kRows) {
+                const float u = Uc[jr * n];
+                const float da = u - va[jr * n] - sa;
+                const float db = u - vb[jr * n] - sb;
                 pa += da * da;
                 pb += db * db;
             }
