@@ -1,60 +1,28 @@
-// Ramp filter of the line projections (Sec. 2.2, optional high-pass step:
-// each slice multiplied by |xi| before the inverse transform; the
-// ramp-filtered distance of Sec. 2.3 and its appendix).  With the filter
-// |xi| sampled on the M = 2L point frequency grid of the detector (DC term
-// zero) and each column zero-padded to M, the filtered column is the cyclic
-// convolution
-//   Pf[k][b] = sum_{b'} h[(b - b') mod M] P[k][b'],   b, b' < L,
-// i.e. the product of the L x L Toeplitz matrix H[b][b'] = h[b - b'] with the
-// columns.  That product runs on the matrix cores in FP32
-// (v_mfma_f32_16x16x4_f32): a wave takes 16 columns, keeps their values as B
-// fragments (b' = 4 s + lane / 16, column lane % 16), and for each 16-bin
-// output tile accumulates the L/4 K-steps with A fragments
-// H[16 t + lane % 16][4 s + lane / 16] read from the kernel table in LDS.
-// The column is padded to LP = L rounded up to 16 with zeros.
-#include "sw_internal.h"
+// Stand-alone ramp filter of projection columns (Sec. 2.2, optional
+// high-pass step; the ramp-filtered distance of Sec. 2.3): waves take tiles
+// of 16 columns (ramp_dev.h).
+#include "ramp_dev.h"
 
 namespace sw {
 
-typedef float f32x4r __attribute__((ext_vector_type(4)));
-
 template <int NS>  // K-steps: LP / 4
-__global__ __launch_bounds__(256) void k_ramp(const float *src, float *dst, int64_t C,
-                                              int L, const float *__restrict__ hx) {
-    constexpr int LP = 4 * NS, NB = LP / 16, HX = 2 * LP - 1;
-    __shared__ float hs[HX];  // hs[t] = h[t - (LP - 1)], 0 beyond |t - (LP - 1)| >= L
+__global__ __launch_bounds__(256) void k_ramp(const float *src, float *dst, int64_t C, int L,
+                                              const float *__restrict__ hx) {
+    constexpr int LP = 4 * NS, HX = 2 * LP - 1;
+    __shared__ float hs[HX];
     for (int i = threadIdx.x; i < HX; i += 256) hs[i] = hx[i];
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
+    const int wave = threadIdx.x >> 6;
     const int64_t ntiles = (C + 15) / 16;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles;
          tile += (int64_t)gridDim.x * 4) {
-        const int64_t col = tile * 16 + li;
-        const bool cv = col < C;
-        const float *P = src + (cv ? col : 0) * (int64_t)L;
-        float bf[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int b = 4 * s + lk;
-            bf[s] = (cv && b < L) ? P[b] : 0.f;
-        }
-        float *out = dst + (cv ? col : 0) * (int64_t)L;
-#pragma unroll
-        for (int t = 0; t < NB; ++t) {
-            f32x4r acc = {0.f, 0.f, 0.f, 0.f};
-            // A[i][k] = h[16 t + i - 4 s - k] at table index 16 t - 4 s + i - k + LP - 1
-            const float *ha = hs + 16 * t + li - lk + (LP - 1);
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * s], bf[s], acc, 0, 0, 0);
-            // this lane holds bins 16 t + 4 (lane / 16) + r of its column
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int b = 16 * t + 4 * lk + r;
-                if (cv && b < L) out[b] = acc[r];
-            }
-        }
+        const int64_t c0 = tile * 16;
+        ramp_tile<NS>(
+            hs, L,
+            [&](int j, int b) { return c0 + j < C ? src[(c0 + j) * L + b] : 0.f; },
+            [&](int j, int b, float v) {
+                if (c0 + j < C) dst[(c0 + j) * L + b] = v;
+            });
     }
 }
 

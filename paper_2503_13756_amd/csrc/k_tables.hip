@@ -6,6 +6,7 @@
 // the stand-alone projection followed by the stand-alone quantile stage.
 #include "proj_dev.h"
 #include "quant_dev.h"
+#include "ramp_dev.h"
 
 namespace sw {
 
@@ -38,6 +39,92 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
     __syncthreads();
     quantile_phase<NT>([&](int k, int b) { return region[k * L + b]; }, L, n, Q, T.levels, T.TC,
                        d64, Ut, colS, qt + g * (int64_t)Q * n, aux ? aux + 4 * g : nullptr);
+}
+
+// Fused ramp-filtered tables (ramp-filtered SW of Sec. 2.3): the projection
+// as above, written into LDS with a padded column stride, the ramp filter in
+// place on the matrix cores (ramp_dev.h; waves take tiles of 16 columns),
+// then the positive and the negative part of every column inverted into the
+// stacked [2Q][n] table, and aux = { smallest part mass (NaN for a NaN
+// value), E and a of the stacked table }.  Same results as sw_project,
+// sw_ramp and sw_quantiles_rf in sequence.
+template <int NT, int TPW, int NS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWaves<NT, TPW>, NT <= 256 ? 2 : 4))) void k_tables_rf(
+    const float *__restrict__ img, int64_t N, TablesShape T, const float2 *__restrict__ d32,
+    const double2 *__restrict__ d64, const float *__restrict__ hx, float *__restrict__ qt,
+    double *__restrict__ aux) {
+    constexpr int NW = NT / 64, LP = 4 * NS, HX = 2 * LP - 1;
+    extern __shared__ __align__(16) double ldsd[];
+    __shared__ double partA[2][4];
+    __shared__ double wmin[NW];
+    __shared__ int wnan[NW];
+    const int64_t g = blockIdx.x;
+    if (g >= N) return;
+    const ProjShape &P = T.P;
+    const int L = P.L, n = P.n, Q = T.Q, ldp = L + 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float *region = (float *)ldsd;
+    double *colS = ldsd + T.region_floats / 2;
+    float *Ut = (float *)(colS + 2 * n);
+    float *hs = Ut + Q * (T.TC + 1);
+    const float *F = img + g * (int64_t)L * L;
+    int bad = 0;
+    // columns ldp = L + 4 floats apart: the filter's 16 columns x 4 bins of
+    // one fragment read fall in distinct banks
+    project_image<NT, TPW>(F, P, d32, region, bad,
+                           [&](int k, int b, float v) { region[k * ldp + b] = v; });
+    if (bad)
+        for (int t = threadIdx.x; t < n * ldp; t += NT) region[t] = __int_as_float(0x7fc00000);
+    for (int i = threadIdx.x; i < HX; i += NT) hs[i] = hx[i];
+    __syncthreads();
+    for (int tile = wave; tile < (n + 15) / 16; tile += NW) {
+        const int c0 = 16 * tile;
+        ramp_tile<NS>(
+            hs, L, [&](int j, int b) { return c0 + j < n ? region[(c0 + j) * ldp + b] : 0.f; },
+            [&](int j, int b, float v) {
+                if (c0 + j < n) region[(c0 + j) * ldp + b] = v;
+            });
+    }
+    __syncthreads();
+    float *U = qt + g * (int64_t)2 * Q * n;
+    quantile_phase<NT>([&](int k, int b) { return fmaxf(region[k * ldp + b], 0.f); }, L, n, Q,
+                       T.levels, T.TC, d64, Ut, colS, U, partA[0]);
+    quantile_phase<NT>([&](int k, int b) { return fmaxf(-region[k * ldp + b], 0.f); }, L, n, Q,
+                       T.levels, T.TC, d64, Ut, colS, U + (int64_t)Q * n, partA[1]);
+    // smallest part mass over the columns, for the status of the image
+    double mn = INFINITY;
+    int nan = 0;
+    for (int k = wave; k < n; k += NW) {
+        double sp = 0.0, sm = 0.0;
+        for (int b = lane; b < L; b += 64) {
+            const float v = region[k * ldp + b];
+            if (v != v) nan = 1;
+            sp += (double)fmaxf(v, 0.f);
+            sm += (double)fmaxf(-v, 0.f);
+        }
+        sp = wave_sum_d(sp);
+        sm = wave_sum_d(sm);
+        mn = fmin(mn, fmin(sp, sm));
+    }
+    nan = __any(nan);
+    if (lane == 0) {
+        wmin[wave] = mn;
+        wnan[wave] = nan;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && aux) {
+        double m = wmin[0];
+        int nb = wnan[0];
+        for (int w = 1; w < NW; ++w) {
+            m = fmin(m, wmin[w]);
+            nb |= wnan[w];
+        }
+        double *A = aux + 4 * g;
+        A[0] = nb ? __longlong_as_double(0x7ff8000000000000LL) : m;
+        A[1] = partA[0][1] + partA[1][1];
+        A[2] = 0.5 * (partA[0][2] + partA[1][2]);
+        A[3] = 0.5 * (partA[0][3] + partA[1][3]);
+    }
 }
 
 // Bytes of LDS the fused kernel needs for a geometry (0 when it cannot run).
@@ -100,6 +187,73 @@ hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t
     if (tpw <= 8) return launch_tables_t<256, 8>(img, N, T, lds, t, qt, aux, s);
     if (tpw <= 12) return launch_tables_t<256, 12>(img, N, T, lds, t, qt, aux, s);
     return launch_tables_t<256, 20>(img, N, T, lds, t, qt, aux, s);
+}
+
+}  // namespace sw
+
+namespace sw {
+
+// LDS of the fused ramp-filtered kernel: the PMF with stride L + 4, the
+// column sums, the quantile tile and the filter table; two 512-thread blocks
+// per CU when it fits 79 KiB.  0 when the geometry has no fused form (the
+// kernel is instantiated for LP = 64 and 128).
+static size_t tables_rf_lds_bytes(Geo g, TablesShape *out) {
+    TablesShape T;
+    T.P = proj_shape(g.L, g.n);
+    T.Q = g.Q;
+    T.levels = g.levels;
+    const int LP = ramp_padded_length(g.L);
+    if (LP != 64 && LP != 128) return 0;
+    if (tasks_per_wave(T.P.ntasks, 512) > 6) return 0;
+    int region = kStripFloats;
+    if (region < g.n * (g.L + 4)) region = g.n * (g.L + 4);
+    region = (region + 1) & ~1;
+    T.region_floats = region;
+    const size_t fixed =
+        sizeof(float) * region + sizeof(double) * 2 * g.n + sizeof(float) * (2 * LP - 1);
+    const size_t budget = 79 * 1024;
+    if (fixed + sizeof(float) * g.Q * 9 > budget) return 0;
+    T.TC = pick_tc(g.n, g.Q, budget - fixed);
+    if (out) *out = T;
+    return fixed + sizeof(float) * g.Q * (T.TC + 1);
+}
+
+bool tables_rf_fused_fits(Geo g) { return tables_rf_lds_bytes(g, nullptr) != 0; }
+
+template <int NT, int TPW, int NS>
+static hipError_t launch_tables_rf_t(const float *img, int64_t N, const TablesShape &T, size_t lds,
+                                     const AngleTable &t, const float *hx, float *qt, double *aux,
+                                     hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_tables_rf<NT, TPW, NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        152 * 1024);
+    (void)attr;
+    hipLaunchKernelGGL((k_tables_rf<NT, TPW, NS>), dim3((unsigned)N), dim3(NT), lds, s, img, N, T,
+                       t.d32, t.d64, hx, qt, aux);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable &t,
+                            const ProjPlan &pp, const float *hx, float *qt, double *aux,
+                            hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    TablesShape T;
+    const size_t lds = tables_rf_lds_bytes(g, &T);
+    if (lds == 0) return hipErrorInvalidValue;  // caller checks tables_rf_fused_fits first
+    if (pp.L != g.L || pp.n != g.n || pp.ntasks != proj_ntasks(g.L, g.n))
+        return hipErrorInvalidValue;
+    T.P.perm = pp.perm;
+    T.P.trow = pp.trow;
+    const int w = tasks_per_wave(T.P.ntasks, 512);
+    const int LP = ramp_padded_length(g.L);
+    if (LP == 64) {
+        if (w <= 2) return launch_tables_rf_t<512, 2, 16>(img, N, T, lds, t, hx, qt, aux, s);
+        if (w <= 4) return launch_tables_rf_t<512, 4, 16>(img, N, T, lds, t, hx, qt, aux, s);
+        return launch_tables_rf_t<512, 6, 16>(img, N, T, lds, t, hx, qt, aux, s);
+    }
+    if (w <= 2) return launch_tables_rf_t<512, 2, 32>(img, N, T, lds, t, hx, qt, aux, s);
+    if (w <= 4) return launch_tables_rf_t<512, 4, 32>(img, N, T, lds, t, hx, qt, aux, s);
+    return launch_tables_rf_t<512, 6, 32>(img, N, T, lds, t, hx, qt, aux, s);
 }
 
 }  // namespace sw

@@ -639,6 +639,10 @@ sw_status sw_tables_rf(void *ctx, const float *img, int64_t N, const sw_geom *g,
     if ((st = get_ramp_table(c, geo.L, &hx)) != SW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const bool small = c->small(N);
+    if (!small && sw::tables_rf_fused_fits(geo)) {
+        hipError_t e = sw::launch_tables_rf(img, N, geo, *t, *pp, hx, qt, aux, s);
+        return e == hipSuccess ? SW_OK : hip_fail(e, "k_tables_rf launch");
+    }
     // projections of a chunk of images in scratch, filtered in place, then
     // split and inverted
     const size_t per = sizeof(float) * (size_t)geo.n * geo.L;

@@ -140,3 +140,16 @@ def test_rf_status_and_validation(api, ctx):
     assert list(r["status"]) == [0, 1, 2]
     with pytest.raises(SwError):
         api.tables(ctx, dev(imgs), 32, 384, ramp=True)
+
+
+@pytest.mark.parametrize("L,n,Q", [(64, 64, 64), (128, 128, 128), (60, 48, 36), (120, 96, 64)])
+def test_tables_rf_fused_equals_staged(api, ctx, L, n, Q):
+    """The fused ramp-filtered tables kernel (projection, filter and both
+    inversions in LDS) gives bitwise the tables and aux of sw_project,
+    sw_ramp and sw_quantiles_rf in sequence."""
+    _, imgs = blob_stack(L, 6, 1300 + L)
+    x = dev(imgs)
+    q1, a1 = api.tables(ctx, x, n, Q, ramp=True)
+    q2, a2 = api.quantiles(ctx, api.ramp(ctx, api.project(ctx, x, n)), Q, ramp=True)
+    assert np.array_equal(q1.cpu().numpy(), q2.cpu().numpy())
+    assert np.array_equal(a1.cpu().numpy(), a2.cpu().numpy())
