@@ -22,6 +22,7 @@ LEVELS_MIDPOINT = 0
 LEVELS_LEFT = 1
 MODE_ROT_TRANS = 0
 MODE_ROT_ONLY = 1
+MODE_MAX_SLICED = 2
 STATUS_OK = 0
 STATUS_ZERO_MASS = 1
 STATUS_NONFINITE = 2

@@ -342,6 +342,27 @@ static double oracle_objective(const double *U, const double *V, int n, int Q, i
     return acc / ((double)n * (double)Q);
 }
 
+/* Max-sliced objective at lag l (extended alignment results: the max-sliced
+   W2 over the equispaced slices, the norm of U - V taken over columns):
+     M(l) = max_k (1/Q) sum_j (U[j][k] - V[j][(k+l) mod n])^2,
+   the largest per-angle W2^2 between f and R_{theta_l} g.  Rotation only:
+   the shift that minimises a maximum has no closed form. */
+static double oracle_max_sliced(const double *U, const double *V, int n, int Q, int rows, int l)
+{
+    double best = 0.0;
+    for (int k = 0; k < n; ++k) {
+        int kl = (k + l) % n;
+        double acc = 0.0;
+        for (int j = 0; j < rows; ++j) {
+            double r = U[(int64_t)j * n + k] - V[(int64_t)j * n + kl];
+            acc += r * r;
+        }
+        acc /= (double)Q;
+        if (acc > best) best = acc;
+    }
+    return best;
+}
+
 /* a6-a10: exhaustive search over the rotation grid with the least-squares
    translation at every rotation, then the argmin (Sec. 2.3, discrete SW2
    over rotations; Thm 3.2 for the translation).
@@ -350,6 +371,7 @@ static double oracle_objective(const double *U, const double *V, int n, int Q, i
      s*(l) = 2 b(l)       (minimiser of D(l, .), using sum_k d_k d_k^T = (n/2) I)
      D*(l) = D(l, s*(l))  (mode 0, rotation + translation)
      D*(l) = D(l, 0)      (mode 1, rotation only: the paper's own objective)
+     D*(l) = M(l)         (mode 2, max-sliced, rotation only, s* = 0)
    (With `rows` table rows and the 1/(nQ) normalisation,
    D(l, s) = D(l, 0) - (2 rows/Q) s.b(l) + (rows/(2Q)) |s|^2, so s*(l) = 2 b(l)
    for the stacked ramp-filtered tables as well.)
@@ -413,7 +435,8 @@ void oracle_align_rows(const double *ref_qt, const double *ref_aux, int64_t n_re
                 sx = 2.0 * bx / (double)n;
                 sy = 2.0 * by / (double)n;
             }
-            double d = oracle_objective(U, V, n, Q, rows, l, sx, sy, cs, sn);
+            double d = mode == 2 ? oracle_max_sliced(U, V, n, Q, rows, l)
+                                 : oracle_objective(U, V, n, Q, rows, l, sx, sy, cs, sn);
             if (curve) curve[p * n + l] = d;
             if (best < 0 || d < bestd) {
                 best = l;

@@ -501,3 +501,53 @@ def test_ramp_quarter_turns_recovered_exactly(oracle, m):
     assert r["status"][0] == 0
     assert r["rot_index"][0] == (m * n // 4) % n or r["rot_index"][0] == (-m * n // 4) % n
     assert r["sw2sq"][0] < 1e-20
+
+
+# ---------------------------------------------------------------- max-sliced SW2
+def test_max_sliced_bounds_and_self(oracle):
+    """The largest per-angle W2^2 is at least the mean over angles (the SW2
+    rotation-only objective) at every lag, at most n times it, and zero on a
+    self pair.  Catches a missing 1/Q, a sum instead of a max, or a wrong
+    column pairing."""
+    L, n = 32, 24
+    f, g = blob_img(L, seed=51), blob_img(L, seed=52)
+    rq, ra = oracle.tables(f, n, n)
+    iq, ia = oracle.tables(g, n, n)
+    m = oracle.align(rq, ra, iq, ia, L, mode=oracle.MODE_MAX_SLICED, want_curve=True)
+    s = oracle.align(rq, ra, iq, ia, L, mode=oracle.MODE_ROT_ONLY, want_curve=True)
+    assert np.all(m["curve"][0] >= s["curve"][0] - 1e-15)
+    assert np.all(m["curve"][0] <= n * s["curve"][0] + 1e-15)
+    assert np.all(m["shift_px"] == 0.0)
+    z = oracle.align(rq, ra, rq, ra, L, mode=oracle.MODE_MAX_SLICED)
+    assert z["rot_index"][0] == 0 and z["sw2sq"][0] == 0.0
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_max_sliced_quarter_turns(oracle, m):
+    """A 90-degree rotation is an exact column shift, so the max-sliced
+    objective vanishes at l = m n/4."""
+    L, n = 32, 16
+    f = blob_img(L, seed=53)
+    g = np.ascontiguousarray(np.rot90(f, m))
+    r = oracle.align_images(f, g[None], n, n, mode=oracle.MODE_MAX_SLICED)
+    assert r["rot_index"][0] in ((m * n // 4) % n, (-m * n // 4) % n)
+    assert r["sw2sq"][0] < 1e-20
+
+
+def test_max_sliced_translation(oracle):
+    """f against f shifted by t: every slice is shifted by t.d_k, so its W2^2
+    is (t.d_k)^2 (1-D W2 between a density and its translate), and the max
+    over angles is |t|^2 when t lies along a detector direction (here d_0 =
+    (1, 0)): twice the SW2 value |t|^2/2 of Thm 3.2.  Smooth re-rendered
+    blobs, discretisation error shrinking with L."""
+    t = np.array([0.08, 0.0])
+    errs = []
+    for L in (32, 64, 128):
+        rng = np.random.Generator(np.random.PCG64(6))
+        cen, sig, amp = synth.blob_params(rng, 3, L, spread=0.3, sig_px=(2, 4))
+        sig = np.full(3, 0.09)
+        f = synth.finish(synth.render(cen, sig, amp, L), L)
+        g = synth.finish(synth.render(cen + t, sig, amp, L), L)
+        r = oracle.align_images(f, g[None], L, L, mode=oracle.MODE_MAX_SLICED, want_curve=True)
+        errs.append(abs(r["curve"][0, 0] - t @ t) / (t @ t))
+    assert errs[-1] < 0.02 and errs[-1] < errs[0], errs
