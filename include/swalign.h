@@ -68,8 +68,14 @@ typedef enum {
 typedef enum { SW_LEVELS_MIDPOINT = 0, SW_LEVELS_LEFT = 1 } sw_levels;
 
 /* Rotation + closed-form translation (default), or rotation only, which is
-   the paper's own objective (Sec. 2.3, discrete SW2 over rotations). */
-typedef enum { SW_MODE_ROT_TRANS = 0, SW_MODE_ROT_ONLY = 1 } sw_mode;
+   the paper's own objective (Sec. 2.3, discrete SW2 over rotations), or the
+   max-sliced objective, rotation only (extended alignment results: the
+   largest per-angle W2^2 instead of the mean, M(l) = max_k (1/Q) sum_j
+   (U[j][k] - V[j][(k+l) mod n])^2; the shift is reported as 0).  The
+   max-sliced mode takes n_angles = 64 or 128; its top_k lags (from an FP32
+   matrix-core estimate of every lag) are rescored as direct residuals, and
+   the curve holds the estimate. */
+typedef enum { SW_MODE_ROT_TRANS = 0, SW_MODE_ROT_ONLY = 1, SW_MODE_MAX_SLICED = 2 } sw_mode;
 
 /* FP32 everywhere, or FP32 tables with a BF16 correlation (FP32 accumulate)
    and an FP32 rescore of the top_k lags. */
@@ -112,6 +118,14 @@ typedef struct {
    LDS-FFT pair kernel for n_angles = 128 instead of the register-FFT one
    (the two agree to FP32 rounding).  The first two change launch shapes
    only, never results. */
+/* Scratch: the context owns one scratch buffer (grown on demand) that the
+   calls needing it share: sw_tables / sw_tables_rf when they take their
+   chunked or small-batch path, sw_align_batch (except the max-sliced mode)
+   and sw_align_stacks; sw_project, sw_ramp, sw_quantiles and
+   sw_quantiles_rf never.  Calls on different streams may overlap
+   only when at most one of them uses scratch (e.g. the tables of a single
+   reference on a side stream next to the fused tables of a large image
+   batch); otherwise order them with events. */
 sw_status sw_ctx_create(void **ctx, int device, const char *tune_json);
 sw_status sw_ctx_destroy(void *ctx);
 const char *sw_last_error(void);

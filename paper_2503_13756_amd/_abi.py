@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libswalign.so")
 SW_OK, SW_NOT_READY, SW_E_INVALID, SW_E_NOMEM, SW_E_DEVICE, SW_E_UNSUPPORTED, SW_E_BUSY = (
     0, 1, -1, -2, -3, -4, -5)
 LEVELS_MIDPOINT, LEVELS_LEFT = 0, 1
-MODE_ROT_TRANS, MODE_ROT_ONLY = 0, 1
+MODE_ROT_TRANS, MODE_ROT_ONLY, MODE_MAX_SLICED = 0, 1, 2
 PREC_FP32, PREC_BF16_SPLIT = 0, 1
 FILTER_NONE, FILTER_RAMP = 0, 1
 RESULT_OK, RESULT_ZERO_MASS, RESULT_NONFINITE = 0, 1, 2

@@ -690,8 +690,12 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
         return fail(SW_E_INVALID, "a table, aux or output pointer is NULL");
     if (b->n_ref == 0 || b->n_img == 0)
         return fail(SW_E_INVALID, "pairs given but a table set is empty");
-    if (b->mode != SW_MODE_ROT_TRANS && b->mode != SW_MODE_ROT_ONLY)
+    if (b->mode != SW_MODE_ROT_TRANS && b->mode != SW_MODE_ROT_ONLY &&
+        b->mode != SW_MODE_MAX_SLICED)
         return fail(SW_E_INVALID, "mode = %d is not a sw_mode value", b->mode);
+    if (b->mode == SW_MODE_MAX_SLICED && !sw::msw_supported(geo))
+        return fail(SW_E_UNSUPPORTED, "max-sliced alignment needs n_angles = 64 or 128, got %d",
+                    geo.n);
     if (b->prec != SW_PREC_FP32 && b->prec != SW_PREC_BF16_SPLIT)
         return fail(SW_E_INVALID, "prec = %d is not a sw_precision value", b->prec);
     int top_k = b->top_k;
@@ -705,6 +709,28 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
     const sw::AngleTable *t;
     if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    if (b->mode == SW_MODE_MAX_SLICED) {
+        sw::PairArgs a{};
+        a.ref_qt = b->ref_qt;
+        a.ref_aux = b->ref_aux;
+        a.n_ref = b->n_ref;
+        a.img_qt = b->img_qt;
+        a.img_aux = b->img_aux;
+        a.n_img = b->n_img;
+        a.pairs = b->pairs;
+        a.n_pairs = b->n_pairs;
+        a.mode = b->mode;
+        a.top_k = top_k;
+        a.out = (sw::Result *)out;
+        a.curve = curve;
+        hipError_t e = sw::launch_align_msw(a, geo, s);
+        if (e != hipSuccess) return hip_fail(e, "k_align_msw launch");
+        if (ramp) {
+            e = sw::launch_scale_results((sw::Result *)out, P, curve, geo.n, 2.f, s);
+            if (e != hipSuccess) return hip_fail(e, "k_scale_results launch");
+        }
+        return SW_OK;
+    }
     const int Wn = geo.n / 2 + 1;
     const bool same_set = b->ref_qt == b->img_qt && b->ref_aux == b->img_aux && b->n_ref == b->n_img;
     if (!b->pairs && !curve && b->prec == SW_PREC_BF16_SPLIT && top_k <= 4 &&

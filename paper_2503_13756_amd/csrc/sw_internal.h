@@ -118,6 +118,9 @@ struct PairArgs {
     float *curve;  // nullable
 };
 hipError_t launch_align_pairs(const PairArgs &a, Geo g, const AngleTable &t, hipStream_t s);
+// Max-sliced alignment (rotation only) of every pair: n = 64 or 128.
+bool msw_supported(Geo g);
+hipError_t launch_align_msw(const PairArgs &a, Geo g, hipStream_t s);
 // The same for n = 128 with register-resident angle FFTs; needs a coefficient
 // scratch of align128_scratch_bytes() (a.ref_spec must hold the references'
 // FP32 spectra).
