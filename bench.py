@@ -350,10 +350,10 @@ def ramp_parity(w, r32, r16, L, n, Q, S=1000):
     S = min(S, len(w["imgs"]))
     o = O.align_images(w["ref"], w["imgs"][:S], n, Q, want_curve=True, ramp=True)
     out = {"pairs": S}
-    for name, r, tau in (("fp32", r32, parity.TAU_FP32), ("bf16_split", r16, parity.TAU_BF16)):
+    for name, r in (("fp32", r32), ("bf16_split", r16)):
         sub = {k: v[:S] for k, v in r.items()}
         try:
-            rep = parity.check(sub, o, L, tau, o["curve"])
+            rep = parity.check(sub, o, L, parity.TAU_RF, o["curve"])
             out[name] = f"{rep['pairs']} pairs ok, exact rotation {rep['exact_rot']}"
         except AssertionError as e:
             out[name] = "FAILED: " + str(e)[:300]

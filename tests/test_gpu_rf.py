@@ -95,8 +95,7 @@ def test_rf_end_to_end_parity(api, ctx, oracle, L, n, Q, mode, prec, top_k):
     oq, oa = oracle.tables(ref[None], n, Q, ramp=True)
     iq0, ia0 = oracle.tables(imgs, n, Q, ramp=True)
     o = oracle.align(oq, oa, iq0, ia0, L, mode=mode, want_curve=True, ramp=True)
-    tau = parity.TAU_FP32 if prec == 0 else parity.TAU_BF16
-    parity.check(g, o, L, tau, o["curve"])
+    parity.check(g, o, L, parity.TAU_RF, o["curve"])
     # the curve is the ramp-filtered objective too: FP32 to a small fraction
     # of its scale; with the BF16 correlation to bfloat16 rounding of the
     # energy term (E_U + E_V) / (nQ) it is computed from

@@ -551,3 +551,29 @@ def test_max_sliced_translation(oracle):
         r = oracle.align_images(f, g[None], L, L, mode=oracle.MODE_MAX_SLICED, want_curve=True)
         errs.append(abs(r["curve"][0, 0] - t @ t) / (t @ t))
     assert errs[-1] < 0.02 and errs[-1] < errs[0], errs
+
+
+def test_ramp_distance_sensitivity(oracle):
+    """Why the ramp-filtered parity tolerance is looser than SW2's: perturb
+    the projections at FP32 level (rounding to float32 and 2e-7 relative
+    noise) and compare the distances before and after.  SW2 moves by ~1e-8
+    relative; the ramp-filtered distance, whose signed parts have near-empty
+    gaps where the inverse CDF jumps, by one to three orders of magnitude
+    more (the ratio depends on the images and L)."""
+    L = n = Q = 128
+    _, imgs = synth.make_stack(1010, L, 60, K=8, shift_px=8.0, jitter_px=2.0, snr=1.0)[:2]
+    P, _ = oracle.project(imgs, n)
+    rng = np.random.default_rng(0)
+    P2 = P.astype(np.float32).astype(np.float64) * (1 + rng.normal(0, 2e-7, P.shape))
+    out = {}
+    for ramp in (False, True):
+        tab = (lambda x: oracle.quantiles_rf(oracle.ramp(x), Q)) if ramp else \
+            (lambda x: oracle.quantiles(x, Q))
+        q1, a1 = tab(P)
+        q2, a2 = tab(P2)
+        r1 = oracle.align(q1[:1], a1[:1], q1, a1, L, ramp=ramp)
+        r2 = oracle.align(q2[:1], a2[:1], q2, a2, L, ramp=ramp)
+        same = (r1["rot_index"] == r2["rot_index"]) & (r1["sw2sq"] > 0)
+        out[ramp] = (np.abs(r1["sw2sq"] - r2["sw2sq"])[same] / r1["sw2sq"][same]).max()
+    assert out[False] < 1e-6, out
+    assert out[True] > 30 * out[False], out
