@@ -75,6 +75,7 @@ hipError_t launch_project(const float *img, int64_t N, Geo g, const AngleTable &
     const int w512 = tasks_per_wave(P.ntasks, 512);
     if (w512 <= 2) return launch_project_t<512, 2>(img, N, P, t.d32, pmf, s);
     if (w512 <= 4) return launch_project_t<512, 4>(img, N, P, t.d32, pmf, s);
+    if (w512 <= 5) return launch_project_t<512, 5>(img, N, P, t.d32, pmf, s);
     if (w512 <= 6) return launch_project_t<512, 6>(img, N, P, t.d32, pmf, s);
     if (w512 <= 9) return launch_project_t<512, 9>(img, N, P, t.d32, pmf, s);
     const int w1024 = tasks_per_wave(P.ntasks, 1024);

@@ -175,6 +175,7 @@ hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t
         const int w = tasks_per_wave(T.P.ntasks, 512);
         if (w <= 2) return launch_tables_t<512, 2>(img, N, T, lds, t, qt, aux, s);
         if (w <= 4) return launch_tables_t<512, 4>(img, N, T, lds, t, qt, aux, s);
+        if (w <= 5) return launch_tables_t<512, 5>(img, N, T, lds, t, qt, aux, s);
         if (w <= 6) return launch_tables_t<512, 6>(img, N, T, lds, t, qt, aux, s);
         if (w <= 9) return launch_tables_t<512, 9>(img, N, T, lds, t, qt, aux, s);
     }
@@ -249,10 +250,12 @@ hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable
     if (LP == 64) {
         if (w <= 2) return launch_tables_rf_t<512, 2, 16>(img, N, T, lds, t, hx, qt, aux, s);
         if (w <= 4) return launch_tables_rf_t<512, 4, 16>(img, N, T, lds, t, hx, qt, aux, s);
+        if (w <= 5) return launch_tables_rf_t<512, 5, 16>(img, N, T, lds, t, hx, qt, aux, s);
         return launch_tables_rf_t<512, 6, 16>(img, N, T, lds, t, hx, qt, aux, s);
     }
     if (w <= 2) return launch_tables_rf_t<512, 2, 32>(img, N, T, lds, t, hx, qt, aux, s);
     if (w <= 4) return launch_tables_rf_t<512, 4, 32>(img, N, T, lds, t, hx, qt, aux, s);
+    if (w <= 5) return launch_tables_rf_t<512, 5, 32>(img, N, T, lds, t, hx, qt, aux, s);
     return launch_tables_rf_t<512, 6, 32>(img, N, T, lds, t, hx, qt, aux, s);
 }
 

@@ -80,8 +80,11 @@ __device__ __forceinline__ float lane_prev(float v) {
 // is read through a buffer resource covering exactly this image: loads are
 // range-checked by the hardware (out-of-range offsets read 0) and go out
 // unconditionally; every element outside the image lies outside the disk
-// and is masked.  A non-finite pixel sets `bad`.
-template <int NT>
+// and is masked.  A non-finite pixel sets `bad`.  B entry groups are loaded
+// before the first of them is used, so a strip costs a few memory latencies
+// rather than one per group; loads past the strip read inside the image or
+// return zero and are never written.
+template <int NT, int B>
 __device__ void stage_strip(const float *__restrict__ F, const ProjShape &P, int i0, int rows,
                             float *lds, int &bad) {
     constexpr int NW = NT / 64, STEP = 64 - kStripPad;
@@ -92,22 +95,36 @@ __device__ void stage_strip(const float *__restrict__ F, const ProjShape &P, int
     const __amdgpu_buffer_rsrc_t img =
         __builtin_amdgcn_make_buffer_rsrc((void *)F, (short)0, 4 * L * L, 0x00020000);
     float nf = 0.f;  // becomes NaN once a non-finite pixel is read
-#pragma unroll
+#pragma unroll 1
     for (int kind = 0; kind < 2; ++kind) {
         float *dst = lds + kind * kKindFloats;
-        for (int f0 = wave * STEP; f0 + kStripPad < total; f0 += NW * STEP) {
-            const int f = f0 + lane;
-            const int r = (int)fmaf((float)f, invW, 0.5f * invW);
-            const int j = f - __mul24(r, W) - kStripPad;
-            const int i = i0 + r;
-            const int off = kind == 0 ? 4 * (__mul24(i, L) + j) : 4 * (__mul24(j, L) + i);
-            const float x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off, 0, 0));
-            nf = fmaf(x, 0.f, nf);
-            const int a = 2 * j - L + 1, b = 2 * i - L + 1;
-            const float v = (__mul24(a, a) + __mul24(b, b) <= rr2) ? fmaxf(x, 0.f) : 0.f;
-            const float v1 = lane_prev(v), v2 = lane_prev(v1), v3 = lane_prev(v2);
-            if (lane >= kStripPad && f < total && j >= 0)
-                *(float4 *)(dst + __mul24(r, RS) + 4 * j) = make_float4(v3, v2, v1, v);
+#pragma unroll 1
+        for (int g0 = wave * STEP; g0 + kStripPad < total; g0 += B * NW * STEP) {
+            float x[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int f = g0 + u * NW * STEP + lane;
+                const int r = (int)fmaf((float)f, invW, 0.5f * invW);
+                const int j = f - __mul24(r, W) - kStripPad;
+                const int i = i0 + r;
+                const int off = kind == 0 ? 4 * (__mul24(i, L) + j) : 4 * (__mul24(j, L) + i);
+                x[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off, 0, 0));
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int f0 = g0 + u * NW * STEP;
+                if (f0 + kStripPad >= total) break;  // wave-uniform
+                const int f = f0 + lane;
+                const int r = (int)fmaf((float)f, invW, 0.5f * invW);
+                const int j = f - __mul24(r, W) - kStripPad;
+                const int i = i0 + r;
+                nf = fmaf(x[u], 0.f, nf);
+                const int a = 2 * j - L + 1, b = 2 * i - L + 1;
+                const float v = (__mul24(a, a) + __mul24(b, b) <= rr2) ? fmaxf(x[u], 0.f) : 0.f;
+                const float v1 = lane_prev(v), v2 = lane_prev(v1), v3 = lane_prev(v2);
+                if (lane >= kStripPad && f < total && j >= 0)
+                    *(float4 *)(dst + __mul24(r, RS) + 4 * j) = make_float4(v3, v2, v1, v);
+            }
         }
     }
     if (nf != 0.f) bad = 1;
@@ -282,7 +299,9 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
     for (int i0 = 0; i0 < P.L; i0 += P.R) {
         const int rows = min(P.R, P.L - i0);
         __syncthreads();
-        stage_strip<NT>(F, P, i0, rows, lds, bad);
+        // a batch of six groups covers a whole L = 128 strip; more tasks per
+        // wave leave registers for four
+        stage_strip<NT, TPW <= 5 ? 6 : 4>(F, P, i0, rows, lds, bad);
         __syncthreads();
         accumulate_strip<TPW>(P, tasks, lds, i0, rows, acc, my_tasks);
     }
