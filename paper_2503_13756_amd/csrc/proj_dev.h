@@ -78,52 +78,93 @@ __device__ __forceinline__ float lane_prev(float v) {
 // writes chunk j from its own element and those of the three lanes before
 // it (DPP shifts), so consecutive waves overlap by three entries.  The image
 // is read through a buffer resource covering exactly this image: loads are
-// range-checked by the hardware (out-of-range offsets read 0) and go out
-// unconditionally; every element outside the image lies outside the disk
-// and is masked.  A non-finite pixel sets `bad`.  B entry groups are loaded
-// before the first of them is used, so a strip costs a few memory latencies
-// rather than one per group; loads past the strip read inside the image or
-// return zero and are never written.
-template <int NT, int B>
-__device__ void stage_strip(const float *__restrict__ F, const ProjShape &P, int i0, int rows,
-                            float *lds, int &bad) {
-    constexpr int NW = NT / 64, STEP = 64 - kStripPad;
-    const int L = P.L, RS = P.RS, W = P.S + kStripPad, total = rows * W;
-    const int rr2 = (L - 2) * (L - 2);
-    const float invW = 1.f / (float)W;  // entry -> strip row, exact for these sizes
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// range-checked by the hardware (out-of-range offsets read 0); every element
+// outside the image lies outside the disk and is masked.
+//
+// Staging is split in two: strip_load issues the loads of a strip into
+// registers and strip_store writes them to LDS, so that the loads of the
+// next strip are in flight while the current one is accumulated.
+//
+// Entries per kind are rows (S + 3) <= 2048 + 3 rows (rows * 4S fits in
+// kKindFloats) and rows <= min(L, 2048 / (L + 4)) <= 43, so at most
+// kStripEntries; a wave takes at most strip_groups of them.
+constexpr int kStripEntries = kKindFloats / 4 + 3 * 43;
+template <int NT>
+__host__ __device__ constexpr int strip_groups() {
+    return (kStripEntries - kStripPad + (NT / 64) * (64 - kStripPad) - 1) /
+           ((NT / 64) * (64 - kStripPad));
+}
+
+template <int NT>
+struct StripRegs {
+    float x[2][strip_groups<NT>()];
+};
+
+// Entry f of a strip with W entries per row: strip row r and element j.
+__device__ __forceinline__ void strip_entry(int f, int W, float invW, int &r, int &j) {
+    r = (int)fmaf((float)f, invW, 0.5f * invW);  // exact for these sizes
+    j = f - __mul24(r, W) - kStripPad;
+}
+
+template <int NT>
+__device__ __forceinline__ void strip_load(const float *__restrict__ F, const ProjShape &P,
+                                           int i0, int rows, StripRegs<NT> &R) {
+    constexpr int NW = NT / 64, STEP = 64 - kStripPad, G = strip_groups<NT>();
+    const int L = P.L, W = P.S + kStripPad, total = rows * W;
+    const float invW = 1.f / (float)W;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the lane index is made opaque here, so that the entry arithmetic is
+    // redone per strip rather than kept live in registers across strips
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
     const __amdgpu_buffer_rsrc_t img =
         __builtin_amdgcn_make_buffer_rsrc((void *)F, (short)0, 4 * L * L, 0x00020000);
+#pragma unroll
+    for (int it = 0; it < G; ++it) {
+        const int f0 = wave * STEP + it * NW * STEP;
+        if (f0 + kStripPad < total) {  // wave-uniform
+            int r, j;
+            strip_entry(f0 + lane, W, invW, r, j);
+            const int i = i0 + r;
+            R.x[0][it] = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(img, 4 * (__mul24(i, L) + j), 0, 0));
+            R.x[1][it] = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(img, 4 * (__mul24(j, L) + i), 0, 0));
+        }
+    }
+}
+
+// Writes the strip loaded by strip_load; a non-finite pixel sets `bad`.
+template <int NT>
+__device__ __forceinline__ void strip_store(const ProjShape &P, int i0, int rows,
+                                            const StripRegs<NT> &R, float *lds, int &bad) {
+    constexpr int NW = NT / 64, STEP = 64 - kStripPad, G = strip_groups<NT>();
+    const int L = P.L, RS = P.RS, W = P.S + kStripPad, total = rows * W;
+    const int rr2 = (L - 2) * (L - 2);
+    const float invW = 1.f / (float)W;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
     float nf = 0.f;  // becomes NaN once a non-finite pixel is read
-#pragma unroll 1
-    for (int kind = 0; kind < 2; ++kind) {
-        float *dst = lds + kind * kKindFloats;
-#pragma unroll 1
-        for (int g0 = wave * STEP; g0 + kStripPad < total; g0 += B * NW * STEP) {
-            float x[B];
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const int f = g0 + u * NW * STEP + lane;
-                const int r = (int)fmaf((float)f, invW, 0.5f * invW);
-                const int j = f - __mul24(r, W) - kStripPad;
-                const int i = i0 + r;
-                const int off = kind == 0 ? 4 * (__mul24(i, L) + j) : 4 * (__mul24(j, L) + i);
-                x[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, off, 0, 0));
-            }
+    for (int it = 0; it < G; ++it) {
+        const int f0 = wave * STEP + it * NW * STEP;
+        if (f0 + kStripPad < total) {  // wave-uniform
+            const int f = f0 + lane;
+            int r, j;
+            strip_entry(f, W, invW, r, j);
+            const int a = 2 * j - L + 1, b = 2 * (i0 + r) - L + 1;
+            const bool keep = lane >= kStripPad && f < total && j >= 0;
+            const bool disk = __mul24(a, a) + __mul24(b, b) <= rr2;
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const int f0 = g0 + u * NW * STEP;
-                if (f0 + kStripPad >= total) break;  // wave-uniform
-                const int f = f0 + lane;
-                const int r = (int)fmaf((float)f, invW, 0.5f * invW);
-                const int j = f - __mul24(r, W) - kStripPad;
-                const int i = i0 + r;
-                nf = fmaf(x[u], 0.f, nf);
-                const int a = 2 * j - L + 1, b = 2 * i - L + 1;
-                const float v = (__mul24(a, a) + __mul24(b, b) <= rr2) ? fmaxf(x[u], 0.f) : 0.f;
+            for (int kind = 0; kind < 2; ++kind) {
+                const float x = R.x[kind][it];
+                nf = fmaf(x, 0.f, nf);
+                const float v = disk ? fmaxf(x, 0.f) : 0.f;
                 const float v1 = lane_prev(v), v2 = lane_prev(v1), v3 = lane_prev(v2);
-                if (lane >= kStripPad && f < total && j >= 0)
-                    *(float4 *)(dst + __mul24(r, RS) + 4 * j) = make_float4(v3, v2, v1, v);
+                if (keep)
+                    *(float4 *)(lds + kind * kKindFloats + __mul24(r, RS) + 4 * j) =
+                        make_float4(v3, v2, v1, v);
             }
         }
     }
@@ -141,10 +182,10 @@ typedef const __attribute__((address_space(3))) f32x4v LdsF4;
 
 // Per-lane constants of one task (slot angle, bin): c = cos theta, the
 // column step r = tan theta per row, A3 = u(0) - 1/c + 3 (u(i) = A3' + i r is
-// the column where the line of bin b crosses row i) and k1 = 2 - 1/c; A3 and
-// k1 are rounded once from FP64.
+// the column where the line of bin b crosses row i) and k1 = 2 - 1/c; A3, A3n
+// and k1 are rounded once from FP64.
 struct LaneTask {
-    float c, r, A3, k1;
+    float c, r, A3, A3n, k1;  // A3n: A3 + r, the offset of the next row
     int rlo, rhi;  // rows the task reads (wave-uniform)
 };
 
@@ -173,20 +214,52 @@ __device__ __forceinline__ LaneTask make_task(const ProjShape &P, const float2 *
         t.c = c;
         t.r = s / c;
         const double ic = 1.0 / (double)c;
-        t.A3 = (float)(((double)b - c0 - 1.0) * ic + c0 + 3.0 - c0 * (double)t.r);
+        const double a3 = ((double)b - c0 - 1.0) * ic + c0 + 3.0 - c0 * (double)t.r;
+        t.A3 = (float)a3;
+        t.A3n = (float)(a3 + (double)t.r);
         t.k1 = (float)(2.0 - ic);
     } else {
         t.c = 1.f;
         t.r = 0.f;
         t.A3 = -100.f;  // clamps to the zero padding
+        t.A3n = -100.f;
         t.k1 = 1.f;
     }
     return t;
 }
 
+// One row of one task: the three hat weights of the line at column position
+// um (shifted by 3, see below) and the twelve multiply-adds of the four
+// variants.  ka / kc are the LDS byte addresses of the windows starting at
+// elements -2 and L - 1 of the row; s16 = 16 and m16 = -16 arrive at run
+// time, so that each address is one 24-bit multiply-add.
+__device__ __forceinline__ void accumulate_row(const LaneTask &tk, float k2, float hi3, float um,
+                                               int ka, int kc, int s16, int m16, float &s0,
+                                               float &s1, float &s2, float &s3) {
+    um = __builtin_amdgcn_fmed3f(um, 0.5f, hi3);
+    const float fr = __builtin_amdgcn_fractf(um);  // fractional part, exact
+    const int j2 = (int)um;                        // j0 + 2
+    const float w0 = fmaf(-tk.c, fr, tk.c);                                // column j0
+    const float w1 = fmaf(-tk.c, fabsf(tk.k1 - fr), 1.f);                   // j0 + 1
+    const float w2 = __builtin_amdgcn_fmed3f(fmaf(tk.c, fr, k2), 0.f, 1.f);  // j0 + 2
+    // window j0 .. j0+3 of the row (and of the transposed column) and the
+    // mirrored window L-3-j0 .. L-j0
+    const int pa = __mul24(j2, s16) + ka;
+    const int pc = __mul24(j2, m16) + kc;
+    const f32x4v A = *(const LdsF4 *)(uintptr_t)pa;
+    const f32x4v B = *(const LdsF4 *)(uintptr_t)(pa + 4 * kKindFloats);
+    const f32x4v C = *(const LdsF4 *)(uintptr_t)pc;
+    const f32x4v D = *(const LdsF4 *)(uintptr_t)(pc + 4 * kKindFloats);
+    s0 = fmaf(w2, A.z, fmaf(w1, A.y, fmaf(w0, A.x, s0)));
+    s1 = fmaf(w2, B.z, fmaf(w1, B.y, fmaf(w0, B.x, s1)));
+    s2 = fmaf(w2, C.x, fmaf(w1, C.y, fmaf(w0, C.z, s2)));
+    s3 = fmaf(w2, D.x, fmaf(w1, D.y, fmaf(w0, D.z, s3)));
+}
+
 // Accumulate one LDS strip into the accumulators of this wave's tasks.  Task
-// slots are the outer loop (a wave-uniform guard each) and rows the inner,
-// unrolled loop, so the LDS reads of consecutive rows are in flight together.
+// slots are the outer loop (a wave-uniform guard each) and rows the inner
+// loop, two rows per iteration (the second from A3n, so that the row index
+// steps once per pair), so the LDS reads of both rows are in flight together.
 template <int TPW>
 __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const LaneTask (&tasks)[TPW],
                                                  const float *lds, int i0, int rows,
@@ -195,6 +268,9 @@ __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const LaneT
     const float hi3 = (float)L + 2.f;
     // LDS byte address of the strip buffer
     const int lbase = (int)(uintptr_t)(const __attribute__((address_space(3))) float *)lds;
+    // in vector registers: a multiply-add takes at most one scalar operand
+    int s16, m16;
+    asm volatile("v_mov_b32 %0, 16\n\tv_mov_b32 %1, -16" : "=v"(s16), "=v"(m16));
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         if (t < my_tasks) {  // wave-uniform
@@ -208,36 +284,26 @@ __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const LaneT
             // and j0 stays in [-2, L]: a line clamped there has its whole hat
             // on columns <= 0 or >= L - 1, outside the disk, and so does the
             // clamped position.
-            const float k1 = tk.k1, k2 = 2.f - 3.f * tk.c;
+            const float k2 = 2.f - 3.f * tk.c;
             float s0 = acc[t][0], s1 = acc[t][1], s2 = acc[t][2], s3 = acc[t][3];
             // only the rows of this strip that the task's lines cross
             const int ra = max(tk.rlo - i0, 0), rb = min(tk.rhi - i0 + 1, rows);
             float fi = (float)(i0 + ra);  // row index, exact in FP32
-#pragma unroll 2
-            for (int rr = ra; rr < rb; ++rr, fi += 1.f) {
-                float um = fmaf(fi, tk.r, tk.A3);
-                um = __builtin_amdgcn_fmed3f(um, 0.5f, hi3);
-                const float fr = __builtin_amdgcn_fractf(um);  // fractional part, exact
-                const int j2 = (int)um;                        // j0 + 2
-                const float w0 = fmaf(-tk.c, fr, tk.c);                                // column j0
-                const float w1 = fmaf(-tk.c, fabsf(k1 - fr), 1.f);                      // j0 + 1
-                const float w2 = __builtin_amdgcn_fmed3f(fmaf(tk.c, fr, k2), 0.f, 1.f);  // j0 + 2
-                // LDS byte addresses of the window j0 .. j0+3 of this row (and
-                // of the transposed column) and of the mirrored window
-                // L-3-j0 .. L-j0: one shift-add, and the mirror as one
-                // subtraction from the sum of the two row constants
-                const int ka = lbase + 4 * window_pos(-2, rr * P.RS);  // + 16 j2
+            int rr = ra;
+            for (; rr + 1 < rb; rr += 2, fi += 2.f) {
+                const int ka = lbase + 4 * window_pos(-2, rr * P.RS);
                 const int kc = lbase + 4 * window_pos(L - 1, rr * P.RS);
-                const int pa = (j2 << 4) + ka;
-                const int pc = (ka + kc) - pa;  // kc - 16 j2
-                const f32x4v A = *(const LdsF4 *)(uintptr_t)pa;
-                const f32x4v B = *(const LdsF4 *)(uintptr_t)(pa + 4 * kKindFloats);
-                const f32x4v C = *(const LdsF4 *)(uintptr_t)pc;
-                const f32x4v D = *(const LdsF4 *)(uintptr_t)(pc + 4 * kKindFloats);
-                s0 = fmaf(w2, A.z, fmaf(w1, A.y, fmaf(w0, A.x, s0)));
-                s1 = fmaf(w2, B.z, fmaf(w1, B.y, fmaf(w0, B.x, s1)));
-                s2 = fmaf(w2, C.x, fmaf(w1, C.y, fmaf(w0, C.z, s2)));
-                s3 = fmaf(w2, D.x, fmaf(w1, D.y, fmaf(w0, D.z, s3)));
+                const int kn = 4 * P.RS;  // next row
+                accumulate_row(tk, k2, hi3, fmaf(fi, tk.r, tk.A3), ka, kc, s16, m16, s0, s1, s2,
+                               s3);
+                accumulate_row(tk, k2, hi3, fmaf(fi, tk.r, tk.A3n), ka + kn, kc + kn, s16, m16,
+                               s0, s1, s2, s3);
+            }
+            if (rr < rb) {
+                const int ka = lbase + 4 * window_pos(-2, rr * P.RS);
+                const int kc = lbase + 4 * window_pos(L - 1, rr * P.RS);
+                accumulate_row(tk, k2, hi3, fmaf(fi, tk.r, tk.A3), ka, kc, s16, m16, s0, s1, s2,
+                               s3);
             }
             acc[t][0] = s0;
             acc[t][1] = s1;
@@ -285,7 +351,7 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
                               const float2 *__restrict__ dtab, float *lds, int tg0, int &bad_out,
                               Emit emit) {
     constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float acc[TPW][4];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0.f;
@@ -296,13 +362,15 @@ __device__ void project_group(const float *__restrict__ F, const ProjShape &P,
 #pragma unroll
     for (int t = 0; t < TPW; ++t) tasks[t] = make_task(P, dtab, tg0 + wave + t * NW, lane);
     int bad = 0;
+    StripRegs<NT> xs;
+    strip_load<NT>(F, P, 0, min(P.R, P.L), xs);
     for (int i0 = 0; i0 < P.L; i0 += P.R) {
         const int rows = min(P.R, P.L - i0);
         __syncthreads();
-        // a batch of six groups covers a whole L = 128 strip; more tasks per
-        // wave leave registers for four
-        stage_strip<NT, TPW <= 5 ? 6 : 4>(F, P, i0, rows, lds, bad);
+        strip_store<NT>(P, i0, rows, xs, lds, bad);
         __syncthreads();
+        // the next strip's loads fly while this one is accumulated
+        if (i0 + P.R < P.L) strip_load<NT>(F, P, i0 + P.R, min(P.R, P.L - i0 - P.R), xs);
         accumulate_strip<TPW>(P, tasks, lds, i0, rows, acc, my_tasks);
     }
     bad_out = __syncthreads_or(bad);
