@@ -130,14 +130,14 @@ sw_status get_table(Ctx *ctx, int n, const sw::AngleTable **out) {
 // range of image rows where a pixel inside the disk has non-zero weight for
 // its line (pixel (i, j) weighs 1 - c |j - u(i)| with u(i) the column where
 // the line crosses row i; a small margin keeps the range conservative under
-// FP32 rounding).  Units of 16 consecutive bins of one slot take the union of
+// FP32 rounding).  Units of 8 consecutive bins of one slot take the union of
 // their items' ranges, units are ordered by the centre of their range, and
-// each run of four forms a task.  Rows outside a task's range only ever add
+// each run of eight forms a task.  Rows outside a task's range only ever add
 // zeros, so skipping them leaves every sum unchanged.
 static void build_plan(int L, int n, std::vector<int> &perm, std::vector<int2> &trow) {
     std::vector<double> c, s;
     angle_values(n, c, s);
-    const int slots = n / 8 + 1, upr = (L + 15) / 16, ntasks = sw::proj_ntasks(L, n);
+    const int slots = n / 8 + 1, upr = (L + 7) / 8, ntasks = sw::proj_ntasks(L, n);
     const double c0 = 0.5 * (L - 1);
     const int r = L - 2;
     struct Unit {
@@ -148,7 +148,7 @@ static void build_plan(int L, int n, std::vector<int> &perm, std::vector<int2> &
         const double ck = c[k], sk = s[k], half = 1.0 / ck + 1e-3;
         for (int u0 = 0; u0 < upr; ++u0) {
             int lo = L, hi = -1;
-            for (int b = 16 * u0; b < std::min(L, 16 * u0 + 16); ++b) {
+            for (int b = 8 * u0; b < std::min(L, 8 * u0 + 8); ++b) {
                 for (int i = 0; i < L; ++i) {
                     if (i >= lo && i <= hi) continue;  // already in the unit's range
                     const double u = (b - c0 + sk * (i - c0)) / ck + c0;
@@ -165,7 +165,7 @@ static void build_plan(int L, int n, std::vector<int> &perm, std::vector<int2> &
                     }
                 }
             }
-            units.push_back(Unit{k, 16 * u0, lo, hi});
+            units.push_back(Unit{k, 8 * u0, lo, hi});
         }
     }
     // units whose lines miss the disk first, then by the centre of the range
@@ -177,8 +177,8 @@ static void build_plan(int L, int n, std::vector<int> &perm, std::vector<int2> &
     trow.assign(ntasks, make_int2(1, 0));
     for (size_t q = 0; q < units.size(); ++q) {
         const Unit &x = units[q];
-        const int t = (int)(q / 4), l0 = (int)(q % 4) * 16;
-        for (int l = 0; l < 16 && x.b0 + l < L; ++l) perm[(size_t)t * 64 + l0 + l] = x.slot * L + x.b0 + l;
+        const int t = (int)(q / 8), l0 = (int)(q % 8) * 8;
+        for (int l = 0; l < 8 && x.b0 + l < L; ++l) perm[(size_t)t * 64 + l0 + l] = x.slot * L + x.b0 + l;
         if (x.lo <= x.hi) {
             int2 &tr = trow[t];
             if (tr.x > tr.y) tr = make_int2(x.lo, x.hi);

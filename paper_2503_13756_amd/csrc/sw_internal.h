@@ -29,16 +29,16 @@ __host__ __device__ inline int strip_row_floats(int L) { return 4 * strip_stride
 __host__ __device__ inline int strip_rows_max(int L) { return kKindFloats / strip_row_floats(L); }
 
 // Projection work order of one geometry (L, n).  The projection's work
-// items are (slot angle, bin) pairs, item = slot * L + bin, in units of 16
+// items are (slot angle, bin) pairs, item = slot * L + bin, in units of 8
 // consecutive bins of one slot (the last unit of a slot padded); a task is
-// four units, one item per lane, so that each 16-lane quarter of a wave
-// reads evenly spaced LDS windows.  perm lists the items of task t at
+// eight units, one item per lane, so that each 8-lane group of a wave reads
+// evenly spaced LDS windows.  perm lists the items of task t at
 // [64 t, 64 t + 64) (-1 for padding), units grouped so that the lines of a
 // task cross nearly the same image rows inside the disk, and trow[t] =
 // (first, last) is the range of rows where any of them has a pixel of
 // non-zero weight (first > last: none).  Device memory, owned by the context.
 __host__ __device__ inline int proj_ntasks(int L, int n) {
-    return ((n / 8 + 1) * ((L + 15) / 16) + 3) / 4;
+    return ((n / 8 + 1) * ((L + 7) / 8) + 7) / 8;
 }
 struct ProjPlan {
     int L = 0, n = 0, ntasks = 0;
