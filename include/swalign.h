@@ -121,9 +121,9 @@ typedef struct {
 /* Scratch: the context owns one scratch buffer (grown on demand) that the
    calls needing it share: sw_tables / sw_tables_rf when they take their
    chunked or small-batch path, sw_align_batch (except the max-sliced mode)
-   and sw_align_stacks; sw_project, sw_ramp, sw_quantiles and
-   sw_quantiles_rf never.  Calls on different streams may overlap
-   only when at most one of them uses scratch (e.g. the tables of a single
+   and sw_align_stacks, sw_project_fourier and sw_tables_fourier;
+   sw_project, sw_ramp, sw_quantiles and sw_quantiles_rf never.  Calls on
+   different streams may overlap only when at most one of them uses scratch (e.g. the tables of a single
    reference on a side stream next to the fused tables of a large image
    batch); otherwise order them with events. */
 sw_status sw_ctx_create(void **ctx, int device, const char *tune_json);
@@ -188,6 +188,30 @@ sw_status sw_quantiles_rf(void *ctx, const float *pf, int64_t N, const sw_geom *
    sw_quantiles_rf in one call (through a bounded scratch buffer). */
 sw_status sw_tables_rf(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/,
                        float *qt, double *aux, void *stream);
+
+/* Step 1 by the Fourier slice theorem (Sec. 2.2; the projections of
+   Sec. 2.3 through a NUFFT and a 1-D inverse DFT), discretised as in the
+   appendix's fixed-angle error theorem with NUFFT precision.  With the same
+   pixel masses m as sw_project (positive part inside the disk), pixel
+   centres x_ij, h = 2/L, L = 2M, d_k = (cos theta_k, -sin theta_k):
+     yhat_k(j) = S_j(d_k) sum_pixels m exp(-i j pi d_k . x),  j = -M .. M-1,
+   with S_j the transform of one pixel cell, sinc(j pi d_x h/2)
+   sinc(j pi d_y h/2); pmf[g][k][b] = max(0, h Re g_k(c_b)) for the
+   trigonometric polynomial g_k(s) = (1/2) sum_j yhat_k(j) exp(i j pi s) at
+   the bin centres c_b (negative lobes clipped; column sums equal the image
+   mass up to the clipped lobes).  The slices are evaluated by a type-2
+   NUFFT (grid oversampled by 2, exponential-of-semicircle kernel of width
+   7: relative error about 1e-6 before FP32 rounding), two slices per FP32
+   inverse FFT.  L must be a power of two.  Uses the context scratch.
+   img: [N][L][L] float32, pmf: [N][n][L] float32.  An image holding a
+   non-finite value yields an all-NaN projection. */
+sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/,
+                             float *pmf, void *stream);
+
+/* sw_project_fourier followed by sw_quantiles, through a bounded scratch
+   buffer: images to quantile tables with the Fourier-slice projector. */
+sw_status sw_tables_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/,
+                            float *qt, double *aux, void *stream);
 
 /* Steps 3-5: alignment of table pairs.
    For each pair (r, g): the angle spectra of both tables, the correlation

@@ -12,7 +12,8 @@ OUT = os.path.join(HERE, "libswalign.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["k_project.hip", "k_quantile.hip", "k_tables.hip", "k_align.hip", "k_align128.hip",
-           "k_mfma.hip", "k_mixed.hip", "k_ramp.hip", "k_msw.hip", "sw_host.cpp", "sw_serve.cpp"]
+           "k_mfma.hip", "k_mixed.hip", "k_ramp.hip", "k_msw.hip", "k_fourier.hip", "sw_host.cpp",
+           "sw_serve.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

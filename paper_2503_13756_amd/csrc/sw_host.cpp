@@ -261,6 +261,78 @@ static sw_status get_ramp_table(Ctx *ctx, int L, const float **out) {
     return SW_OK;
 }
 
+// Tables of the Fourier-slice projector for L (a power of two), laid out as
+// described beside sw::FourierTabs in one device buffer.  The interpolation
+// kernel is the exponential of semicircle phi(z) = exp(beta (sqrt(1 -
+// (2z/W)^2) - 1)), |z| < W/2, on the grid oversampled by 2; its Fourier
+// transform phihat(zeta) = int phi(z) cos(2 pi zeta z) dz is integrated in
+// FP64 after z = (W/2) sin t, which leaves a smooth periodic integrand for
+// the midpoint rule.
+static constexpr float kFourierBeta = 2.3f * (float)sw::kFourierW;
+
+static double es_hat(double zeta) {
+    const double pi = 3.141592653589793238462643383279502884;
+    const int nodes = 512;
+    const double W = (double)sw::kFourierW, beta = (double)kFourierBeta;
+    double acc = 0.0;
+    for (int q = 0; q < nodes; ++q) {
+        const double t = -0.5 * pi + (q + 0.5) * pi / nodes;
+        acc += std::exp(beta * (std::cos(t) - 1.0)) * std::cos(t) *
+               std::cos(pi * zeta * W * std::sin(t));
+    }
+    return 0.5 * W * (pi / nodes) * acc;
+}
+
+static sw_status get_fourier_tabs(Ctx *ctx, int L, sw::FourierTabs *out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int M = L / 2, Nf = 2 * L;
+    const size_t n2 = (size_t)Nf / 2 + L / 2 + L;  // float2 entries
+    auto f = ctx->fourier_tabs.find(L);
+    void *d = nullptr;
+    if (f != ctx->fourier_tabs.end()) {
+        d = f->second;
+    } else {
+        const double pi = 3.141592653589793238462643383279502884;
+        std::vector<float2> t2(n2);
+        std::vector<float> corr(L);
+        for (int k = 0; k < Nf / 2; ++k)
+            t2[k] = make_float2((float)std::cos(2 * pi * k / Nf), (float)-std::sin(2 * pi * k / Nf));
+        for (int k = 0; k < L / 2; ++k)
+            t2[Nf / 2 + k] =
+                make_float2((float)std::cos(2 * pi * k / L), (float)-std::sin(2 * pi * k / L));
+        for (int t = 0; t < L; ++t) {
+            const int k = t < M ? t : t - L;
+            const double sg = (k & 1) ? -1.0 : 1.0;
+            t2[Nf / 2 + L / 2 + t] =
+                make_float2((float)(sg * std::cos(pi * k / L)), (float)(sg * std::sin(pi * k / L)));
+        }
+        for (int j = 0; j < L; ++j) corr[j] = (float)(1.0 / es_hat((double)(j - M) / Nf));
+        hipError_t e = hipMalloc(&d, sizeof(float2) * n2 + sizeof(float) * L);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(Fourier tables)");
+        e = hipMemcpy(d, t2.data(), sizeof(float2) * n2, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((char *)d + sizeof(float2) * n2, corr.data(), sizeof(float) * L,
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_fail(e, "hipMemcpy(Fourier tables)");
+        }
+        ctx->fourier_tabs.emplace(L, d);
+    }
+    const float2 *t2 = (const float2 *)d;
+    out->twf = t2;
+    out->twl = t2 + Nf / 2;
+    out->shift = t2 + Nf / 2 + L / 2;
+    out->corr = (const float *)(t2 + n2);
+    return SW_OK;
+}
+
+static int log2_exact(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return (1 << l) == v ? l : -1;
+}
+
 sw_status get_scratch(Ctx *ctx, size_t bytes, hipStream_t stream, void **out) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (bytes > ctx->scratch_bytes) {
@@ -486,6 +558,7 @@ sw_status sw_ctx_destroy(void *ctx) {
             (void)hipFree(kv.second.trow);
         }
         for (auto &kv : c->ramp_tables) (void)hipFree(kv.second);
+        for (auto &kv : c->fourier_tabs) (void)hipFree(kv.second);
         if (c->scratch) (void)hipFree(c->scratch);
         for (int i = 0; i < DescRing::kSlots; ++i)
             if (c->ring.ev[i]) (void)hipEventDestroy(c->ring.ev[i]);
@@ -662,6 +735,97 @@ sw_status sw_tables_rf(void *ctx, const float *img, int64_t N, const sw_geom *g,
                                     qt + i0 * (int64_t)2 * geo.Q * geo.n,
                                     aux ? aux + 4 * i0 : nullptr, s, small);
         if (e != hipSuccess) return hip_fail(e, "k_quantile_rf launch");
+    }
+    return SW_OK;
+}
+
+// Geometry and scratch of the Fourier-slice projector: L a power of two.
+static sw_status fourier_setup(Ctx *c, const sw::Geo &geo, int64_t N, sw::FourierShape *S,
+                               sw::FourierTabs *T, int *slots) {
+    const int lg = log2_exact(geo.L);
+    if (lg < 0)
+        return fail(SW_E_INVALID, "the Fourier-slice projector needs L a power of two (L = %d)",
+                    geo.L);
+    S->L = geo.L;
+    S->n = geo.n;
+    S->Nf = 2 * geo.L;
+    S->lgNf = lg + 1;
+    S->lgL = lg;
+    S->H = geo.L + 1;
+    S->beta = kFourierBeta;
+    sw_status st = get_fourier_tabs(c, geo.L, T);
+    if (st != SW_OK) return st;
+    const int64_t cap = 2 * (int64_t)c->cu_count;  // two blocks per CU
+    *slots = (int)(N < cap ? N : cap);
+    return SW_OK;
+}
+
+sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g, float *pmf,
+                             void *stream) {
+    if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
+    sw::Geo geo;
+    sw_status st = check_geom(g, &geo);
+    if (st != SW_OK) return st;
+    if (N < 0) return fail(SW_E_INVALID, "N = %lld is negative", (long long)N);
+    if (N == 0) return SW_OK;
+    if (!img || !pmf) return fail(SW_E_INVALID, "img or pmf is NULL");
+    Ctx *c = as_ctx(ctx);
+    DeviceGuard dg(c->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    const sw::AngleTable *t;
+    if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
+    sw::FourierShape S;
+    sw::FourierTabs T;
+    int slots;
+    if ((st = fourier_setup(c, geo, N, &S, &T, &slots)) != SW_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    void *scr;
+    if ((st = get_scratch(c, sw::fourier_slot_bytes(S.L, S.Nf) * slots, s, &scr)) != SW_OK)
+        return st;
+    hipError_t e = sw::launch_fourier(img, N, S, T, *t, scr, slots, pmf, s);
+    return e == hipSuccess ? SW_OK : hip_fail(e, "k_fourier launch");
+}
+
+sw_status sw_tables_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g, float *qt,
+                            double *aux, void *stream) {
+    if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
+    sw::Geo geo;
+    sw_status st = check_geom(g, &geo);
+    if (st != SW_OK) return st;
+    if (N < 0) return fail(SW_E_INVALID, "N = %lld is negative", (long long)N);
+    if (N == 0) return SW_OK;
+    if (!img || !qt) return fail(SW_E_INVALID, "img or qt is NULL");
+    Ctx *c = as_ctx(ctx);
+    DeviceGuard dg(c->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    const sw::AngleTable *t;
+    if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
+    sw::FourierShape S;
+    sw::FourierTabs T;
+    int slots;
+    if ((st = fourier_setup(c, geo, N, &S, &T, &slots)) != SW_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // projections of a chunk of images, then their quantile tables; the
+    // scratch holds the chunk's projections and the projector's slots
+    const size_t per = sizeof(float) * (size_t)geo.n * geo.L;
+    int64_t chunk = (int64_t)((size_t)256 << 20) / (int64_t)per;
+    if (chunk < 1) chunk = 1;
+    if (chunk > N) chunk = N;
+    const size_t pmf_bytes = (per * (size_t)chunk + 255) & ~(size_t)255;
+    void *scr;
+    if ((st = get_scratch(c, pmf_bytes + sw::fourier_slot_bytes(S.L, S.Nf) * slots, s, &scr)) !=
+        SW_OK)
+        return st;
+    float *pmf = (float *)scr;
+    void *slot_mem = (char *)scr + pmf_bytes;
+    for (int64_t i0 = 0; i0 < N; i0 += chunk) {
+        const int64_t m = N - i0 < chunk ? N - i0 : chunk;
+        hipError_t e = sw::launch_fourier(img + i0 * (int64_t)geo.L * geo.L, m, S, T, *t, slot_mem,
+                                          slots, pmf, s);
+        if (e != hipSuccess) return hip_fail(e, "k_fourier launch");
+        e = sw::launch_quantiles(pmf, m, geo, *t, qt + i0 * (int64_t)geo.Q * geo.n,
+                                 aux ? aux + 4 * i0 : nullptr, s, c->small(m));
+        if (e != hipSuccess) return hip_fail(e, "k_quantile launch");
     }
     return SW_OK;
 }

@@ -91,6 +91,27 @@ bool tables_rf_fused_fits(Geo g);
 hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable &t,
                             const ProjPlan &pp, const float *hx, float *qt, double *aux,
                             hipStream_t s);
+// Fourier-slice projector (k_fourier.hip): L a power of two, oversampled
+// grid Nf = 2L, H = Nf/2 + 1 stored spectrum columns.  Tables (device,
+// context-owned): corr[j] = 1 / phihat((j - L/2) / Nf) for the interpolation
+// kernel phi, twf[k] = exp(-2 pi i k / Nf) (k < Nf/2), twl[k] =
+// exp(-2 pi i k / L) (k < L/2), shift[t] = (-1)^k exp(i pi k / L) with
+// k = t for t < L/2 and t - L otherwise.  The scratch holds `slots` regions
+// of fourier_slot_bytes; the grid is min(N, slots) persistent blocks.
+constexpr int kFourierW = 7;  // interpolation kernel width in fine-grid points
+struct FourierShape {
+    int L, n, Nf, lgNf, lgL, H;
+    float beta;  // kernel shape: phi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1))
+};
+struct FourierTabs {
+    const float *corr;
+    const float2 *twf, *twl, *shift;
+};
+size_t fourier_lds_bytes(int L, int Nf);
+size_t fourier_slot_bytes(int L, int Nf);
+hipError_t launch_fourier(const float *img, int64_t N, const FourierShape &S, const FourierTabs &T,
+                          const AngleTable &t, void *scratch, int slots, float *pmf,
+                          hipStream_t s);
 // sw2sq of the valid results, and the curve, times f.
 hipError_t launch_scale_results(Result *out, int64_t P, float *curve, int n, float f,
                                 hipStream_t s);

@@ -1,0 +1,132 @@
+"""GPU parity of the Fourier-slice projector (type-2 NUFFT on an oversampled
+grid, slices back to the detector by FP32 inverse FFTs) against the FP64
+oracle's exact non-uniform DFT, through the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+# NUFFT kernel error (about 5e-7 of the largest value with the width-7
+# kernel, measured in FP64) plus FP32 rounding through two 2L-point and one
+# L-point FFT (observed below 1e-6): 5e-6 of the image's largest projection value
+TOL_PROJ = 5e-6
+
+FGEOMS = [(8, 8, 8), (16, 16, 16), (32, 24, 16), (64, 64, 64), (128, 128, 128), (256, 64, 32)]
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2503_13756_amd import api as A
+
+    return A
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def blob_stack(L, N, seed):
+    ref, imgs, _, _ = synth.make_stack(seed, L, N, K=6, shift_px=max(1.0, L / 16), jitter_px=1.0,
+                                       snr=1.0)
+    return ref, imgs
+
+
+def proj_err(pmf, P0):
+    """Largest deviation per image relative to its largest oracle value."""
+    P0 = np.maximum(P0, 0.0)
+    return np.abs(pmf - P0).max(axis=(1, 2)) / P0.max(axis=(1, 2))
+
+
+@pytest.mark.parametrize("L,n,Q", FGEOMS)
+def test_fourier_projection_parity(api, ctx, oracle, L, n, Q):
+    """Blob images and uniform noise: every clipped projection value against
+    the oracle's (clipped) exact DFT route."""
+    N = 2 if L >= 128 else 4
+    _, imgs = blob_stack(L, N, 300 + L)
+    imgs = np.concatenate([imgs, synth.uniform_images(11, L, 1)])
+    pmf = api.project_fourier(ctx, dev(imgs), n).cpu().numpy()
+    P0, _ = oracle.fourier_project(imgs, n)
+    err = proj_err(pmf, P0)
+    assert err.max() < TOL_PROJ, err
+
+
+def test_fourier_more_images_than_slots(api, ctx, oracle):
+    """A batch larger than the persistent grid (two blocks per CU): sampled
+    images across the slot wrap-around, and a ragged end."""
+    import torch
+
+    L, n = 16, 16
+    N = 2 * torch.cuda.get_device_properties(0).multi_processor_count + 37
+    imgs = synth.uniform_images(12, L, N)
+    pmf = api.project_fourier(ctx, dev(imgs), n).cpu().numpy()
+    idx = [0, 1, N // 2, N - 38, N - 37, N - 1]
+    P0, _ = oracle.fourier_project(imgs[idx], n)
+    assert proj_err(pmf[idx], P0).max() < TOL_PROJ
+
+
+def test_fourier_mass_half_turn_and_edge_cases(api, ctx):
+    """Column sums carry the image mass up to the clipped negative lobes; the
+    theta + pi mirror is exact; an empty image projects to zeros, an image
+    with a NaN to NaN, N = 0 is a no-op."""
+    import torch
+
+    L, n = 64, 32
+    _, imgs = blob_stack(L, 3, 77)
+    zero = np.zeros((1, L, L), np.float32)
+    nan = imgs[:1].copy()
+    nan[0, 5, 9] = np.nan
+    batch = np.concatenate([imgs, zero, nan])
+    pmf = api.project_fourier(ctx, dev(batch), n).cpu().numpy()
+    i, j = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    disk = (2 * j - L + 1) ** 2 + (2 * i - L + 1) ** 2 <= (L - 2) ** 2
+    m = np.where(disk, np.maximum(imgs.astype(np.float64), 0), 0).sum(axis=(1, 2))
+    cols = pmf[:3].sum(axis=2)
+    assert np.all(cols >= m[:, None] * (1 - 1e-4))
+    assert np.all(np.abs(cols - cols[:, :1]) < 2e-2 * cols[:, :1])
+    assert np.array_equal(pmf[:3, n // 2:], pmf[:3, :n // 2, ::-1])
+    assert np.all(pmf[3] == 0)
+    assert np.all(np.isnan(pmf[4]))
+    out = torch.full((1, n, L), 7.0, device="cuda")
+    api.project_fourier(ctx, dev(imgs[:0]), n, out=out[:0])
+    assert float(out.min()) == 7.0
+
+
+def test_fourier_rejects_other_sizes(api, ctx):
+    """L must be a power of two: other sizes are refused with an error, no
+    launch."""
+    imgs = synth.uniform_images(3, 24, 2)
+    with pytest.raises(RuntimeError, match="power of two"):
+        api.project_fourier(ctx, dev(imgs), 24)
+
+
+@pytest.mark.parametrize("L,n,Q", [(32, 32, 32), (64, 64, 64), (128, 128, 128)])
+def test_fourier_tables_and_alignment(api, ctx, oracle, L, n, Q):
+    """Images -> Fourier-slice tables -> alignment on the GPU against the
+    oracle from the same images: tables, rotation (tie-aware), shift and
+    distance."""
+    N = 8 if L == 128 else 16
+    ref, imgs = blob_stack(L, N, 500 + L)
+    rq, ra = api.tables_fourier(ctx, dev(ref[None]), n, Q)
+    iq, ia = api.tables_fourier(ctx, dev(imgs), n, Q)
+    oq, oa = oracle.fourier_tables(ref[None], n, Q)
+    iq0, ia0 = oracle.fourier_tables(imgs, n, Q)
+    assert np.abs(iq.cpu().numpy() - iq0).max() < 2e-3
+    res, _ = api.align_batch(ctx, rq, ra, iq, ia, L, want_curve=True)
+    g = api.unpack_results(res)
+    o = oracle.align(oq, oa, iq0, ia0, L, want_curve=True)
+    parity.check(g, o, L, parity.TAU_FP32, o["curve"])
