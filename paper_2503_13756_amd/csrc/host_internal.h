@@ -35,7 +35,8 @@ struct Ctx {
     std::map<int, sw::AngleTable> tables;
     std::map<int, sw::ProjPlan> plans;  // key L * 4096 + n
     std::map<int, float *> ramp_tables;  // ramp filter kernel per L
-    std::map<int, void *> fourier_tabs;  // Fourier-slice projector tables per L
+    std::map<int, void *> fourier_tabs;     // Fourier-slice projector tables per L
+    std::map<int, void *> fourier_targets;  // its slice-point tables, key L * 4096 + n
     std::map<int, int> tile_R;  // projection strip rows per L (autotuner)
     // batches of fewer images take the split (many blocks per image) launches;
     // -1: the number of compute units

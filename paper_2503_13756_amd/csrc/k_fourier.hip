@@ -69,62 +69,48 @@ __device__ float2 *fft_batch(float2 *a, float2 *b, int lg, int cnt, const float2
     return a;
 }
 
-// Slice value yhat at k pi d from the oversampled spectrum B [Nf][H].
-__device__ float2 slice_point(const float2 *__restrict__ B, int Nf, int H, int L, double dx,
-                              double dy, int k, float beta) {
-    const double scale = (double)Nf / (double)L;
-    const double gx = k * dx * scale, gy = k * dy * scale;  // fine-grid coordinates
-    const int vx0 = (int)floor(gx - 0.5 * kFourierW) + 1;
-    const int uy0 = (int)floor(gy - 0.5 * kFourierW) + 1;
-    const float fx = (float)(gx - vx0), fy = (float)(gy - uy0);  // in [kW/2 - 1, kW/2)
-    float wx[kFourierW], wy[kFourierW];
-#pragma unroll
-    for (int c = 0; c < kFourierW; ++c) {
-        const float tx = 2.f * (fx - (float)c) / (float)kFourierW;
-        const float ty = 2.f * (fy - (float)c) / (float)kFourierW;
-        wx[c] = fabsf(tx) < 1.f ? expf(beta * (sqrtf(1.f - tx * tx) - 1.f)) : 0.f;
-        wy[c] = fabsf(ty) < 1.f ? expf(beta * (sqrtf(1.f - ty * ty) - 1.f)) : 0.f;
-    }
-    const int hm = Nf >> 1, msk = Nf - 1;
+// Slice value yhat at one slice point from the oversampled spectrum, stored
+// with kFourierPad conjugate-mirrored columns on both sides (row length Hx,
+// column v at v + kFourierPad), so that every tap is a plain load.  The
+// target entry (host-built per geometry, float4 x 5): (u0, v0 | conj << 16)
+// as ints and the complex factor (pixel-centre phase times the cell
+// transform); the kW x-weights; the kW y-weights.  Taps are rows
+// (u0 + a) mod Nf, columns v0 - kFourierPad + c; with conj the kernel was
+// evaluated at the mirrored point and the sum is conjugated.
+__device__ __forceinline__ float2 slice_point(const float2 *__restrict__ B, int Nf, int Hx,
+                                              const float4 *__restrict__ e) {
+    const float4 e0 = e[0], e1 = e[1], e2 = e[2], e3 = e[3], e4 = e[4];
+    const int u0 = __float_as_int(e0.x), vw = __float_as_int(e0.y);
+    const float wx[kFourierW] = {e1.x, e1.y, e1.z, e1.w, e2.x, e2.y, e2.z};
+    const float wy[kFourierW] = {e3.x, e3.y, e3.z, e3.w, e4.x, e4.y, e4.z};
+    const float2 *col = B + (vw & 0xffff);
+    const int msk = Nf - 1;
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int a = 0; a < kFourierW; ++a) {
-        const int u = (uy0 + a) & msk, um = (Nf - u) & msk;
+        const float2 *row = col + ((u0 + a) & msk) * Hx;
         float2 ra = make_float2(0.f, 0.f);
 #pragma unroll
         for (int c = 0; c < kFourierW; ++c) {
-            const int v = (vx0 + c) & msk;
-            float2 bv;
-            if (v <= hm) {
-                bv = B[u * H + v];
-            } else {  // conjugate mirror of the stored half
-                bv = B[um * H + (Nf - v)];
-                bv.y = -bv.y;
-            }
+            const float2 bv = row[c];
             ra.x = fmaf(wx[c], bv.x, ra.x);
             ra.y = fmaf(wx[c], bv.y, ra.y);
         }
         acc.x = fmaf(wy[a], ra.x, acc.x);
         acc.y = fmaf(wy[a], ra.y, acc.y);
     }
-    // pixel centres sit half a pixel off the centred integer grid, and the
-    // cell transform sinc(xi_x h/2) sinc(xi_y h/2) with xi h/2 = k pi d / L
-    const double pi = 3.141592653589793238462643383279502884;
-    const double ang = -pi * k * (dx + dy) / L;
-    const double ax = pi * k * dx / L, ay = pi * k * dy / L;
-    const double sx = ax == 0.0 ? 1.0 : sin(ax) / ax, sy = ay == 0.0 ? 1.0 : sin(ay) / ay;
-    const float2 ph = make_float2((float)(cos(ang) * sx * sy), (float)(sin(ang) * sx * sy));
-    return cmul(acc, ph);
+    if (vw >> 16) acc.y = -acc.y;
+    return cmul(acc, make_float2(e0.z, e0.w));
 }
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_fourier(const float *__restrict__ img, int64_t N,
                                                 FourierShape S, FourierTabs T,
-                                                const double2 *__restrict__ d64,
                                                 float2 *__restrict__ scratch, float *__restrict__ pmf) {
     extern __shared__ __align__(16) float2 lds2[];
     __shared__ int sbad;
     const int L = S.L, M = L >> 1, n = S.n, Nf = S.Nf, H = S.H, lgNf = S.lgNf, lgL = S.lgL;
+    const int Hx = H + 2 * kFourierPad - 1;
     const float h = 2.f / (float)L;
     float2 *fa = lds2, *fb = lds2 + kFftFloats2;
     float2 *Y = fb + kFftFloats2;                      // [slices][M + 1]
@@ -138,8 +124,8 @@ __global__ __launch_bounds__(NT) void k_fourier(const float *__restrict__ img, i
         shf[t] = T.shift[t];
         corr[t] = T.corr[t];
     }
-    float2 *R = scratch + (size_t)blockIdx.x * (size_t)(L + Nf) * H;  // [L][H]
-    float2 *B = R + (size_t)L * H;                                      // [Nf][H]
+    float2 *R = scratch + (size_t)blockIdx.x * fourier_slot_elems(L, Nf);  // [L][H]
+    float2 *B = R + (size_t)L * H;  // [Nf][Hx], column v at v + kFourierPad
     const int GR = kFftFloats2 >> lgNf;  // transforms of length Nf per round
     const int GS = kFftFloats2 >> lgL;   // transforms of length L per round (two slices each)
     for (int64_t g = blockIdx.x; g < N; g += gridDim.x) {
@@ -190,20 +176,28 @@ __global__ __launch_bounds__(NT) void k_fourier(const float *__restrict__ img, i
             const float2 *X = fft_batch<NT>(fa, fb, lgNf, cnt, twf, false);
             for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT) {
                 const int u = idx / cnt, f = idx - u * cnt;
-                B[(size_t)u * H + v0 + f] = X[(f << lgNf) + u];
+                B[(size_t)u * Hx + kFourierPad + v0 + f] = X[(f << lgNf) + u];
             }
         }
         __syncthreads();  // B written
+        // mirrored pad columns: B[u][v] = conj B[-u][-v] for v < 0 and for
+        // v > Nf/2 (there as B[-u][Nf - v])
+        for (int idx = threadIdx.x; idx < Nf * (2 * kFourierPad - 1); idx += NT) {
+            const int u = idx / (2 * kFourierPad - 1), c = idx - u * (2 * kFourierPad - 1);
+            const int v = c < kFourierPad ? c - kFourierPad : (Nf >> 1) + 1 + (c - kFourierPad);
+            const int vs = v < 0 ? -v : Nf - v;
+            float2 z = B[(size_t)((Nf - u) & (Nf - 1)) * Hx + kFourierPad + vs];
+            z.y = -z.y;
+            B[(size_t)u * Hx + kFourierPad + v] = z;
+        }
+        __syncthreads();
         const bool isbad = sbad != 0;
         float *out = pmf + g * (int64_t)n * L;
         // 3. slices theta_m, m < n/2, two per inverse transform
         for (int m0 = 0; m0 < (n >> 1); m0 += 2 * GS) {
             const int ns = min(2 * GS, (n >> 1) - m0);  // even: n is a multiple of 8
-            for (int idx = threadIdx.x; idx < ns * (M + 1); idx += NT) {
-                const int sl = idx / (M + 1), k = idx - sl * (M + 1);
-                const double2 d = d64[m0 + sl];
-                Y[idx] = slice_point(B, Nf, H, L, d.x, d.y, k, S.beta);
-            }
+            for (int idx = threadIdx.x; idx < ns * (M + 1); idx += NT)
+                Y[idx] = slice_point(B, Nf, Hx, T.targets + 5 * ((size_t)m0 * (M + 1) + idx));
             __syncthreads();
             for (int idx = threadIdx.x; idx < ((ns >> 1) << lgL); idx += NT) {
                 const int f = idx >> lgL, t = idx & (L - 1);
@@ -247,11 +241,10 @@ size_t fourier_lds_bytes(int L, int Nf) {
            sizeof(float) * L;
 }
 
-size_t fourier_slot_bytes(int L, int Nf) { return sizeof(float2) * (size_t)(L + Nf) * (Nf / 2 + 1); }
+size_t fourier_slot_bytes(int L, int Nf) { return sizeof(float2) * fourier_slot_elems(L, Nf); }
 
 hipError_t launch_fourier(const float *img, int64_t N, const FourierShape &S, const FourierTabs &T,
-                          const AngleTable &t, void *scratch, int slots, float *pmf,
-                          hipStream_t s) {
+                          void *scratch, int slots, float *pmf, hipStream_t s) {
     if (N <= 0) return hipSuccess;
     constexpr int NT = 256;
     const size_t lds = fourier_lds_bytes(S.L, S.Nf);
@@ -259,7 +252,7 @@ hipError_t launch_fourier(const float *img, int64_t N, const FourierShape &S, co
         (const void *)k_fourier<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     (void)attr;
     const int grid = (int)(N < slots ? N : slots);
-    hipLaunchKernelGGL((k_fourier<NT>), dim3(grid), dim3(NT), lds, s, img, N, S, T, t.d64,
+    hipLaunchKernelGGL((k_fourier<NT>), dim3(grid), dim3(NT), lds, s, img, N, S, T,
                        (float2 *)scratch, pmf);
     return hipGetLastError();
 }

@@ -327,6 +327,71 @@ static sw_status get_fourier_tabs(Ctx *ctx, int L, sw::FourierTabs *out) {
     return SW_OK;
 }
 
+static double es_phi(double z) {
+    const double W = (double)sw::kFourierW, t = 2.0 * z / W;
+    return std::fabs(t) < 1.0 ? std::exp((double)kFourierBeta * (std::sqrt(1.0 - t * t) - 1.0))
+                              : 0.0;
+}
+
+// Slice-point table of the Fourier-slice projector for (L, n): for theta_m,
+// m < n/2, and k = 0 .. L/2, the fine-grid point g = k d_m Nf / L of the
+// slice frequency k pi d_m (mirrored to g_x >= 0, the conjugate then taken
+// in the kernel), its first tap row u0 and column v0 of the kernel's
+// support, the kernel weights per row and column, and the factor
+// exp(-i pi k (d_x + d_y) / L) sinc(pi k d_x / L) sinc(pi k d_y / L) (the
+// pixel centres' half-pixel offset and the transform of one pixel cell),
+// all from FP64.  Layout as read by slice_point in k_fourier.hip.
+static sw_status get_fourier_targets(Ctx *ctx, int L, int n, const float4 **out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int key = L * 4096 + n;
+    auto f = ctx->fourier_targets.find(key);
+    if (f != ctx->fourier_targets.end()) {
+        *out = (const float4 *)f->second;
+        return SW_OK;
+    }
+    const double pi = 3.141592653589793238462643383279502884;
+    const int M = L / 2, Nf = 2 * L, W = sw::kFourierW;
+    std::vector<double> c, s;
+    angle_values(n, c, s);
+    std::vector<float4> tab((size_t)(n / 2) * (M + 1) * 5);
+    for (int m = 0; m < n / 2; ++m) {
+        const double dx = c[m], dy = -s[m];
+        const bool flip = dx < 0.0;
+        for (int k = 0; k <= M; ++k) {
+            const double sc = (double)k * Nf / L;
+            const double gx = (flip ? -dx : dx) * sc, gy = (flip ? -dy : dy) * sc;
+            const int v0 = (int)std::floor(gx - 0.5 * W) + 1, u0 = (int)std::floor(gy - 0.5 * W) + 1;
+            float wx[8] = {0}, wy[8] = {0};
+            for (int t = 0; t < W; ++t) {
+                wx[t] = (float)es_phi(gx - (v0 + t));
+                wy[t] = (float)es_phi(gy - (u0 + t));
+            }
+            const double ax = pi * k * dx / L, ay = pi * k * dy / L, ang = -(ax + ay);
+            const double sinc = (ax == 0.0 ? 1.0 : std::sin(ax) / ax) * (ay == 0.0 ? 1.0 : std::sin(ay) / ay);
+            float4 *e = &tab[((size_t)m * (M + 1) + k) * 5];
+            int hdr[2] = {((u0 % Nf) + Nf) % Nf, (v0 + sw::kFourierPad) | (flip ? 1 << 16 : 0)};
+            float hf[2];
+            std::memcpy(hf, hdr, sizeof(hf));
+            e[0] = make_float4(hf[0], hf[1], (float)(std::cos(ang) * sinc), (float)(std::sin(ang) * sinc));
+            e[1] = make_float4(wx[0], wx[1], wx[2], wx[3]);
+            e[2] = make_float4(wx[4], wx[5], wx[6], 0.f);
+            e[3] = make_float4(wy[0], wy[1], wy[2], wy[3]);
+            e[4] = make_float4(wy[4], wy[5], wy[6], 0.f);
+        }
+    }
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(float4) * tab.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(Fourier slice table)");
+    e = hipMemcpy(d, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "hipMemcpy(Fourier slice table)");
+    }
+    ctx->fourier_targets.emplace(key, d);
+    *out = (const float4 *)d;
+    return SW_OK;
+}
+
 static int log2_exact(int v) {
     int l = 0;
     while ((1 << l) < v) ++l;
@@ -559,6 +624,7 @@ sw_status sw_ctx_destroy(void *ctx) {
         }
         for (auto &kv : c->ramp_tables) (void)hipFree(kv.second);
         for (auto &kv : c->fourier_tabs) (void)hipFree(kv.second);
+        for (auto &kv : c->fourier_targets) (void)hipFree(kv.second);
         if (c->scratch) (void)hipFree(c->scratch);
         for (int i = 0; i < DescRing::kSlots; ++i)
             if (c->ring.ev[i]) (void)hipEventDestroy(c->ring.ev[i]);
@@ -752,10 +818,12 @@ static sw_status fourier_setup(Ctx *c, const sw::Geo &geo, int64_t N, sw::Fourie
     S->lgNf = lg + 1;
     S->lgL = lg;
     S->H = geo.L + 1;
-    S->beta = kFourierBeta;
     sw_status st = get_fourier_tabs(c, geo.L, T);
     if (st != SW_OK) return st;
-    const int64_t cap = 2 * (int64_t)c->cu_count;  // two blocks per CU
+    if ((st = get_fourier_targets(c, geo.L, geo.n, &T->targets)) != SW_OK) return st;
+    // as many blocks per CU as the 160 KiB of LDS hold (at most four)
+    const int per_cu = std::max(1, std::min(4, (int)((160 << 10) / sw::fourier_lds_bytes(S->L, S->Nf))));
+    const int64_t cap = (int64_t)per_cu * c->cu_count;
     *slots = (int)(N < cap ? N : cap);
     return SW_OK;
 }
@@ -772,8 +840,6 @@ sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_ge
     Ctx *c = as_ctx(ctx);
     DeviceGuard dg(c->device);
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-    const sw::AngleTable *t;
-    if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
     sw::FourierShape S;
     sw::FourierTabs T;
     int slots;
@@ -782,7 +848,7 @@ sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_ge
     void *scr;
     if ((st = get_scratch(c, sw::fourier_slot_bytes(S.L, S.Nf) * slots, s, &scr)) != SW_OK)
         return st;
-    hipError_t e = sw::launch_fourier(img, N, S, T, *t, scr, slots, pmf, s);
+    hipError_t e = sw::launch_fourier(img, N, S, T, scr, slots, pmf, s);
     return e == hipSuccess ? SW_OK : hip_fail(e, "k_fourier launch");
 }
 
@@ -820,7 +886,7 @@ sw_status sw_tables_fourier(void *ctx, const float *img, int64_t N, const sw_geo
     void *slot_mem = (char *)scr + pmf_bytes;
     for (int64_t i0 = 0; i0 < N; i0 += chunk) {
         const int64_t m = N - i0 < chunk ? N - i0 : chunk;
-        hipError_t e = sw::launch_fourier(img + i0 * (int64_t)geo.L * geo.L, m, S, T, *t, slot_mem,
+        hipError_t e = sw::launch_fourier(img + i0 * (int64_t)geo.L * geo.L, m, S, T, slot_mem,
                                           slots, pmf, s);
         if (e != hipSuccess) return hip_fail(e, "k_fourier launch");
         e = sw::launch_quantiles(pmf, m, geo, *t, qt + i0 * (int64_t)geo.Q * geo.n,

@@ -98,20 +98,26 @@ hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable
 // exp(-2 pi i k / L) (k < L/2), shift[t] = (-1)^k exp(i pi k / L) with
 // k = t for t < L/2 and t - L otherwise.  The scratch holds `slots` regions
 // of fourier_slot_bytes; the grid is min(N, slots) persistent blocks.
-constexpr int kFourierW = 7;  // interpolation kernel width in fine-grid points
+// targets: per slice point (theta_m, k pi), m < n/2, k <= L/2, in that
+// order, five float4 (layout at slice_point in k_fourier.hip).
+constexpr int kFourierW = 7;    // interpolation kernel width in fine-grid points
+constexpr int kFourierPad = 4;  // mirrored spectrum columns kept on each side
 struct FourierShape {
     int L, n, Nf, lgNf, lgL, H;
-    float beta;  // kernel shape: phi(z) = exp(beta (sqrt(1 - (2z/W)^2) - 1))
 };
 struct FourierTabs {
     const float *corr;
     const float2 *twf, *twl, *shift;
+    const float4 *targets;
 };
+// per slot: R [L][Nf/2 + 1] and B [Nf][Nf/2 + 2 kFourierPad] complex
+__host__ __device__ inline size_t fourier_slot_elems(int L, int Nf) {
+    return (size_t)L * (Nf / 2 + 1) + (size_t)Nf * (Nf / 2 + 2 * kFourierPad);
+}
 size_t fourier_lds_bytes(int L, int Nf);
 size_t fourier_slot_bytes(int L, int Nf);
 hipError_t launch_fourier(const float *img, int64_t N, const FourierShape &S, const FourierTabs &T,
-                          const AngleTable &t, void *scratch, int slots, float *pmf,
-                          hipStream_t s);
+                          void *scratch, int slots, float *pmf, hipStream_t s);
 // sw2sq of the valid results, and the curve, times f.
 hipError_t launch_scale_results(Result *out, int64_t P, float *curve, int n, float f,
                                 hipStream_t s);

@@ -66,12 +66,12 @@ def test_fourier_projection_parity(api, ctx, oracle, L, n, Q):
 
 
 def test_fourier_more_images_than_slots(api, ctx, oracle):
-    """A batch larger than the persistent grid (two blocks per CU): sampled
+    """A batch larger than the persistent grid (up to four blocks per CU): sampled
     images across the slot wrap-around, and a ragged end."""
     import torch
 
     L, n = 16, 16
-    N = 2 * torch.cuda.get_device_properties(0).multi_processor_count + 37
+    N = 4 * torch.cuda.get_device_properties(0).multi_processor_count + 37
     imgs = synth.uniform_images(12, L, N)
     pmf = api.project_fourier(ctx, dev(imgs), n).cpu().numpy()
     idx = [0, 1, N // 2, N - 38, N - 37, N - 1]
