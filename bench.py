@@ -245,6 +245,9 @@ def main():
         log("max-sliced SW2")
         line["max_sliced"], extra_res["msw"] = bench_msw(api, ctx, torch, rq, ra, iq, ia, L,
                                                          seg32[0] + seg32[1])
+        log("Fourier-slice projector")
+        line["fourier_slice"], extra_res["fourier"] = bench_fourier(api, ctx, torch, ref, imgs, pmf,
+                                                                    L, n, Q, seg32[0] + seg32[1])
         del pmf, iq, ia, res
         torch.cuda.empty_cache()
         log("all pairs")
@@ -272,6 +275,9 @@ def main():
         if "ramp" in extra_res:
             log("ramp-filtered parity (oracle)")
             line["cpu_baseline"]["ramp_parity"] = ramp_parity(w, *extra_res["ramp"], L, n, Q)
+        if "fourier" in extra_res:
+            log("Fourier-slice parity (oracle)")
+            line["cpu_baseline"]["fourier_parity"] = fourier_parity(w, extra_res["fourier"], L, n, Q)
         if "msw" in extra_res:
             log("max-sliced parity (oracle)")
             line["cpu_baseline"]["max_sliced_parity"] = msw_parity(w, extra_res["msw"], L, n, Q)
@@ -396,6 +402,72 @@ def msw_parity(w, r, L, n, Q, S=500):
     S = min(S, len(w["imgs"]))
     o = O.align_images(w["ref"], w["imgs"][:S], n, Q, mode=O.MODE_MAX_SLICED, want_curve=True)
     sub = {k: v[:S] for k, v in r.items()}
+    try:
+        rep = parity.check(sub, o, L, parity.TAU_FP32, o["curve"])
+        return f"{rep['pairs']} pairs ok, exact rotation {rep['exact_rot']}"
+    except AssertionError as e:
+        return "FAILED: " + str(e)[:300]
+
+
+def fourier_flops(L, n):
+    """Algorithmic FP32 flops of the Fourier-slice projector per image:
+    5 N log2 N per complex FFT (L/2 row transforms and L+1 column transforms
+    of length 2L, n/4 slice transforms of length L) and 4 per kernel tap
+    (W^2 = 49 taps per slice point, n/2 (L/2 + 1) points)."""
+    Nf = 2 * L
+    fft = 5 * Nf * math.log2(Nf) * (L // 2 + L + 1) + 5 * L * math.log2(L) * (n // 4)
+    return fft + 4 * 49 * (n // 2) * (L // 2 + 1)
+
+
+def bench_fourier(api, ctx, torch, ref, imgs, pmf, L, n, Q, line_tables_ms, K=5):
+    """Fourier-slice projector (NUFFT) on the images of the main line: the
+    projector alone next to the line-sum projector, and the whole path
+    (images -> Fourier tables -> alignment against the reference's Fourier
+    tables); then the projector alone at L = 256 on 3000 blob images."""
+    N = imgs.shape[0]
+    dev = imgs.device
+    t_f = timed(torch, lambda: api.project_fourier(ctx, imgs, n, out=pmf), K)
+    t_l = timed(torch, lambda: api.project(ctx, imgs, n, out=pmf), K)
+    rq, ra = api.tables_fourier(ctx, ref, n, Q)
+    iq = torch.empty((N, Q, n), dtype=torch.float32, device=dev)
+    ia = torch.empty((N, 4), dtype=torch.float64, device=dev)
+    res = torch.empty((N, 6), dtype=torch.int32, device=dev)
+    t_t = timed(torch, lambda: api.tables_fourier(ctx, imgs, n, Q, out=iq, aux=ia), K)
+    t_a = timed(torch, lambda: api.align_batch(ctx, rq, ra, iq, ia, L, out=res), K)
+    fl = fourier_flops(L, n)
+    out = {"workload": f"1 reference vs {N} images, L={L}, n=Q={L} (images of the main line), "
+                       "Fourier-slice projections (type-2 NUFFT, width-7 kernel, grid x2), "
+                       "negative lobes clipped, images to results",
+           "projector_ms": t_f, "line_sum_projector_ms": t_l, "tables_ms": t_t, "align_ms": t_a,
+           "value": N / ((t_t + t_a) * 1e-3), "unit": "alignments/s",
+           "line_sum_tables_ms": line_tables_ms,
+           "projector_tflops": fl * N / (t_f * 1e-3) / 1e12,
+           "paper_context": "the paper projects with a NUFFT in O(L^2 log L) per image (Sec. 2.3)"}
+    del iq, ia
+    L2, N2 = 256, 3000
+    _, big = _pool(L2, N2, 1210, distinct=64)
+    big = big.to(dev)
+    p2 = torch.empty((N2, L2, L2), dtype=torch.float32, device=dev)
+    t_f2 = timed(torch, lambda: api.project_fourier(ctx, big, L2, out=p2), K)
+    t_l2 = timed(torch, lambda: api.project(ctx, big, L2, out=p2), K)
+    out["L256"] = {"images": N2, "projector_ms": t_f2, "line_sum_projector_ms": t_l2,
+                   "projector_tflops": fourier_flops(L2, L2) * N2 / (t_f2 * 1e-3) / 1e12}
+    del big, p2
+    return out, (rq, ra, api.unpack_results(res))
+
+
+def fourier_parity(w, r, L, n, Q, S=16):
+    """Oracle Fourier-slice tables and alignment of the first S images against
+    the GPU's."""
+    from oracle import oracle as O
+    from tests import parity
+
+    rq, ra, g = r
+    S = min(S, len(w["imgs"]))
+    oq, oa = O.fourier_tables(w["ref"][None], n, Q)
+    iq0, ia0 = O.fourier_tables(w["imgs"][:S], n, Q)
+    o = O.align(oq, oa, iq0, ia0, L, want_curve=True)
+    sub = {k: v[:S] for k, v in g.items()}
     try:
         rep = parity.check(sub, o, L, parity.TAU_FP32, o["curve"])
         return f"{rep['pairs']} pairs ok, exact rotation {rep['exact_rot']}"
