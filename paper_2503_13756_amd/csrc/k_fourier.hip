@@ -6,7 +6,8 @@
 // frequencies k pi, k = -M .. M-1 (L = 2M), and the trigonometric polynomial
 // with coefficients yhat_k / 2 sampled at the detector bin centres.
 //
-// One block per image slot of a persistent grid; per image:
+// One 512-thread block per image slot of a persistent grid (as many slots as
+// fit on the CUs at once); per image:
 //  1. rows: the pixel masses (positive part inside the disk, exactly as for
 //     the line sum) divided by the kernel's Fourier transform at their
 //     centred index, zero-padded to Nf = 2L and transformed along x; two
@@ -243,14 +244,30 @@ size_t fourier_lds_bytes(int L, int Nf) {
 
 size_t fourier_slot_bytes(int L, int Nf) { return sizeof(float2) * fourier_slot_elems(L, Nf); }
 
+constexpr int kFourierNT = 512;
+
+static void fourier_attr() {
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)k_fourier<kFourierNT>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    (void)attr;
+}
+
+int fourier_blocks_per_cu(int L, int Nf) {
+    fourier_attr();
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fourier<kFourierNT>, kFourierNT,
+                                                     fourier_lds_bytes(L, Nf)) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
 hipError_t launch_fourier(const float *img, int64_t N, const FourierShape &S, const FourierTabs &T,
                           void *scratch, int slots, float *pmf, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    constexpr int NT = 256;
+    constexpr int NT = kFourierNT;
     const size_t lds = fourier_lds_bytes(S.L, S.Nf);
-    static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)k_fourier<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-    (void)attr;
+    fourier_attr();
     const int grid = (int)(N < slots ? N : slots);
     hipLaunchKernelGGL((k_fourier<NT>), dim3(grid), dim3(NT), lds, s, img, N, S, T,
                        (float2 *)scratch, pmf);

@@ -821,9 +821,8 @@ static sw_status fourier_setup(Ctx *c, const sw::Geo &geo, int64_t N, sw::Fourie
     sw_status st = get_fourier_tabs(c, geo.L, T);
     if (st != SW_OK) return st;
     if ((st = get_fourier_targets(c, geo.L, geo.n, &T->targets)) != SW_OK) return st;
-    // as many blocks per CU as the 160 KiB of LDS hold (at most four)
-    const int per_cu = std::max(1, std::min(4, (int)((160 << 10) / sw::fourier_lds_bytes(S->L, S->Nf))));
-    const int64_t cap = (int64_t)per_cu * c->cu_count;
+    // one slot per block that can be resident at once
+    const int64_t cap = (int64_t)sw::fourier_blocks_per_cu(S->L, S->Nf) * c->cu_count;
     *slots = (int)(N < cap ? N : cap);
     return SW_OK;
 }

@@ -116,6 +116,7 @@ __host__ __device__ inline size_t fourier_slot_elems(int L, int Nf) {
 }
 size_t fourier_lds_bytes(int L, int Nf);
 size_t fourier_slot_bytes(int L, int Nf);
+int fourier_blocks_per_cu(int L, int Nf);  // resident blocks of the projector per CU
 hipError_t launch_fourier(const float *img, int64_t N, const FourierShape &S, const FourierTabs &T,
                           void *scratch, int slots, float *pmf, hipStream_t s);
 // sw2sq of the valid results, and the curve, times f.
