@@ -105,7 +105,7 @@ __device__ __forceinline__ float2 slice_point(const float2 *__restrict__ B, int 
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_fourier(const float *__restrict__ img, int64_t N,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fourier(const float *__restrict__ img, int64_t N,
                                                 FourierShape S, FourierTabs T,
                                                 float2 *__restrict__ scratch, float *__restrict__ pmf) {
     extern __shared__ __align__(16) float2 lds2[];
