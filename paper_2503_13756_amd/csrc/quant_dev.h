@@ -140,11 +140,13 @@ __device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut
                 const double tl = fma((double)b, h, -1.0), tr = tl + h;
                 const double den = cr - cl;
                 const double slope = den > 0.0 ? div_by(h, den) : 0.0;
+                // the offset z - cl inside the bin in FP64, the interpolation
+                // and the clamp to the bin in FP32 (the result's precision)
+                const float tlf = (float)tl, trf = (float)tr, slf = (float)slope;
                 for (int j = jl; j < jr; ++j) {
                     const double z = fma((double)j, invQ, z0);
-                    double u = fma(z - cl, slope, tl);
-                    u = u < tl ? tl : (u > tr ? tr : u);
-                    const float uf = (float)u;
+                    const float uf =
+                        __builtin_amdgcn_fmed3f(fmaf((float)(z - cl), slf, tlf), tlf, trf);
                     Ut[j * ldt + kl] = uf;
                     s1 += (double)uf;
                     s2 = fma((double)uf, (double)uf, s2);
