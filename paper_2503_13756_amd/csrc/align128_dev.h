@@ -290,6 +290,19 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
         if (part == 0) S[w] = s;
     }
     __syncthreads();
+    // The transpose buffer is free from here on: the rescore's first chunk of
+    // V rows is copied into it straight from memory to LDS (1 KiB per wave
+    // instruction, no registers) while the lags are scored.
+    constexpr int RC = (NG * 8 * kA128Stride * 2) / n >= 128 ? 128 : 64;  // rows per chunk
+    static_assert(RC * n <= NG * 8 * kA128Stride * 2, "chunk fits the buffer");
+    {
+        const int rows0 = Q < RC ? Q : RC;
+        const int segs = rows0 * n / 256;  // 1 KiB segments (n = 128: two rows each)
+        for (int q = wave; q < segs; q += NW)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(job.V + 256 * q + 4 * lane),
+                (__attribute__((address_space(3))) void *)((float *)xb + 256 * q), 16, 0, 0);
+    }
 
     // --- inverse transform over w, translation correction, objective per lag
     const double nq = (double)n * (double)Q;
@@ -353,14 +366,15 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
     }
     if (lane < K) red[wave][lane] = 0.f;
     float *vl = (float *)xb;
-    // rows per chunk: the largest power of two that fits the transpose buffer
-    constexpr int RC = (NG * 8 * kA128Stride * 2) / n >= 128 ? 128 : 64;
-    static_assert(RC * n <= NG * 8 * kA128Stride * 2, "chunk fits the buffer");
     for (int j0 = 0; j0 < Q; j0 += RC) {
         const int rows = Q - j0 < RC ? Q - j0 : RC;
-        __syncthreads();
-        for (int q = threadIdx.x; q < rows * (n / 4); q += NT)
-            *(float4 *)(vl + 4 * q) = *(const float4 *)(V + (int64_t)j0 * n + 4 * q);
+        if (j0 == 0) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copy above has landed
+        } else {
+            __syncthreads();
+            for (int q = threadIdx.x; q < rows * (n / 4); q += NT)
+                *(float4 *)(vl + 4 * q) = *(const float4 *)(V + (int64_t)j0 * n + 4 * q);
+        }
         __syncthreads();
         // a thread keeps one column k (NT is a multiple of n) and walks
         // rows kRows apart, so the angle, the shift terms and the rotated
