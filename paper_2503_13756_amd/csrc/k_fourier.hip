@@ -21,7 +21,8 @@
 //     transform of one pixel cell; the coefficients of two slices are packed
 //     into one complex L-point inverse FFT (both results are real), scaled by
 //     h/2, clipped at zero and written with their theta + pi mirror.
-// The FFTs are radix-2 Stockham transforms in LDS over a batch of sequences.
+// The FFTs are Stockham transforms (radix 4, one radix-2 step for odd
+// powers of two) in LDS over a batch of sequences.
 #include "sw_internal.h"
 
 namespace sw {
@@ -39,29 +40,71 @@ __device__ __forceinline__ bool in_disk_f(int L, int i, int j) {
     return a * a + b * b <= r * r;
 }
 
+// One Stockham step of radix R over cnt transforms of length 2^lg: element
+// j + r 2^lg / R of each transform, twiddled by exp(-+2 pi i r (j mod Ns) /
+// (Ns R)), goes through an R-point DFT to position (j / Ns) Ns R + (j mod Ns)
+// + r Ns of the output.
+template <int NT, int R>
+__device__ __forceinline__ void fft_step(const float2 *a, float2 *b, int lg, int lgNs, int cnt,
+                                         const float2 *tw, bool inv) {
+    constexpr int lgR = R == 4 ? 2 : 1;
+    const int nq = 1 << (lg - lgR), Ns = 1 << lgNs;
+    for (int idx = threadIdx.x; idx < cnt * nq; idx += NT) {
+        const int f = idx >> (lg - lgR), j = idx & (nq - 1);
+        const float2 *src = a + (f << lg);
+        float2 *dst = b + (f << lg);
+        const int jm = j & (Ns - 1);
+        const int o = ((j - jm) << lgR) + jm;
+        // twiddle index of r = 1: jm N / (Ns R)
+        const int t1 = jm << (lg - lgNs - lgR);
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            v[r] = src[j + r * nq];
+            if (r > 0) {
+                float2 w = tw[r * t1];
+                if (inv) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+        }
+        if (R == 2) {
+            dst[o] = make_float2(v[0].x + v[1].x, v[0].y + v[1].y);
+            dst[o + Ns] = make_float2(v[0].x - v[1].x, v[0].y - v[1].y);
+        } else {
+            const float2 a0 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+            const float2 a1 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+            const float2 a2 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+            // (v1 - v3) times -i (forward) or +i (inverse)
+            const float2 d = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
+            const float2 a3 = inv ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+            dst[o] = make_float2(a0.x + a2.x, a0.y + a2.y);
+            dst[o + Ns] = make_float2(a1.x + a3.x, a1.y + a3.y);
+            dst[o + 2 * Ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
+            dst[o + 3 * Ns] = make_float2(a1.x - a3.x, a1.y - a3.y);
+        }
+    }
+}
+
 // cnt transforms of length 2^lg held at a[f << lg .. ]; b is a work buffer of
-// the same size.  tw[k] = exp(-2 pi i k / 2^lg), k < 2^(lg-1); inv selects
-// the conjugate twiddles (exp(+2 pi i ...)).  Inputs must be visible to the
-// whole block on entry; returns the buffer holding the (naturally ordered)
-// result, visible to the whole block.
+// the same size.  tw[k] = exp(-2 pi i k / 2^lg) for k < 2^lg; inv selects the
+// conjugate twiddles (exp(+2 pi i ...)).  Stockham steps of radix 4 (one of
+// radix 2 first when lg is odd).  Inputs must be visible to the whole block
+// on entry; returns the buffer holding the (naturally ordered) result,
+// visible to the whole block.
 template <int NT>
 __device__ float2 *fft_batch(float2 *a, float2 *b, int lg, int cnt, const float2 *tw, bool inv) {
-    const int half = 1 << (lg - 1), total = cnt * half;
-    for (int s = 0; s < lg; ++s) {
-        const int Ns = 1 << s;
+    int lgNs = 0;
+    if (lg & 1) {
         __syncthreads();
-        for (int idx = threadIdx.x; idx < total; idx += NT) {
-            const int f = idx >> (lg - 1), j = idx & (half - 1);
-            const float2 *src = a + (f << lg);
-            float2 *dst = b + (f << lg);
-            const float2 v0 = src[j];
-            float2 t = tw[(j & (Ns - 1)) << (lg - 1 - s)];
-            if (inv) t.y = -t.y;
-            const float2 v1 = cmul(src[j + half], t);
-            const int o = ((j & ~(Ns - 1)) << 1) + (j & (Ns - 1));
-            dst[o] = make_float2(v0.x + v1.x, v0.y + v1.y);
-            dst[o + Ns] = make_float2(v0.x - v1.x, v0.y - v1.y);
-        }
+        fft_step<NT, 2>(a, b, lg, 0, cnt, tw, inv);
+        float2 *x = a;
+        a = b;
+        b = x;
+        lgNs = 1;
+    }
+    for (; lgNs < lg; lgNs += 2) {
+        __syncthreads();
+        fft_step<NT, 4>(a, b, lg, lgNs, cnt, tw, inv);
         float2 *x = a;
         a = b;
         b = x;
@@ -115,12 +158,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     const float h = 2.f / (float)L;
     float2 *fa = lds2, *fb = lds2 + kFftFloats2;
     float2 *Y = fb + kFftFloats2;                      // [slices][M + 1]
-    float2 *twf = Y + (2 * kFftFloats2 / L) * (M + 1);  // [Nf / 2]
-    float2 *twl = twf + (Nf >> 1);                      // [L / 2]
-    float2 *shf = twl + (L >> 1);                       // [L]
+    float2 *twf = Y + (2 * kFftFloats2 / L) * (M + 1);  // [Nf]
+    float2 *twl = twf + Nf;                             // [L]
+    float2 *shf = twl + L;                              // [L]
     float *corr = (float *)(shf + L);                   // [L]
-    for (int t = threadIdx.x; t < (Nf >> 1); t += NT) twf[t] = T.twf[t];
-    for (int t = threadIdx.x; t < (L >> 1); t += NT) twl[t] = T.twl[t];
+    for (int t = threadIdx.x; t < Nf; t += NT) twf[t] = T.twf[t];
+    for (int t = threadIdx.x; t < L; t += NT) twl[t] = T.twl[t];
     for (int t = threadIdx.x; t < L; t += NT) {
         shf[t] = T.shift[t];
         corr[t] = T.corr[t];
@@ -153,31 +196,46 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                 fa[idx] = z;
             }
             const float2 *X = fft_batch<NT>(fa, fb, lgNf, cnt, twf, false);
-            for (int idx = threadIdx.x; idx < cnt * H; idx += NT) {
-                const int f = idx / H, v = idx - f * H;
+            auto unpack = [&](int f, int v) {
                 const float2 zv = X[(f << lgNf) + v], zc = X[(f << lgNf) + ((Nf - v) & (Nf - 1))];
                 const int i = 2 * (p0 + f);
                 // Z = X_i + i X_{i+1}: X_i[v] = (Z[v] + conj Z[-v]) / 2,
                 // X_{i+1}[v] = (Z[v] - conj Z[-v]) / (2 i)
                 R[(size_t)i * H + v] = make_float2(0.5f * (zv.x + zc.x), 0.5f * (zv.y - zc.y));
                 R[(size_t)(i + 1) * H + v] = make_float2(0.5f * (zv.y + zc.y), -0.5f * (zv.x - zc.x));
-            }
+            };
+            for (int idx = threadIdx.x; idx < (cnt << (lgNf - 1)); idx += NT)
+                unpack(idx >> (lgNf - 1), idx & ((Nf >> 1) - 1));
+            for (int f = threadIdx.x; f < cnt; f += NT) unpack(f, Nf >> 1);  // v = Nf/2
         }
         if (bad) sbad = 1;
         // 2. columns
         for (int v0 = 0; v0 < H; v0 += GR) {
             const int cnt = min(GR, H - v0);
             __syncthreads();  // R written; work buffers free
-            for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT) {
-                const int q = idx / cnt, f = idx - q * cnt;
+            // element idx = q cnt + f (f fastest: neighbouring threads take
+            // neighbouring columns); cnt is a power of two except for L <= 16
+            const int lgc = 31 - __builtin_clz(cnt);
+            const bool p2 = (1 << lgc) == cnt;
+            auto load = [&](int q, int f) {
                 const int i = (q < (Nf >> 1) ? q : q - Nf) + M;
                 fa[(f << lgNf) + q] =
                     (i >= 0 && i < L) ? R[(size_t)i * H + v0 + f] : make_float2(0.f, 0.f);
+            };
+            if (p2) {
+                for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT)
+                    load(idx >> lgc, idx & (cnt - 1));
+            } else {
+                for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT)
+                    load(idx / cnt, idx % cnt);
             }
             const float2 *X = fft_batch<NT>(fa, fb, lgNf, cnt, twf, false);
-            for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT) {
-                const int u = idx / cnt, f = idx - u * cnt;
-                B[(size_t)u * Hx + kFourierPad + v0 + f] = X[(f << lgNf) + u];
+            auto store = [&](int u, int f) { B[(size_t)u * Hx + kFourierPad + v0 + f] = X[(f << lgNf) + u]; };
+            if (p2) {
+                for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT)
+                    store(idx >> lgc, idx & (cnt - 1));
+            } else {
+                for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT) store(idx / cnt, idx % cnt);
             }
         }
         __syncthreads();  // B written
@@ -238,7 +296,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
 
 size_t fourier_lds_bytes(int L, int Nf) {
     const int M = L / 2;
-    return sizeof(float2) * (2 * kFftFloats2 + (2 * kFftFloats2 / L) * (M + 1) + Nf / 2 + L / 2 + L) +
+    return sizeof(float2) * (2 * kFftFloats2 + (2 * kFftFloats2 / L) * (M + 1) + Nf + L + L) +
            sizeof(float) * L;
 }
 

@@ -286,7 +286,7 @@ static double es_hat(double zeta) {
 static sw_status get_fourier_tabs(Ctx *ctx, int L, sw::FourierTabs *out) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     const int M = L / 2, Nf = 2 * L;
-    const size_t n2 = (size_t)Nf / 2 + L / 2 + L;  // float2 entries
+    const size_t n2 = (size_t)Nf + L + L;  // float2 entries
     auto f = ctx->fourier_tabs.find(L);
     void *d = nullptr;
     if (f != ctx->fourier_tabs.end()) {
@@ -295,15 +295,14 @@ static sw_status get_fourier_tabs(Ctx *ctx, int L, sw::FourierTabs *out) {
         const double pi = 3.141592653589793238462643383279502884;
         std::vector<float2> t2(n2);
         std::vector<float> corr(L);
-        for (int k = 0; k < Nf / 2; ++k)
+        for (int k = 0; k < Nf; ++k)
             t2[k] = make_float2((float)std::cos(2 * pi * k / Nf), (float)-std::sin(2 * pi * k / Nf));
-        for (int k = 0; k < L / 2; ++k)
-            t2[Nf / 2 + k] =
-                make_float2((float)std::cos(2 * pi * k / L), (float)-std::sin(2 * pi * k / L));
+        for (int k = 0; k < L; ++k)
+            t2[Nf + k] = make_float2((float)std::cos(2 * pi * k / L), (float)-std::sin(2 * pi * k / L));
         for (int t = 0; t < L; ++t) {
             const int k = t < M ? t : t - L;
             const double sg = (k & 1) ? -1.0 : 1.0;
-            t2[Nf / 2 + L / 2 + t] =
+            t2[Nf + L + t] =
                 make_float2((float)(sg * std::cos(pi * k / L)), (float)(sg * std::sin(pi * k / L)));
         }
         for (int j = 0; j < L; ++j) corr[j] = (float)(1.0 / es_hat((double)(j - M) / Nf));
@@ -321,8 +320,8 @@ static sw_status get_fourier_tabs(Ctx *ctx, int L, sw::FourierTabs *out) {
     }
     const float2 *t2 = (const float2 *)d;
     out->twf = t2;
-    out->twl = t2 + Nf / 2;
-    out->shift = t2 + Nf / 2 + L / 2;
+    out->twl = t2 + Nf;
+    out->shift = t2 + Nf + L;
     out->corr = (const float *)(t2 + n2);
     return SW_OK;
 }

@@ -94,8 +94,8 @@ hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable
 // Fourier-slice projector (k_fourier.hip): L a power of two, oversampled
 // grid Nf = 2L, H = Nf/2 + 1 stored spectrum columns.  Tables (device,
 // context-owned): corr[j] = 1 / phihat((j - L/2) / Nf) for the interpolation
-// kernel phi, twf[k] = exp(-2 pi i k / Nf) (k < Nf/2), twl[k] =
-// exp(-2 pi i k / L) (k < L/2), shift[t] = (-1)^k exp(i pi k / L) with
+// kernel phi, twf[k] = exp(-2 pi i k / Nf) (k < Nf), twl[k] =
+// exp(-2 pi i k / L) (k < L), shift[t] = (-1)^k exp(i pi k / L) with
 // k = t for t < L/2 and t - L otherwise.  The scratch holds `slots` regions
 // of fourier_slot_bytes; the grid is min(N, slots) persistent blocks.
 // targets: per slice point (theta_m, k pi), m < n/2, k <= L/2, in that
