@@ -622,7 +622,8 @@ def _pool(L, N, seed, distinct=None):
     return ref_p, imgs_p
 
 
-def bench_serving(api, torch, n_req, Ls=(128,), pool_n=5000, seed=1004, distinct=None):
+def bench_serving(api, torch, n_req, Ls=(128,), pool_n=5000, seed=1004, distinct=None,
+                  max_slots=64):
     """Poisson trace of requests (1 reference + N images, N log-uniform in
     [1, 5000]); served bf16 form (continuous batching) against the plain FP32
     path serving one request at a time.  Images come from a pool of rendered
@@ -664,7 +665,7 @@ def bench_serving(api, torch, n_req, Ls=(128,), pool_n=5000, seed=1004, distinct
 
     def served(arrivals):
         ctx = api.Context(0)
-        srv = api.Server(ctx, hbm_budget_bytes=16 << 30, prec=1, max_slots=64)
+        srv = api.Server(ctx, hbm_budget_bytes=16 << 30, prec=1, max_slots=max_slots)
         tickets = [None] * len(reqs)
         done = np.zeros(len(reqs))
         t0 = time.perf_counter()
