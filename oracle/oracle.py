@@ -153,7 +153,7 @@ def _disk_mask(L: int):
     return (2 * j - L + 1) ** 2 + (2 * i - L + 1) ** 2 <= (L - 2) ** 2
 
 
-def fourier_project(img: np.ndarray, n: int, cell: bool = True):
+def fourier_project(img: np.ndarray, n: int, cell: bool = True, angles=None):
     """Fourier-slice projections (Sec. 2.2, Fourier slice theorem; the
     discretisation of the fixed-angle error theorem with NUFFT precision in
     the appendix), written out as the exact non-uniform DFT that a NUFFT
@@ -169,16 +169,22 @@ def fourier_project(img: np.ndarray, n: int, cell: bool = True):
     (cell=False: point masses); the projection is the trigonometric
     polynomial g(s) = (1/2) sum_k yhat_k exp(i k pi s) sampled at the bin
     centres s_b = -1 + (b + 1/2) h, P[a][b] = h * Re g(s_b).  Negative lobes
-    are kept (the caller clips).  Returns (P [N, n, L] float64, non-finite
-    flag [N] int32); an image with a non-finite value gives NaN.
-    Plain double sum per angle: O(n L^3) per image."""
+    are kept (the caller clips).  With `angles` (n radians) the slices are
+    taken at those angles instead of theta_a = 2 pi a / n.  Returns (P [N,
+    n, L] float64, non-finite flag [N] int32); an image with a non-finite
+    value gives NaN.  Plain double sum per angle: O(n L^3) per image."""
     img = np.asarray(img, dtype=np.float64)
     if img.ndim == 2:
         img = img[None]
     N, L, L2 = img.shape
     assert L == L2 and L % 2 == 0
     M, h, c0 = L // 2, 2.0 / L, 0.5 * (L - 1)
-    cs, sn = angle_table(n)
+    if angles is None:
+        cs, sn = angle_table(n)
+    else:
+        angles = np.asarray(angles, dtype=np.float64)
+        assert angles.shape == (n,)
+        cs, sn = np.cos(angles), np.sin(angles)
     pos = (np.arange(L) - c0) * h            # x_j for columns, y_i for rows
     k = np.arange(-M, M, dtype=np.float64)
     sb = -1.0 + (np.arange(L) + 0.5) * h
@@ -204,12 +210,32 @@ def fourier_project(img: np.ndarray, n: int, cell: bool = True):
     return out, bad
 
 
-def fourier_tables(img: np.ndarray, n: int, Q: int, levels: int = LEVELS_MIDPOINT):
+def fourier_tables(img: np.ndarray, n: int, Q: int, levels: int = LEVELS_MIDPOINT, angles=None):
     """Quantile tables of the Fourier-slice projections with negative lobes
     clipped to zero before normalisation (Sec. 2.3: the outputs are
-    normalised into probability measures)."""
-    P, bad = fourier_project(img, n)
+    normalised into probability measures); optionally at given angles."""
+    P, bad = fourier_project(img, n, angles=angles)
     return quantiles(np.maximum(P, 0.0), Q, levels, bad)
+
+
+def mc_angles(n: int, seed: int):
+    """n directions drawn uniformly on the circle (PCG64, `seed`), sorted:
+    the Monte-Carlo SW directions of the extended alignment results.  This
+    draws random numbers only; the method takes the angles as an input."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.uniform(0.0, 2.0 * np.pi, n))
+
+
+def mc_align_images(ref_img, imgs, n: int, Q: int, angles, levels: int = LEVELS_MIDPOINT,
+                    want_curve: bool = False):
+    """Monte-Carlo SW2 over rotations (extended alignment results): the
+    projections are taken at n given directions (sorted), and the discrete
+    rotational SW2 scan is applied unchanged, lag l read as the rotation
+    2 pi l / n; rotation only."""
+    L = imgs.shape[-1]
+    rq, ra = fourier_tables(ref_img, n, Q, levels, angles)
+    iq, ia = fourier_tables(imgs, n, Q, levels, angles)
+    return align(rq, ra, iq, ia, L, mode=MODE_ROT_ONLY, want_curve=want_curve)
 
 
 def tables(img: np.ndarray, n: int, Q: int, levels: int = LEVELS_MIDPOINT, ramp: bool = False):

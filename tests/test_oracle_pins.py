@@ -676,3 +676,63 @@ def test_fourier_close_to_line_sum_for_smooth_image(oracle):
     assert l1.max() < 0.08, l1.max()
     # a wrong angle convention is far off
     assert np.abs(PF - PL[::-1]).sum(axis=1).max() > 0.2
+
+
+# ---------------------------------------------------------------- Monte-Carlo SW over rotations
+def test_fourier_at_given_angles(oracle):
+    """Slices at explicit angles: the grid angles reproduce the default table,
+    and one point mass at random angles gives the closed-form Dirichlet
+    kernel at its projected position.  Catches angles applied with the
+    wrong sign or the default table ignoring the argument."""
+    L, n = 32, 16
+    M, h = L // 2, 2.0 / L
+    img = blob_img(L, seed=12)
+    P0, _ = oracle.fourier_project(img, n)
+    P1, _ = oracle.fourier_project(img, n, angles=2 * np.pi * np.arange(n) / n)
+    assert np.max(np.abs(P0 - P1)) < 1e-12 * P0.max()
+    pt = np.zeros((L, L), np.float32)
+    i0, j0 = 9, 21
+    pt[i0, j0] = 1.0
+    th = oracle.mc_angles(n, 3)
+    P, _ = oracle.fourier_project(pt, n, cell=False, angles=th)
+    c0 = 0.5 * (L - 1)
+    sb = -1.0 + (np.arange(L) + 0.5) * h
+    for a in range(n):
+        t0 = (j0 - c0) * h * np.cos(th[a]) - (i0 - c0) * h * np.sin(th[a])
+        x = np.pi * (sb - t0)
+        assert np.max(np.abs(P[0, a] - 0.5 * h * np.sin(M * x) / np.tan(x / 2))) < 1e-12
+
+
+def test_mc_with_grid_directions_is_the_rotation_scan(oracle):
+    """Monte-Carlo SW2 with the n equispaced directions in place of random
+    ones is exactly the rotation-only SW2 scan of the same tables (the
+    method differs only in its directions).  Catches a lag convention or a
+    normalisation that differs between the two."""
+    L, n, Q = 32, 32, 32
+    ref = blob_img(L, seed=21)
+    imgs = np.stack([np.rot90(ref, 1).copy(), blob_img(L, seed=22)])
+    grid = 2 * np.pi * np.arange(n) / n
+    r = oracle.mc_align_images(ref[None], imgs, n, Q, grid, want_curve=True)
+    rq, ra = oracle.fourier_tables(ref[None], n, Q)
+    iq, ia = oracle.fourier_tables(imgs, n, Q)
+    o = oracle.align(rq, ra, iq, ia, L, mode=oracle.MODE_ROT_ONLY, want_curve=True)
+    assert np.array_equal(r["rot_index"], o["rot_index"])
+    assert np.max(np.abs(r["curve"] - o["curve"])) < 1e-15
+    # a quarter turn of the image is a shift of n/4 columns (the sign of the
+    # lag follows the rotation-direction convention of the scan)
+    assert r["rot_index"][0] in (n // 4, 3 * n // 4)
+
+
+def test_mc_random_directions_find_planted_rotations(oracle):
+    """With sorted random directions the scan is approximate (a column shift
+    is a rotation only on average); on blob images it still finds planted
+    quarter and half turns to within a few grid steps, as the paper reports
+    for its Monte-Carlo variant.  Catches unsorted directions or a mismatch
+    between the directions of the two images."""
+    L, n, Q = 32, 64, 32
+    ref = blob_img(L, seed=31)
+    imgs = np.stack([np.rot90(ref, k).copy() for k in (1, 2, 3)])
+    r = oracle.mc_align_images(ref[None], imgs, n, Q, oracle.mc_angles(n, 7))
+    g = oracle.mc_align_images(ref[None], imgs, n, Q, 2 * np.pi * np.arange(n) / n)
+    err = np.abs(((r["rot_index"] - g["rot_index"]) + n // 2) % n - n // 2)
+    assert err.max() <= 3, (r["rot_index"], g["rot_index"])
