@@ -121,7 +121,7 @@ typedef struct {
 /* Scratch: the context owns one scratch buffer (grown on demand) that the
    calls needing it share: sw_tables / sw_tables_rf when they take their
    chunked or small-batch path, sw_align_batch (except the max-sliced mode)
-   and sw_align_stacks, sw_project_fourier and sw_tables_fourier;
+   and sw_align_stacks, sw_project_fourier(_at) and sw_tables_fourier(_at);
    sw_project, sw_ramp, sw_quantiles and sw_quantiles_rf never.  Calls on
    different streams may overlap only when at most one of them uses scratch (e.g. the tables of a single
    reference on a side stream next to the fused tables of a large image
@@ -212,6 +212,24 @@ sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_ge
    buffer: images to quantile tables with the Fourier-slice projector. */
 sw_status sw_tables_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/,
                             float *qt, double *aux, void *stream);
+
+/* The same projections at n_angles explicit directions theta[k] (radians,
+   any values; d_k = (cos theta_k, -sin theta_k)) instead of 2 pi k / n, each
+   slice computed on its own.  This is the Monte-Carlo SW of the extended
+   alignment results: draw the directions uniformly on the circle, sort
+   them, build both images' tables with the same theta, and run
+   sw_align_batch in SW_MODE_ROT_ONLY (the column-shift scan unchanged, lag
+   l read as the rotation 2 pi l / n; the closed-form translation assumes
+   equispaced directions).  sw_tables_fourier_at computes the quantile
+   tables with aux moments over these directions.  theta: host
+   [n_angles] float64, read during the call (the slice tables are cached
+   per distinct theta in the context).  Otherwise as sw_project_fourier and
+   sw_tables_fourier. */
+sw_status sw_project_fourier_at(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/,
+                                const double *theta /*host*/, float *pmf, void *stream);
+sw_status sw_tables_fourier_at(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/,
+                               const double *theta /*host*/, float *qt, double *aux,
+                               void *stream);
 
 /* Steps 3-5: alignment of table pairs.
    For each pair (r, g): the angle spectra of both tables, the correlation

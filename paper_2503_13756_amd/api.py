@@ -75,29 +75,49 @@ def project(ctx: Context, imgs: torch.Tensor, n: int, stream=None, out=None):
     return pmf
 
 
-def project_fourier(ctx: Context, imgs: torch.Tensor, n: int, stream=None, out=None):
+def _angles(theta, n):
+    import numpy as np
+
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    if th.shape != (n,):
+        raise ValueError(f"theta must hold n = {n} angles, got shape {th.shape}")
+    return th, th.ctypes.data_as(ctypes.c_void_p)
+
+
+def project_fourier(ctx: Context, imgs: torch.Tensor, n: int, stream=None, out=None, theta=None):
     """sw_project_fourier: [N, L, L] float32 -> [N, n, L] float32 projections
-    by the Fourier slice theorem (L a power of two)."""
+    by the Fourier slice theorem (L a power of two); with theta (n radians,
+    host) sw_project_fourier_at at those directions."""
     _need(imgs, torch.float32, "imgs")
     N, L = imgs.shape[0], imgs.shape[-1]
     g = geom(L, n, 8)
     pmf = out if out is not None else torch.empty((N, n, L), dtype=torch.float32, device=imgs.device)
-    check(ctx._lib.sw_project_fourier(ctx.handle, _ptr(imgs), N, ctypes.byref(g), _ptr(pmf),
-                                      _stream(stream)))
+    if theta is None:
+        check(ctx._lib.sw_project_fourier(ctx.handle, _ptr(imgs), N, ctypes.byref(g), _ptr(pmf),
+                                          _stream(stream)))
+    else:
+        th, tp = _angles(theta, n)
+        check(ctx._lib.sw_project_fourier_at(ctx.handle, _ptr(imgs), N, ctypes.byref(g), tp,
+                                             _ptr(pmf), _stream(stream)))
     return pmf
 
 
 def tables_fourier(ctx: Context, imgs: torch.Tensor, n: int, Q: int, levels=_abi.LEVELS_MIDPOINT,
-                   stream=None, out=None, aux=None):
+                   stream=None, out=None, aux=None, theta=None):
     """sw_tables_fourier: images to quantile tables [N, Q, n] through the
-    Fourier-slice projector."""
+    Fourier-slice projector; with theta, sw_tables_fourier_at."""
     _need(imgs, torch.float32, "imgs")
     N, L = imgs.shape[0], imgs.shape[-1]
     g = geom(L, n, Q, levels)
     qt = out if out is not None else torch.empty((N, Q, n), dtype=torch.float32, device=imgs.device)
     ax = aux if aux is not None else torch.empty((N, 4), dtype=torch.float64, device=imgs.device)
-    check(ctx._lib.sw_tables_fourier(ctx.handle, _ptr(imgs), N, ctypes.byref(g), _ptr(qt), _ptr(ax),
-                                     _stream(stream)))
+    if theta is None:
+        check(ctx._lib.sw_tables_fourier(ctx.handle, _ptr(imgs), N, ctypes.byref(g), _ptr(qt),
+                                         _ptr(ax), _stream(stream)))
+    else:
+        th, tp = _angles(theta, n)
+        check(ctx._lib.sw_tables_fourier_at(ctx.handle, _ptr(imgs), N, ctypes.byref(g), tp,
+                                            _ptr(qt), _ptr(ax), _stream(stream)))
     return qt, ax
 
 

@@ -37,6 +37,9 @@ struct Ctx {
     std::map<int, float *> ramp_tables;  // ramp filter kernel per L
     std::map<int, void *> fourier_tabs;     // Fourier-slice projector tables per L
     std::map<int, void *> fourier_targets;  // its slice-point tables, key L * 4096 + n
+    // slice-point tables for explicit angles: (L, n, the angles' bytes) -> table
+    std::map<std::string, void *> fourier_dir_targets;
+    std::map<std::string, sw::AngleTable> fourier_dir_angles;  // their direction tables
     std::map<int, int> tile_R;  // projection strip rows per L (autotuner)
     // batches of fewer images take the split (many blocks per image) launches;
     // -1: the number of compute units

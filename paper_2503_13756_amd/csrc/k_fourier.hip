@@ -15,7 +15,8 @@
 //     the slot's scratch (R).
 //  2. columns: the same transform along y for every v <= Nf/2 (B, the
 //     oversampled spectrum; the other half is its conjugate mirror).
-//  3. slices: every slice point k pi d_theta (theta in [0, pi), k = 0..M) is
+//  3. slices: every slice point k pi d_theta (theta in [0, pi), k = 0..M, or
+//     every given angle) is
 //     interpolated from B with a separable exponential-of-semicircle kernel
 //     of width kW, phase-shifted to the pixel centres and multiplied by the
 //     transform of one pixel cell; the coefficients of two slices are packed
@@ -253,8 +254,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         const bool isbad = sbad != 0;
         float *out = pmf + g * (int64_t)n * L;
         // 3. slices theta_m, m < n/2, two per inverse transform
-        for (int m0 = 0; m0 < (n >> 1); m0 += 2 * GS) {
-            const int ns = min(2 * GS, (n >> 1) - m0);  // even: n is a multiple of 8
+        // slices m < nsl: nsl = n/2 with their theta + pi mirrors, or all n
+        // (slices at explicit angles)
+        const int nsl = S.mirror ? (n >> 1) : n;
+        for (int m0 = 0; m0 < nsl; m0 += 2 * GS) {
+            const int ns = min(2 * GS, nsl - m0);  // even: n is a multiple of 8
             for (int idx = threadIdx.x; idx < ns * (M + 1); idx += NT)
                 Y[idx] = slice_point(B, Nf, Hx, T.targets + 5 * ((size_t)m0 * (M + 1) + idx));
             __syncthreads();
@@ -283,9 +287,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                 const float p1 = isbad ? qnan : fmaxf(0.5f * h * z.x, 0.f);
                 const float p2 = isbad ? qnan : fmaxf(0.5f * h * z.y, 0.f);
                 out[(int64_t)m1 * L + b] = p1;
-                out[(int64_t)(m1 + (n >> 1)) * L + (L - 1 - b)] = p1;
                 out[(int64_t)m2 * L + b] = p2;
-                out[(int64_t)(m2 + (n >> 1)) * L + (L - 1 - b)] = p2;
+                if (S.mirror) {
+                    out[(int64_t)(m1 + (n >> 1)) * L + (L - 1 - b)] = p1;
+                    out[(int64_t)(m2 + (n >> 1)) * L + (L - 1 - b)] = p2;
+                }
             }
             __syncthreads();  // Y and the work buffers are rewritten next round
         }

@@ -332,28 +332,21 @@ static double es_phi(double z) {
                               : 0.0;
 }
 
-// Slice-point table of the Fourier-slice projector for (L, n): for theta_m,
-// m < n/2, and k = 0 .. L/2, the fine-grid point g = k d_m Nf / L of the
-// slice frequency k pi d_m (mirrored to g_x >= 0, the conjugate then taken
-// in the kernel), its first tap row u0 and column v0 of the kernel's
-// support, the kernel weights per row and column, and the factor
-// exp(-i pi k (d_x + d_y) / L) sinc(pi k d_x / L) sinc(pi k d_y / L) (the
-// pixel centres' half-pixel offset and the transform of one pixel cell),
-// all from FP64.  Layout as read by slice_point in k_fourier.hip.
-static sw_status get_fourier_targets(Ctx *ctx, int L, int n, const float4 **out) {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    const int key = L * 4096 + n;
-    auto f = ctx->fourier_targets.find(key);
-    if (f != ctx->fourier_targets.end()) {
-        *out = (const float4 *)f->second;
-        return SW_OK;
-    }
+// Slice-point table of the Fourier-slice projector for L and the slice
+// directions d = (c[m], -s[m]): for each slice m and k = 0 .. L/2, the
+// fine-grid point g = k d Nf / L of the slice frequency k pi d (mirrored to
+// g_x >= 0, the conjugate then taken in the kernel), its first tap row u0
+// and column v0 of the kernel's support, the kernel weights per row and
+// column, and the factor exp(-i pi k (d_x + d_y) / L) sinc(pi k d_x / L)
+// sinc(pi k d_y / L) (the pixel centres' half-pixel offset and the transform
+// of one pixel cell), all from FP64.  Layout as read by slice_point in
+// k_fourier.hip.
+static std::vector<float4> fourier_target_table(int L, const std::vector<double> &c,
+                                                const std::vector<double> &s) {
     const double pi = 3.141592653589793238462643383279502884;
-    const int M = L / 2, Nf = 2 * L, W = sw::kFourierW;
-    std::vector<double> c, s;
-    angle_values(n, c, s);
-    std::vector<float4> tab((size_t)(n / 2) * (M + 1) * 5);
-    for (int m = 0; m < n / 2; ++m) {
+    const int M = L / 2, Nf = 2 * L, W = sw::kFourierW, nsl = (int)c.size();
+    std::vector<float4> tab((size_t)nsl * (M + 1) * 5);
+    for (int m = 0; m < nsl; ++m) {
         const double dx = c[m], dy = -s[m];
         const bool flip = dx < 0.0;
         for (int k = 0; k <= M; ++k) {
@@ -378,16 +371,91 @@ static sw_status get_fourier_targets(Ctx *ctx, int L, int n, const float4 **out)
             e[4] = make_float4(wy[4], wy[5], wy[6], 0.f);
         }
     }
-    void *d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(float4) * tab.size());
+    return tab;
+}
+
+static sw_status upload_table(const std::vector<float4> &tab, void **d) {
+    hipError_t e = hipMalloc(d, sizeof(float4) * tab.size());
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(Fourier slice table)");
-    e = hipMemcpy(d, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice);
+    e = hipMemcpy(*d, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(d);
+        (void)hipFree(*d);
         return hip_fail(e, "hipMemcpy(Fourier slice table)");
     }
+    return SW_OK;
+}
+
+// Table for the grid angles theta_m = 2 pi m / n, m < n/2 (the kernel writes
+// the theta + pi mirrors).
+static sw_status get_fourier_targets(Ctx *ctx, int L, int n, const float4 **out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int key = L * 4096 + n;
+    auto f = ctx->fourier_targets.find(key);
+    if (f != ctx->fourier_targets.end()) {
+        *out = (const float4 *)f->second;
+        return SW_OK;
+    }
+    std::vector<double> c, s;
+    angle_values(n, c, s);
+    c.resize(n / 2);
+    s.resize(n / 2);
+    void *d = nullptr;
+    sw_status st = upload_table(fourier_target_table(L, c, s), &d);
+    if (st != SW_OK) return st;
     ctx->fourier_targets.emplace(key, d);
     *out = (const float4 *)d;
+    return SW_OK;
+}
+
+// Slice-point table and direction table (cos theta, -sin theta) for n
+// explicit angles (radians), cached by the angles' exact bytes.
+static sw_status get_fourier_dir_targets(Ctx *ctx, int L, int n, const double *theta,
+                                         const float4 **out, const sw::AngleTable **dirs) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::string key((const char *)&L, sizeof(int));
+    key.append((const char *)theta, sizeof(double) * n);
+    auto f = ctx->fourier_dir_targets.find(key);
+    if (f != ctx->fourier_dir_targets.end()) {
+        *out = (const float4 *)f->second;
+        *dirs = &ctx->fourier_dir_angles.at(key);
+        return SW_OK;
+    }
+    std::vector<double> c(n), s(n);
+    std::vector<float2> t32(n);
+    std::vector<double2> t64(n);
+    for (int m = 0; m < n; ++m) {
+        c[m] = std::cos(theta[m]);
+        s[m] = std::sin(theta[m]);
+        t32[m] = make_float2((float)c[m], (float)(-s[m]));
+        t64[m] = make_double2(c[m], -s[m]);
+    }
+    void *d = nullptr;
+    sw_status st = upload_table(fourier_target_table(L, c, s), &d);
+    if (st != SW_OK) return st;
+    sw::AngleTable t;
+    t.n = n;
+    hipError_t e = hipMalloc(&t.d32, sizeof(float2) * n);
+    if (e == hipSuccess) {
+        e = hipMalloc(&t.d64, sizeof(double2) * n);
+        if (e != hipSuccess) (void)hipFree(t.d32);
+    }
+    if (e == hipSuccess) {
+        e = hipMemcpy(t.d32, t32.data(), sizeof(float2) * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(t.d64, t64.data(), sizeof(double2) * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(t.d32);
+            (void)hipFree(t.d64);
+        }
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "direction table");
+    }
+    ctx->fourier_dir_targets.emplace(key, d);
+    auto it = ctx->fourier_dir_angles.emplace(key, t).first;
+    *out = (const float4 *)d;
+    *dirs = &it->second;
     return SW_OK;
 }
 
@@ -624,6 +692,11 @@ sw_status sw_ctx_destroy(void *ctx) {
         for (auto &kv : c->ramp_tables) (void)hipFree(kv.second);
         for (auto &kv : c->fourier_tabs) (void)hipFree(kv.second);
         for (auto &kv : c->fourier_targets) (void)hipFree(kv.second);
+        for (auto &kv : c->fourier_dir_targets) (void)hipFree(kv.second);
+        for (auto &kv : c->fourier_dir_angles) {
+            (void)hipFree(kv.second.d32);
+            (void)hipFree(kv.second.d64);
+        }
         if (c->scratch) (void)hipFree(c->scratch);
         for (int i = 0; i < DescRing::kSlots; ++i)
             if (c->ring.ev[i]) (void)hipEventDestroy(c->ring.ev[i]);
@@ -805,8 +878,9 @@ sw_status sw_tables_rf(void *ctx, const float *img, int64_t N, const sw_geom *g,
 }
 
 // Geometry and scratch of the Fourier-slice projector: L a power of two.
-static sw_status fourier_setup(Ctx *c, const sw::Geo &geo, int64_t N, sw::FourierShape *S,
-                               sw::FourierTabs *T, int *slots) {
+static sw_status fourier_setup(Ctx *c, const sw::Geo &geo, int64_t N, const double *theta,
+                               sw::FourierShape *S, sw::FourierTabs *T, int *slots,
+                               const sw::AngleTable **dirs) {
     const int lg = log2_exact(geo.L);
     if (lg < 0)
         return fail(SW_E_INVALID, "the Fourier-slice projector needs L a power of two (L = %d)",
@@ -817,17 +891,27 @@ static sw_status fourier_setup(Ctx *c, const sw::Geo &geo, int64_t N, sw::Fourie
     S->lgNf = lg + 1;
     S->lgL = lg;
     S->H = geo.L + 1;
+    S->mirror = theta ? 0 : 1;
     sw_status st = get_fourier_tabs(c, geo.L, T);
     if (st != SW_OK) return st;
-    if ((st = get_fourier_targets(c, geo.L, geo.n, &T->targets)) != SW_OK) return st;
+    if (theta) {
+        for (int m = 0; m < geo.n; ++m)
+            if (!std::isfinite(theta[m]))
+                return fail(SW_E_INVALID, "angle %d is not finite", m);
+        st = get_fourier_dir_targets(c, geo.L, geo.n, theta, &T->targets, dirs);
+    } else {
+        st = get_fourier_targets(c, geo.L, geo.n, &T->targets);
+        if (st == SW_OK) st = get_table(c, geo.n, dirs);
+    }
+    if (st != SW_OK) return st;
     // one slot per block that can be resident at once
     const int64_t cap = (int64_t)sw::fourier_blocks_per_cu(S->L, S->Nf) * c->cu_count;
     *slots = (int)(N < cap ? N : cap);
     return SW_OK;
 }
 
-sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g, float *pmf,
-                             void *stream) {
+static sw_status project_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g,
+                                 const double *theta, float *pmf, void *stream) {
     if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
     sw::Geo geo;
     sw_status st = check_geom(g, &geo);
@@ -841,7 +925,9 @@ sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_ge
     sw::FourierShape S;
     sw::FourierTabs T;
     int slots;
-    if ((st = fourier_setup(c, geo, N, &S, &T, &slots)) != SW_OK) return st;
+    const sw::AngleTable *dirs;
+    if ((st = fourier_setup(c, geo, N, theta, &S, &T, &slots, &dirs)) != SW_OK) return st;
+    (void)dirs;  // the projection needs the slice-point table only
     hipStream_t s = (hipStream_t)stream;
     void *scr;
     if ((st = get_scratch(c, sw::fourier_slot_bytes(S.L, S.Nf) * slots, s, &scr)) != SW_OK)
@@ -850,8 +936,19 @@ sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_ge
     return e == hipSuccess ? SW_OK : hip_fail(e, "k_fourier launch");
 }
 
-sw_status sw_tables_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g, float *qt,
-                            double *aux, void *stream) {
+sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g, float *pmf,
+                             void *stream) {
+    return project_fourier(ctx, img, N, g, nullptr, pmf, stream);
+}
+
+sw_status sw_project_fourier_at(void *ctx, const float *img, int64_t N, const sw_geom *g,
+                                const double *theta, float *pmf, void *stream) {
+    if (!theta) return fail(SW_E_INVALID, "theta is NULL");
+    return project_fourier(ctx, img, N, g, theta, pmf, stream);
+}
+
+static sw_status tables_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g,
+                                const double *theta, float *qt, double *aux, void *stream) {
     if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
     sw::Geo geo;
     sw_status st = check_geom(g, &geo);
@@ -862,12 +959,11 @@ sw_status sw_tables_fourier(void *ctx, const float *img, int64_t N, const sw_geo
     Ctx *c = as_ctx(ctx);
     DeviceGuard dg(c->device);
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-    const sw::AngleTable *t;
-    if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
     sw::FourierShape S;
     sw::FourierTabs T;
     int slots;
-    if ((st = fourier_setup(c, geo, N, &S, &T, &slots)) != SW_OK) return st;
+    const sw::AngleTable *dirs;
+    if ((st = fourier_setup(c, geo, N, theta, &S, &T, &slots, &dirs)) != SW_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     // projections of a chunk of images, then their quantile tables; the
     // scratch holds the chunk's projections and the projector's slots
@@ -887,11 +983,22 @@ sw_status sw_tables_fourier(void *ctx, const float *img, int64_t N, const sw_geo
         hipError_t e = sw::launch_fourier(img + i0 * (int64_t)geo.L * geo.L, m, S, T, slot_mem,
                                           slots, pmf, s);
         if (e != hipSuccess) return hip_fail(e, "k_fourier launch");
-        e = sw::launch_quantiles(pmf, m, geo, *t, qt + i0 * (int64_t)geo.Q * geo.n,
+        e = sw::launch_quantiles(pmf, m, geo, *dirs, qt + i0 * (int64_t)geo.Q * geo.n,
                                  aux ? aux + 4 * i0 : nullptr, s, c->small(m));
         if (e != hipSuccess) return hip_fail(e, "k_quantile launch");
     }
     return SW_OK;
+}
+
+sw_status sw_tables_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g, float *qt,
+                            double *aux, void *stream) {
+    return tables_fourier(ctx, img, N, g, nullptr, qt, aux, stream);
+}
+
+sw_status sw_tables_fourier_at(void *ctx, const float *img, int64_t N, const sw_geom *g,
+                               const double *theta, float *qt, double *aux, void *stream) {
+    if (!theta) return fail(SW_E_INVALID, "theta is NULL");
+    return tables_fourier(ctx, img, N, g, theta, qt, aux, stream);
 }
 
 sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *curve,

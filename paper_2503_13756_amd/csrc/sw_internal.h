@@ -98,12 +98,15 @@ hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable
 // exp(-2 pi i k / L) (k < L), shift[t] = (-1)^k exp(i pi k / L) with
 // k = t for t < L/2 and t - L otherwise.  The scratch holds `slots` regions
 // of fourier_slot_bytes; the grid is min(N, slots) persistent blocks.
-// targets: per slice point (theta_m, k pi), m < n/2, k <= L/2, in that
-// order, five float4 (layout at slice_point in k_fourier.hip).
+// targets: per slice point (theta_m, k pi), m < n/2 (n with explicit
+// angles), k <= L/2, in that order, five float4 (layout at slice_point in
+// k_fourier.hip).
 constexpr int kFourierW = 7;    // interpolation kernel width in fine-grid points
 constexpr int kFourierPad = 4;  // mirrored spectrum columns kept on each side
 struct FourierShape {
     int L, n, Nf, lgNf, lgL, H;
+    int mirror;  // 1: slices theta_m = 2 pi m / n, m < n/2, plus their theta + pi
+                 // mirrors; 0: n slices at explicit angles (the targets table)
 };
 struct FourierTabs {
     const float *corr;

@@ -130,3 +130,50 @@ def test_fourier_tables_and_alignment(api, ctx, oracle, L, n, Q):
     g = api.unpack_results(res)
     o = oracle.align(oq, oa, iq0, ia0, L, want_curve=True)
     parity.check(g, o, L, parity.TAU_FP32, o["curve"])
+
+
+# ---------------------------------------------------------------- explicit angles, Monte-Carlo SW2
+@pytest.mark.parametrize("L,n", [(16, 16), (64, 48), (128, 128)])
+def test_fourier_at_random_angles_parity(api, ctx, oracle, L, n):
+    """Slices at sorted random directions (each computed on its own, no
+    half-turn mirror) against the oracle's exact DFT at the same angles."""
+    theta = oracle.mc_angles(n, 40 + L)
+    _, imgs = blob_stack(L, 2, 700 + L)
+    pmf = api.project_fourier(ctx, dev(imgs), n, theta=theta).cpu().numpy()
+    P0, _ = oracle.fourier_project(imgs, n, angles=theta)
+    assert proj_err(pmf, P0).max() < TOL_PROJ
+
+
+def test_fourier_at_grid_angles_equals_default(api, ctx):
+    """Explicit angles equal to the grid give the default projections: both
+    approximate the same exact values to TOL_PROJ (the slices at theta + pi
+    are computed directly here and mirrored by default)."""
+    L, n = 64, 32
+    _, imgs = blob_stack(L, 3, 91)
+    a = api.project_fourier(ctx, dev(imgs), n).cpu().numpy()
+    b = api.project_fourier(ctx, dev(imgs), n, theta=2 * np.pi * np.arange(n) / n).cpu().numpy()
+    assert np.abs(a - b).max() <= 2 * TOL_PROJ * a.max(axis=(1, 2)).min()
+
+
+def test_fourier_at_rejects_bad_angles(api, ctx):
+    imgs = synth.uniform_images(5, 32, 1)
+    th = np.zeros(16)
+    th[3] = np.nan
+    with pytest.raises(RuntimeError, match="not finite"):
+        api.project_fourier(ctx, dev(imgs), 16, theta=th)
+
+
+@pytest.mark.parametrize("L,n,Q", [(32, 64, 32), (128, 128, 128)])
+def test_monte_carlo_sw_alignment_parity(api, ctx, oracle, L, n, Q):
+    """Monte-Carlo SW2 over rotations: tables at sorted random directions,
+    rotation-only scan on the GPU, against the oracle (rotation tie-aware,
+    distance)."""
+    theta = oracle.mc_angles(n, 77)
+    N = 6 if L == 128 else 12
+    ref, imgs = blob_stack(L, N, 800 + L)
+    rq, ra = api.tables_fourier(ctx, dev(ref[None]), n, Q, theta=theta)
+    iq, ia = api.tables_fourier(ctx, dev(imgs), n, Q, theta=theta)
+    res, _ = api.align_batch(ctx, rq, ra, iq, ia, L, mode=1, want_curve=True)
+    g = api.unpack_results(res)
+    o = oracle.mc_align_images(ref[None], imgs, n, Q, theta, want_curve=True)
+    parity.check(g, o, L, parity.TAU_FP32, o["curve"])
