@@ -453,26 +453,49 @@ def bench_fourier(api, ctx, torch, ref, imgs, pmf, L, n, Q, line_tables_ms, K=5)
     out["L256"] = {"images": N2, "projector_ms": t_f2, "line_sum_projector_ms": t_l2,
                    "projector_tflops": fourier_flops(L2, L2) * N2 / (t_f2 * 1e-3) / 1e12}
     del big, p2
-    return out, (rq, ra, api.unpack_results(res))
+    fourier_res = (rq, ra, api.unpack_results(res))
+    # Monte-Carlo SW2 (extended alignment results): the same images, slices at
+    # n sorted random directions (seeded), rotation-only scan
+    theta = synth.mc_angles(n, 2024)
+    iq = torch.empty((N, Q, n), dtype=torch.float32, device=dev)
+    ia = torch.empty((N, 4), dtype=torch.float64, device=dev)
+    mq, ma = api.tables_fourier(ctx, ref, n, Q, theta=theta)
+    t_mt = timed(torch, lambda: api.tables_fourier(ctx, imgs, n, Q, out=iq, aux=ia, theta=theta), K)
+    t_ma = timed(torch, lambda: api.align_batch(ctx, mq, ma, iq, ia, L, mode=1, out=res), K)
+    out["monte_carlo"] = {
+        "workload": f"1 reference vs {N} images, L={L}, n=Q={L}: slices at {n} sorted uniform "
+                    "random directions (seed 2024), rotation-only scan",
+        "tables_ms": t_mt, "align_ms": t_ma, "value": N / ((t_mt + t_ma) * 1e-3),
+        "unit": "alignments/s",
+        "paper_context": "Monte-Carlo SW2 costs 0.97x SW2 on CPU (Table 4 of the extended results: "
+                         "0.568 s vs 0.586 s)"}
+    del iq, ia
+    return out, (fourier_res, (theta, api.unpack_results(res)))
 
 
 def fourier_parity(w, r, L, n, Q, S=16):
     """Oracle Fourier-slice tables and alignment of the first S images against
-    the GPU's."""
+    the GPU's, for the grid directions and for the Monte-Carlo ones."""
     from oracle import oracle as O
     from tests import parity
 
-    rq, ra, g = r
+    (rq, ra, g), (theta, gm) = r
     S = min(S, len(w["imgs"]))
+    out = {}
     oq, oa = O.fourier_tables(w["ref"][None], n, Q)
     iq0, ia0 = O.fourier_tables(w["imgs"][:S], n, Q)
-    o = O.align(oq, oa, iq0, ia0, L, want_curve=True)
-    sub = {k: v[:S] for k, v in g.items()}
-    try:
-        rep = parity.check(sub, o, L, parity.TAU_FP32, o["curve"])
-        return f"{rep['pairs']} pairs ok, exact rotation {rep['exact_rot']}"
-    except AssertionError as e:
-        return "FAILED: " + str(e)[:300]
+    cases = (("fourier", g, lambda: O.align(oq, oa, iq0, ia0, L, want_curve=True)),
+             ("monte_carlo", gm, lambda: O.mc_align_images(w["ref"][None], w["imgs"][:S], n, Q,
+                                                           theta, want_curve=True)))
+    for name, gg, orc in cases:
+        o = orc()
+        sub = {k: v[:S] for k, v in gg.items()}
+        try:
+            rep = parity.check(sub, o, L, parity.TAU_FP32, o["curve"])
+            out[name] = f"{rep['pairs']} pairs ok, exact rotation {rep['exact_rot']}"
+        except AssertionError as e:
+            out[name] = "FAILED: " + str(e)[:300]
+    return out
 
 
 def bench_all_pairs(api, ctx, torch, N=2000, L=64):

@@ -218,14 +218,6 @@ def fourier_tables(img: np.ndarray, n: int, Q: int, levels: int = LEVELS_MIDPOIN
     return quantiles(np.maximum(P, 0.0), Q, levels, bad)
 
 
-def mc_angles(n: int, seed: int):
-    """n directions drawn uniformly on the circle (PCG64, `seed`), sorted:
-    the Monte-Carlo SW directions of the extended alignment results.  This
-    draws random numbers only; the method takes the angles as an input."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    return np.sort(rng.uniform(0.0, 2.0 * np.pi, n))
-
-
 def mc_align_images(ref_img, imgs, n: int, Q: int, angles, levels: int = LEVELS_MIDPOINT,
                     want_curve: bool = False):
     """Monte-Carlo SW2 over rotations (extended alignment results): the

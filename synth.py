@@ -130,6 +130,13 @@ def uniform_images(seed, L, N):
     return out
 
 
+def mc_angles(n, seed):
+    """n directions drawn uniformly on the circle (PCG64, `seed`), sorted: the
+    random draw of Monte-Carlo sliced Wasserstein (an input to the method)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.uniform(0.0, 2.0 * math.pi, n))
+
+
 def gaussian_image(L, centre, sigma):
     """A single isotropic Gaussian (unit coordinates), masked, unit mass."""
     return finish(render([centre], [sigma], [1.0], L), L)

@@ -137,7 +137,7 @@ def test_fourier_tables_and_alignment(api, ctx, oracle, L, n, Q):
 def test_fourier_at_random_angles_parity(api, ctx, oracle, L, n):
     """Slices at sorted random directions (each computed on its own, no
     half-turn mirror) against the oracle's exact DFT at the same angles."""
-    theta = oracle.mc_angles(n, 40 + L)
+    theta = synth.mc_angles(n, 40 + L)
     _, imgs = blob_stack(L, 2, 700 + L)
     pmf = api.project_fourier(ctx, dev(imgs), n, theta=theta).cpu().numpy()
     P0, _ = oracle.fourier_project(imgs, n, angles=theta)
@@ -168,7 +168,7 @@ def test_monte_carlo_sw_alignment_parity(api, ctx, oracle, L, n, Q):
     """Monte-Carlo SW2 over rotations: tables at sorted random directions,
     rotation-only scan on the GPU, against the oracle (rotation tie-aware,
     distance)."""
-    theta = oracle.mc_angles(n, 77)
+    theta = synth.mc_angles(n, 77)
     N = 6 if L == 128 else 12
     ref, imgs = blob_stack(L, N, 800 + L)
     rq, ra = api.tables_fourier(ctx, dev(ref[None]), n, Q, theta=theta)

@@ -693,7 +693,7 @@ def test_fourier_at_given_angles(oracle):
     pt = np.zeros((L, L), np.float32)
     i0, j0 = 9, 21
     pt[i0, j0] = 1.0
-    th = oracle.mc_angles(n, 3)
+    th = synth.mc_angles(n, 3)
     P, _ = oracle.fourier_project(pt, n, cell=False, angles=th)
     c0 = 0.5 * (L - 1)
     sb = -1.0 + (np.arange(L) + 0.5) * h
@@ -732,7 +732,7 @@ def test_mc_random_directions_find_planted_rotations(oracle):
     L, n, Q = 32, 64, 32
     ref = blob_img(L, seed=31)
     imgs = np.stack([np.rot90(ref, k).copy() for k in (1, 2, 3)])
-    r = oracle.mc_align_images(ref[None], imgs, n, Q, oracle.mc_angles(n, 7))
+    r = oracle.mc_align_images(ref[None], imgs, n, Q, synth.mc_angles(n, 7))
     g = oracle.mc_align_images(ref[None], imgs, n, Q, 2 * np.pi * np.arange(n) / n)
     err = np.abs(((r["rot_index"] - g["rot_index"]) + n // 2) % n - n // 2)
     assert err.max() <= 3, (r["rot_index"], g["rot_index"])
