@@ -94,6 +94,37 @@ struct Step {
     std::vector<uint64_t> tickets;
 };
 
+// Pinned host buffers for results, reused across requests in power-of-two
+// size classes: pinned allocation and release stay off the request path
+// (releasing pinned memory can wait for the device to drain).  Guarded by
+// the server mutex; everything is released when serving stops.
+class PinPool {
+  public:
+    void *get(size_t bytes, size_t *cap) {
+        size_t c = 4096;
+        while (c < bytes) c <<= 1;
+        *cap = c;
+        auto it = free_.find(c);
+        if (it != free_.end()) {
+            void *p = it->second;
+            free_.erase(it);
+            return p;
+        }
+        void *p = nullptr;
+        return hipHostMalloc(&p, c) == hipSuccess ? p : nullptr;
+    }
+    void put(void *p, size_t cap) {
+        if (p) free_.emplace(cap, p);
+    }
+    void clear() {
+        for (auto &kv : free_) (void)hipHostFree(kv.second);
+        free_.clear();
+    }
+
+  private:
+    std::multimap<size_t, void *> free_;
+};
+
 struct Req {
     uint64_t ticket = 0;
     sw_request r{};
@@ -106,6 +137,7 @@ struct Req {
     uint64_t ref_key = 0;       // cache entry used (0 = own tables)
     bool ref_compute = false;   // this request's step computes the reference tables
     sw_result *host_out = nullptr;
+    size_t host_cap = 0;  // size class of host_out in the pin pool
     hipEvent_t copied = nullptr;
     std::string err;
 };
@@ -136,6 +168,7 @@ struct Server {
     int grid = 512;
     std::map<std::vector<int>, hipGraphExec_t> graphs;
     DescRing ring;  // pinned descriptor staging of this server
+    PinPool pins;   // pinned result buffers
 };
 
 namespace {
@@ -255,6 +288,8 @@ void admit(Server *s, std::vector<Req *> &fresh) {
             ++e.users;
             e.last_use = ++s->clock;
         }
+        q->host_out = (sw_result *)s->pins.get(sizeof(sw_result) * (size_t)q->r.N, &q->host_cap);
+        if (!q->host_out) q->err = "hipHostMalloc for the results failed";
         q->state = RState::Admitted;
         s->pending.pop_front();
         s->admitted.push_back(q->ticket);
@@ -445,7 +480,7 @@ void scheduler(Server *s) {
                 } else if (r->cancel) {
                     r->state = RState::Cancelled;
                     ++s->st.cancelled;
-                    if (r->host_out) (void)hipHostFree(r->host_out);
+                    s->pins.put(r->host_out, r->host_cap);
                     r->host_out = nullptr;
                     s->reqs.erase(it);
                 } else {
@@ -465,11 +500,11 @@ void scheduler(Server *s) {
         if (!fresh.empty()) {
             lk.unlock();
             for (Req *q : fresh) {
-                hipError_t e = hipHostMalloc((void **)&q->host_out, sizeof(sw_result) * (size_t)q->r.N);
+                if (!q->host_out) continue;  // finished as a failure at launch
                 const size_t L2 = (size_t)q->geo.L * q->geo.L;
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(s->base + q->o_img, q->r.imgs, 4 * (size_t)q->r.N * L2,
-                                       hipMemcpyHostToDevice, s->copy_s);
+                hipError_t e = hipMemcpyAsync(s->base + q->o_img, q->r.imgs,
+                                              4 * (size_t)q->r.N * L2, hipMemcpyHostToDevice,
+                                              s->copy_s);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(s->base + q->o_ref, q->r.ref_img, 4 * L2,
                                        hipMemcpyHostToDevice, s->copy_s);
@@ -555,8 +590,10 @@ void stop_server(Ctx *c) {
     if (s->copy_s) (void)hipStreamSynchronize(s->copy_s);
     for (auto &kv : s->reqs) {
         release_request(s, kv.second.get());
-        if (kv.second->host_out) (void)hipHostFree(kv.second->host_out);
+        s->pins.put(kv.second->host_out, kv.second->host_cap);
+        kv.second->host_out = nullptr;
     }
+    s->pins.clear();
     for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
     for (int i = 0; i < DescRing::kSlots; ++i)
         if (s->ring.ev[i]) (void)hipEventDestroy(s->ring.ev[i]);
@@ -665,13 +702,13 @@ sw_status sw_serve_poll(void *ctx, uint64_t ticket, sw_result *out) {
     Req *q = it->second.get();
     if (q->state == RState::Failed) {
         std::string msg = q->err;
-        if (q->host_out) (void)hipHostFree(q->host_out);
+        s->pins.put(q->host_out, q->host_cap);
         s->reqs.erase(it);
         return fail(SW_E_DEVICE, "request failed: %s", msg.c_str());
     }
     if (q->state != RState::Done) return SW_NOT_READY;
     if (out) std::memcpy(out, q->host_out, sizeof(sw_result) * (size_t)q->r.N);
-    (void)hipHostFree(q->host_out);
+    s->pins.put(q->host_out, q->host_cap);
     s->reqs.erase(it);
     return SW_OK;
 }
@@ -691,7 +728,7 @@ sw_status sw_serve_cancel(void *ctx, uint64_t ticket) {
         return SW_OK;
     }
     if (q->state == RState::Done || q->state == RState::Failed) {
-        if (q->host_out) (void)hipHostFree(q->host_out);
+        s->pins.put(q->host_out, q->host_cap);
         s->reqs.erase(it);
         ++s->st.cancelled;
         return SW_OK;
@@ -705,7 +742,7 @@ sw_status sw_serve_cancel(void *ctx, uint64_t ticket) {
     });
     auto f = s->reqs.find(ticket);
     if (f != s->reqs.end()) {
-        if (f->second->host_out) (void)hipHostFree(f->second->host_out);
+        s->pins.put(f->second->host_out, f->second->host_cap);
         s->reqs.erase(f);
     }
     return SW_OK;
