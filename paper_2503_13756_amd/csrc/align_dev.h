@@ -22,7 +22,10 @@
 
 namespace sw {
 
-constexpr int kFftElems = 4096;  // complex elements of one LDS FFT chunk (32 KiB, two buffers)
+// Complex elements of one LDS FFT chunk (8 KiB, two buffers).  The per-pair
+// alignment is latency bound: small chunks keep its LDS near 22 KiB at
+// n = 256, so that seven blocks fit on a compute unit instead of two.
+constexpr int kFftElems = 1024;
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

@@ -262,8 +262,9 @@ hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const Mi
     // four 40 KiB blocks of the register-FFT kernel per compute unit
     hipLaunchKernelGGL((k_align128_mixed<NT>), dim3((unsigned)(2 * grid)), dim3(NT), 0, s, d_imgs,
                        counters + 3);
-    hipLaunchKernelGGL((k_align_mixed<NT>), dim3((unsigned)grid), dim3(NT), m.align_lds, s, d_imgs,
-                       counters + 2);
+    // small LDS tiles: four blocks of the LDS-FFT kernel per compute unit
+    hipLaunchKernelGGL((k_align_mixed<NT>), dim3((unsigned)(4 * grid)), dim3(NT), m.align_lds, s,
+                       d_imgs, counters + 2);
     return hipGetLastError();
 }
 
