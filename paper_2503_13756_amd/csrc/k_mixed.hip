@@ -35,23 +35,30 @@ __device__ __forceinline__ int64_t next_work(unsigned long long *counter, int64_
     return *slot;
 }
 
-// Images -> quantile tables for every item of the group.  `scratch` holds one
-// PMF slot of slot_floats per block, used by images whose PMF table does not
-// fit in LDS.
+// Images -> quantile tables for every item of two groups: the work queue
+// holds the images of G0 (the references) first, then those of G1, so that
+// the references, one block each, run beside the first images instead of
+// alone on an otherwise idle device.  `scratch` holds one PMF slot of
+// slot_floats per block, used by images whose PMF table does not fit in LDS.
 template <int NT, int TPW>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWaves<NT, TPW>, NT <= 256 ? 2 : 4))) void k_tables_mixed(
-    const MixGroup *__restrict__ G, unsigned long long *counter, float *scratch,
-    int64_t slot_floats, int region_floats, int /*lmax*/, int nmax) {
+    const MixGroup *__restrict__ G0, const MixGroup *__restrict__ G1, unsigned long long *counter,
+    float *scratch, int64_t slot_floats, int region_floats, int /*lmax*/, int nmax) {
     constexpr int NW = NT / 64;
     extern __shared__ __align__(16) double ldsd[];  // 16-byte aligned: ds_read_b128 on strips
     __shared__ int64_t wslot;
     float *region = (float *)ldsd;
     double *colS = ldsd + region_floats / 2;
     float *Ut = (float *)(colS + 2 * nmax);
-    const int64_t total = G->total;
+    const int64_t total0 = G0->total, total = total0 + G1->total;
     for (;;) {
-        const int64_t w = next_work<NT>(counter, &wslot);
+        int64_t w = next_work<NT>(counter, &wslot);
         if (w >= total) break;
+        const MixGroup *G = G0;
+        if (w >= total0) {
+            G = G1;
+            w -= total0;
+        }
         const MixItem &it = G->items[find_item(G, w)];
         const int64_t gi = w - it.first;
         ProjShape P;
@@ -77,17 +84,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
         __syncthreads();
         quantile_phase<NT>([&](int k, int b) { return pmf[k * L + b]; }, L, n, Q, it.levels, it.TC,
                            it.d64, Ut, colS, it.qt + gi * (int64_t)Q * n, it.aux + 4 * gi);
+        if (G == G0 && it.spec) {
+            // the reference's spectrum, from the table this block just wrote
+            __threadfence_block();
+            spectrum_block<NT>(it.qt + gi * (int64_t)Q * n, n, Q, it.ref_spec, 0, it.d32,
+                               (float2 *)ldsd);
+        }
     }
 }
 
-// FP32 spectrum of the reference of every item: one block per item.
+// FP32 spectrum of the reference of every item whose reference tables were
+// not computed in this launch (cached references): one block per item.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_refspec_mixed(const MixGroup *__restrict__ G) {
     extern __shared__ __align__(16) float2 lds2[];
     const int i = blockIdx.x;
     if (i >= G->nitems) return;
     const MixItem &it = G->items[i];
-    if (it.count <= 0) return;
+    if (it.count <= 0 || it.spec) return;  // spec: written by the tables kernel
     spectrum_block<NT>(it.ref_qt, it.n, it.Q, it.ref_spec, 0, it.d32, lds2);
 }
 
@@ -251,13 +265,10 @@ hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const Mi
     prepare_mixed();
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, 4);
     hipLaunchKernelGGL((k_tables_mixed<NTT, TPW>), dim3((unsigned)grid), dim3(NTT), m.tables_lds, s,
-                       d_refs, counters + 0, scratch, m.slot_floats, m.region_floats, m.lmax,
-                       m.nmax);
+                       d_refs, d_imgs, counters + 0, scratch, m.slot_floats, m.region_floats,
+                       m.lmax, m.nmax);
     hipLaunchKernelGGL((k_refspec_mixed<NT>), dim3((unsigned)kMaxMix), dim3(NT),
                        sizeof(float2) * (kMaxN + 2 * kFftElems), s, d_imgs);
-    hipLaunchKernelGGL((k_tables_mixed<NTT, TPW>), dim3((unsigned)grid), dim3(NTT), m.tables_lds, s,
-                       d_imgs, counters + 1, scratch, m.slot_floats, m.region_floats, m.lmax,
-                       m.nmax);
     hipLaunchKernelGGL(k_gamma_mixed, dim3((unsigned)kMaxMix), dim3(256), 0, s, d_imgs);
     // four 40 KiB blocks of the register-FFT kernel per compute unit
     hipLaunchKernelGGL((k_align128_mixed<NT>), dim3((unsigned)(2 * grid)), dim3(NT), 0, s, d_imgs,

@@ -562,6 +562,7 @@ sw_status run_stack_chunk(Ctx *c, const sw_stack *const *st, int n, int mode, in
         a.count = k.N;
         a.gam = nullptr;
         r.gam = nullptr;
+        a.spec = r.spec = 1;  // the reference item writes the spectrum
         first += k.N;
         if (i < nfast) split = first;
         gr.items[i] = r;

@@ -204,6 +204,9 @@ struct MixItem {
     int mode, bf16, top_k;
     float2 *gam;  // n = 128 register-FFT alignment: coefficients [Q/2][130] of the
                   // reference (written by the launch), or null for the LDS-FFT path
+    int spec;     // reference item: write the FP32 spectrum of its table to ref_spec
+                  // after the tables; image item: its ref_spec is written that way
+    int pad;
 };
 struct MixGroup {
     int64_t total;
@@ -220,9 +223,10 @@ struct MixLaunch {
 };
 // Fills the per-item tile fields (R clamped, TC, fused) and the launch sizes.
 MixLaunch plan_mixed(MixItem *items, int nitems);
-// Reference tables (group d_refs), reference spectra, image tables and
-// alignment (group d_imgs).  counters: 3 device words; scratch: grid *
-// slot_floats floats.  Capturable: no host-side dependence on the contents.
+// Reference tables and spectra (group d_refs) and image tables (group d_imgs)
+// from one work queue, spectra of cached references, alignment (group
+// d_imgs).  counters: 4 device words; scratch: grid * slot_floats floats.
+// Capturable: no host-side dependence on the contents.
 hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const MixLaunch &m,
                         unsigned long long *counters, float *scratch, int grid, hipStream_t s);
 void prepare_mixed();

@@ -379,6 +379,8 @@ hipError_t issue_step(Server *s, const std::vector<Req *> &rs, hipEvent_t done) 
             r.first = gr.nitems;
             r.count = 1;
             r.gam = nullptr;
+            r.spec = 1;  // writes this request's reference spectrum
+            gi.items[i].spec = 1;
             gr.items[gr.nitems++] = r;
             if (q->ref_key) keys_done.push_back(q->ref_key);
         }

@@ -201,6 +201,12 @@ def test_serving_reference_cache_and_cancel(api):
     assert srv.stats()["cache_hits"] >= 1
     p = list(plain.values())[0]
     assert np.array_equal(got1[t1], p) and np.array_equal(got2[t2], p[:5])
+    # a new key twice in a row (normally one step): the first request computes
+    # the reference tables and its spectrum, the second reads the same tables
+    t3 = srv.submit(r, x, ref_key=78)
+    t4 = srv.submit(r, x[:7], ref_key=78)
+    got34 = wait_all(srv, [t3, t4])
+    assert np.array_equal(got34[t3], p) and np.array_equal(got34[t4], p[:7])
     # cancel: pending or in flight, the ticket is gone afterwards
     ts = [srv.submit(*stack(128, 50, 2710 + i)) for i in range(4)]
     srv.cancel(ts[3])
