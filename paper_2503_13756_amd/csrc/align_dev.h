@@ -375,18 +375,30 @@ __device__ void align_pair_block(const PairJob &job, Geo g, int mode, int bf16, 
         sy[c] = (float)(2.0 * b.y);
         part[c] = 0.f;
     }
-    for (int idx = threadIdx.x; idx < Q * n; idx += NT) {
-        const int j = idx / n, k = idx - j * n;
-        const float u = U[idx];
-        const float2 dk = tw[k];
-        const float *vrow = V + (int64_t)j * n;
+    // rows of V pass through LDS (the FFT buffers, free by now): every element
+    // is read once from memory and K times from LDS
+    float *Vs = (float *)Z0;
+    const int RS = 4 * kFftElems / n;
+    for (int j0 = 0; j0 < Q; j0 += RS) {
+        const int cnt = min(RS, Q - j0) * n;
+        const float *Vg = V + (int64_t)j0 * n;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < cnt; idx += NT) Vs[idx] = Vg[idx];
+        __syncthreads();
+        const float *Ug = U + (int64_t)j0 * n;
+        for (int idx = threadIdx.x; idx < cnt; idx += NT) {
+            const int jl = idx / n, k = idx - jl * n;
+            const float u = Ug[idx];
+            const float2 dk = tw[k];
+            const float *vrow = Vs + jl * n;
 #pragma unroll
-        for (int c = 0; c < kMaxTopK; ++c) {
-            if (c < K) {
-                int kk = k + lc[c];
-                if (kk >= n) kk -= n;
-                const float e = u - vrow[kk] - (sx[c] * dk.x + sy[c] * dk.y);
-                part[c] += e * e;
+            for (int c = 0; c < kMaxTopK; ++c) {
+                if (c < K) {
+                    int kk = k + lc[c];
+                    if (kk >= n) kk -= n;
+                    const float e = u - vrow[kk] - (sx[c] * dk.x + sy[c] * dk.y);
+                    part[c] += e * e;
+                }
             }
         }
     }
