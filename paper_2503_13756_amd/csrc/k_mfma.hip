@@ -8,9 +8,10 @@
 // interleaved along K.  k_corr_mfma runs them on MFMA with bfloat16 spectra
 // and FP32 accumulation, one 16 x 16 pair tile per block (the four waves
 // split the frequencies), keeps S in LDS, and finishes every pair in the same
-// block: the inverse DFT over w (even/odd split), the closed-form translation
-// correction D*(l) = (E_a + E_b - 2 C(l))/(nQ) - 2|b(l)|^2 and the top-k lags.
-// S never reaches HBM.
+// block: the inverse DFT over w (a second product, S times the real DFT
+// matrix, on FP32 MFMA), the closed-form translation correction
+// D*(l) = (E_a + E_b - 2 C(l))/(nQ) - 2|b(l)|^2 and the top-k lags.  S never
+// reaches HBM.
 //
 // k_rescore_tiles then recomputes the objective at the top-k lags in FP32:
 // the translation-free residual R0(l) = sum_{j,k} (U[j][k] - V[j][k+l])^2
@@ -87,13 +88,55 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
     }
     __syncthreads();
 
-    // ---- one pair per thread: inverse DFT over w, correction, top-k
+    // ---- inverse DFT over w on MFMA (FP32): C[p][l] = sum_k S[p][k] T[k][l]
+    // with k = 2w (real part) or 2w + 1 (imaginary part) and
+    //   T[2w][l] = c_w cos(2 pi w l / N) / N,  T[2w + 1][l] = -c_w sin(2 pi w l / N) / N,
+    // c_w = 1 at w = 0 and N/2 (whose imaginary rows are 0), else 2.  Wave v
+    // owns pairs 64 v .. 64 v + 63 (four 16-pair row tiles) and writes C over
+    // its own S rows; only this wave reads or writes them from here on.
+    {
+        constexpr int KS = (2 * Wn + 3) / 4;  // k-steps of four
+        constexpr int CT = N / 16;            // lag tiles
+        const int kq = lane >> 4, jl = lane & 15;
+        f32x4_t acc[4][CT];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        const float *Srow = Sl + (64 * wave + jl) * SS;
+        for (int st = 0; st < KS; ++st) {
+            const int k = 4 * st + kq;  // this lane's k for A (pair jl) and B (lag jl)
+            const bool kin = k < 2 * Wn;
+            float av[4];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) av[rt] = kin ? Srow[16 * rt * SS + k] : 0.f;
+            const int w = k >> 1;
+            const bool edge = w == 0 || w == N / 2;
+            const float cw = edge ? 1.f / (float)N : 2.f / (float)N;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const float2 e = tw[(w * (16 * ct + jl)) & (N - 1)];  // (cos, -sin)
+                const float bv = !kin ? 0.f : (k & 1) ? (edge ? 0.f : e.y * cw) : e.x * cw;
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt], bv, acc[rt][ct], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Sl[(64 * wave + 16 * rt + 4 * kq + v) * SS + 16 * ct + jl] = acc[rt][ct][v];
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // ---- one pair per thread: correction, top-k
     const int t = threadIdx.x;
     const int64_t r = r0 + t / 16, g = g0 + t % 16;
     if (r >= n_ref || g >= n_img) return;  // no barrier follows
-    float S[2 * Wn];
-#pragma unroll
-    for (int i = 0; i < 2 * Wn; ++i) S[i] = Sl[t * SS + i];
+    const float *Crow = Sl + t * SS;
     const double *au = ref_aux + 4 * r, *av = img_aux + 4 * g;
     const float Esum = (float)(au[1] + av[1]);
     const float aux_ = (float)au[2], auy = (float)au[3], avx = (float)av[2], avy = (float)av[3];
@@ -129,23 +172,7 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
             }
         }
     };
-    const float s0 = S[0], sh = S[2 * (N / 2)];
-    const float sgn_half = ((N / 2) & 1) ? -1.f : 1.f;
-    for (int l = 0; l < N / 2; ++l) {
-        float ev = 0.f, od = 0.f;
-#pragma unroll
-        for (int w = 1; w < N / 2; ++w) {
-            const float2 e = tw[(w * l) & (N - 1)];
-            const float term = S[2 * w] * e.x + S[2 * w + 1] * e.y;  // Re(S e^{+i 2 pi w l/n})
-            if (w & 1) od += term;
-            else ev += term;
-        }
-        const float alt = (l & 1) ? -sh : sh;
-        const float c_lo = (s0 + alt + 2.f * (ev + od)) / (float)N;
-        const float c_hi = (s0 + sgn_half * alt + 2.f * (ev - od)) / (float)N;
-        consider(l, c_lo);
-        consider(l + N / 2, c_hi);
-    }
+    for (int l = 0; l < N; ++l) consider(l, Crow[l]);
     int16_t *out = cand + (r * n_img + g) * (int64_t)top_k;
     for (int c = 0; c < top_k; ++c) out[c] = (int16_t)bl[c];
 }
