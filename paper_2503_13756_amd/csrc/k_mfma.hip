@@ -88,6 +88,24 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
     }
     __syncthreads();
 
+    // ---- translation correction folded into the w = 1 term.  With
+    // z = conj(a_ref) a_img, |b(l)|^2 = |a_ref|^2 + |a_img|^2 - 2 Re(z e^{i theta_l}), so
+    //   D*(l) = const - (2/nQ) X(l),  X(l) = C(l) - 2 nQ Re(z e^{i theta_l}),
+    // and Re(z e^{i theta_l}) is the w = 1 basis function: X is C of the
+    // spectrum with S_1 lowered by nQ N z.  The lags of smallest D* are those
+    // of largest X.
+    const int t = threadIdx.x;
+    const int64_t r = r0 + t / 16, g = g0 + t % 16;
+    const bool pair_ok = r < n_ref && g < n_img;
+    if (mode == 0 && pair_ok) {
+        const double *au = ref_aux + 4 * r, *av = img_aux + 4 * g;
+        const double s = (double)N * (double)N * (double)Q;
+        const double zx = au[2] * av[2] + au[3] * av[3], zy = au[2] * av[3] - au[3] * av[2];
+        Sl[t * SS + 2] -= (float)(s * zx);
+        Sl[t * SS + 3] -= (float)(s * zy);
+    }
+    __builtin_amdgcn_wave_barrier();  // rows of this wave only: no block barrier
+
     // ---- inverse DFT over w on MFMA (FP32): C[p][l] = sum_k S[p][k] T[k][l]
     // with k = 2w (real part) or 2w + 1 (imaginary part) and
     //   T[2w][l] = c_w cos(2 pi w l / N) / N,  T[2w + 1][l] = -c_w sin(2 pi w l / N) / N,
@@ -132,49 +150,29 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
         __builtin_amdgcn_wave_barrier();
     }
 
-    // ---- one pair per thread: correction, top-k
-    const int t = threadIdx.x;
-    const int64_t r = r0 + t / 16, g = g0 + t % 16;
-    if (r >= n_ref || g >= n_img) return;  // no barrier follows
+    // ---- one pair per thread: the top-k lags of largest X.  Keys: X mapped
+    // to an unsigned code that grows as X falls, its low bits replaced by the
+    // lag, kept sorted by a min/max insertion (ties, and values within 2^-17
+    // relative, go to the smaller lag; the exact FP32 rescore decides among
+    // the candidates).
+    if (!pair_ok) return;  // no barrier follows
     const float *Crow = Sl + t * SS;
-    const double *au = ref_aux + 4 * r, *av = img_aux + 4 * g;
-    const float Esum = (float)(au[1] + av[1]);
-    const float aux_ = (float)au[2], auy = (float)au[3], avx = (float)av[2], avy = (float)av[3];
-    const float inv_nq = 1.f / ((float)N * (float)Q);
-    float bd[KMAX];
-    int bl[KMAX];
+    uint32_t top[KMAX];
 #pragma unroll
-    for (int c = 0; c < KMAX; ++c) {
-        bd[c] = __builtin_inff();
-        bl[c] = 0x7fff;
-    }
-    auto consider = [&](int l, float Cl) {
-        float d = (Esum - 2.f * Cl) * inv_nq;
-        if (mode == 0) {
-            const float2 e = tw[l];  // (cos, -sin)
-            const float bx = aux_ - (e.x * avx + e.y * avy);
-            const float by = auy - (-e.y * avx + e.x * avy);
-            d -= 2.f * (bx * bx + by * by);
-        }
-        int li = l;
+    for (int c = 0; c < KMAX; ++c) top[c] = 0xffffffffu;
+    for (int l = 0; l < N; ++l) {
+        const uint32_t u = __float_as_uint(-Crow[l]);
+        uint32_t key = (u >> 31) ? ~u : (u | 0x80000000u);
+        key = (key & ~(uint32_t)(N - 1)) | (uint32_t)l;
 #pragma unroll
         for (int c = 0; c < KMAX; ++c) {
-            if (c < top_k) {
-                const bool better = d < bd[c] || (d == bd[c] && li < bl[c]);
-                if (better) {
-                    const float td = bd[c];
-                    const int tl = bl[c];
-                    bd[c] = d;
-                    bl[c] = li;
-                    d = td;
-                    li = tl;
-                }
-            }
+            const uint32_t lo = min(key, top[c]);
+            key = max(key, top[c]);
+            top[c] = lo;
         }
-    };
-    for (int l = 0; l < N; ++l) consider(l, Crow[l]);
+    }
     int16_t *out = cand + (r * n_img + g) * (int64_t)top_k;
-    for (int c = 0; c < top_k; ++c) out[c] = (int16_t)bl[c];
+    for (int c = 0; c < top_k; ++c) out[c] = (int16_t)(top[c] & (uint32_t)(N - 1));
 }
 
 // Sum over the 64 lanes: butterflies inside each row of 16 lanes on DPP,
