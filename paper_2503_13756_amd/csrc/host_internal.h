@@ -8,6 +8,8 @@
 #include <string>
 
 #include "swalign.h"
+#include "fourier_internal.h"
+#include "mix_internal.h"
 #include "sw_internal.h"
 
 namespace swh {

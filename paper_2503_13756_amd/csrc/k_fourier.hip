@@ -24,7 +24,7 @@
 //     h/2, clipped at zero and written with their theta + pi mirror.
 // The FFTs are Stockham transforms (radix 4, one radix-2 step for odd
 // powers of two) in LDS over a batch of sequences.
-#include "sw_internal.h"
+#include "fourier_internal.h"
 
 namespace sw {
 

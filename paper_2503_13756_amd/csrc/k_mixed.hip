@@ -7,6 +7,7 @@
 // as the single-geometry kernels (projection, CDF/quantiles, FFT alignment).
 #include "align128_dev.h"
 #include "align_dev.h"
+#include "mix_internal.h"
 #include "proj_dev.h"
 #include "quant_dev.h"
 

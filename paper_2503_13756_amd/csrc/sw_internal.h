@@ -91,37 +91,6 @@ bool tables_rf_fused_fits(Geo g);
 hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable &t,
                             const ProjPlan &pp, const float *hx, float *qt, double *aux,
                             hipStream_t s);
-// Fourier-slice projector (k_fourier.hip): L a power of two, oversampled
-// grid Nf = 2L, H = Nf/2 + 1 stored spectrum columns.  Tables (device,
-// context-owned): corr[j] = 1 / phihat((j - L/2) / Nf) for the interpolation
-// kernel phi, twf[k] = exp(-2 pi i k / Nf) (k < Nf), twl[k] =
-// exp(-2 pi i k / L) (k < L), shift[t] = (-1)^k exp(i pi k / L) with
-// k = t for t < L/2 and t - L otherwise.  The scratch holds `slots` regions
-// of fourier_slot_bytes; the grid is min(N, slots) persistent blocks.
-// targets: per slice point (theta_m, k pi), m < n/2 (n with explicit
-// angles), k <= L/2, in that order, five float4 (layout at slice_point in
-// k_fourier.hip).
-constexpr int kFourierW = 7;    // interpolation kernel width in fine-grid points
-constexpr int kFourierPad = 4;  // mirrored spectrum columns kept on each side
-struct FourierShape {
-    int L, n, Nf, lgNf, lgL, H;
-    int mirror;  // 1: slices theta_m = 2 pi m / n, m < n/2, plus their theta + pi
-                 // mirrors; 0: n slices at explicit angles (the targets table)
-};
-struct FourierTabs {
-    const float *corr;
-    const float2 *twf, *twl, *shift;
-    const float4 *targets;
-};
-// per slot: R [L][Nf/2 + 1] and B [Nf][Nf/2 + 2 kFourierPad] complex
-__host__ __device__ inline size_t fourier_slot_elems(int L, int Nf) {
-    return (size_t)L * (Nf / 2 + 1) + (size_t)Nf * (Nf / 2 + 2 * kFourierPad);
-}
-size_t fourier_lds_bytes(int L, int Nf);
-size_t fourier_slot_bytes(int L, int Nf);
-int fourier_blocks_per_cu(int L, int Nf);  // resident blocks of the projector per CU
-hipError_t launch_fourier(const float *img, int64_t N, const FourierShape &S, const FourierTabs &T,
-                          void *scratch, int slots, float *pmf, hipStream_t s);
 // sw2sq of the valid results, and the curve, times f.
 hipError_t launch_scale_results(Result *out, int64_t P, float *curve, int n, float f,
                                 hipStream_t s);
@@ -177,59 +146,6 @@ struct MfmaArgs {
 };
 bool mfma_path_supported(Geo g);
 hipError_t launch_mfma_all_pairs(const MfmaArgs &a, Geo g, const AngleTable &t, hipStream_t s);
-
-// ---- mixed-geometry persistent launches (uneven stacks, serving) ----
-constexpr int kMaxMix = 64;
-// block size and tasks per wave of the persistent tables kernel
-constexpr int kMixTablesThreads = 512, kMixTablesTasks = 6;  // stacks (or requests) per launch
-
-// One stack of images of one geometry aligned against one reference.
-struct MixItem {
-    const float *img;   // [count][L][L]
-    float *qt;          // [count][Q][n]
-    double *aux;        // [count][4]
-    const float *ref_qt;
-    const double *ref_aux;
-    float2 *ref_spec;   // [n/2+1][Q] FP32, written by the launch
-    Result *out;        // [count]
-    const float2 *d32;  // angle table of n
-    const double2 *d64;
-    const int *perm;    // projection work order of (L, n)
-    const int2 *trow;
-    int64_t first, count;  // work-index range
-    int L, n, Q, levels;
-    int R;      // projection strip rows (tile)
-    int TC;     // quantile column tile
-    int fused;  // PMF kept in LDS
-    int mode, bf16, top_k;
-    float2 *gam;  // n = 128 register-FFT alignment: coefficients [Q/2][130] of the
-                  // reference (written by the launch), or null for the LDS-FFT path
-    int spec;     // reference item: write the FP32 spectrum of its table to ref_spec
-                  // after the tables; image item: its ref_spec is written that way
-    int pad;
-};
-struct MixGroup {
-    int64_t total;
-    int64_t split;  // work items [0, split) belong to items with gam (listed first)
-    int nitems;
-    int pad;
-    MixItem items[kMaxMix];
-};
-struct MixLaunch {
-    int region_floats, lmax, nmax;
-    size_t tables_lds;
-    int64_t slot_floats;
-    size_t align_lds;
-};
-// Fills the per-item tile fields (R clamped, TC, fused) and the launch sizes.
-MixLaunch plan_mixed(MixItem *items, int nitems);
-// Reference tables and spectra (group d_refs) and image tables (group d_imgs)
-// from one work queue, spectra of cached references, alignment (group
-// d_imgs).  counters: 4 device words; scratch: grid * slot_floats floats.
-// Capturable: no host-side dependence on the contents.
-hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const MixLaunch &m,
-                        unsigned long long *counters, float *scratch, int grid, hipStream_t s);
-void prepare_mixed();
 
 hipError_t launch_fill_synthetic(float *x, int64_t n, hipStream_t s);
 
