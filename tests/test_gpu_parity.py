@@ -254,6 +254,23 @@ def test_all_pairs_mfma_parity(api, ctx, oracle, L, n, nr, ni):
     assert np.all(g["rot_index"][diag] == 0) and np.all(g["sw2sq"][diag] == 0.0)
 
 
+@pytest.mark.parametrize("L,n,mode,top_k", [(64, 64, 1, 4), (32, 32, 1, 2), (64, 64, 0, 1),
+                                            (32, 32, 0, 3)])
+def test_all_pairs_mfma_modes_and_topk(api, ctx, oracle, L, n, mode, top_k):
+    """All pairs on the matrix cores in rotation-only mode (no correction
+    folded into the spectra) and with fewer than four candidates, against
+    the oracle with the same mode, BF16 tolerance."""
+    nr, ni = 19, 33
+    _, imgs = blob_stack(L, ni, 1300 + 10 * mode + top_k)
+    rq, ra = api.tables(ctx, dev(imgs[:nr]), n, n)
+    iq, ia = api.tables(ctx, dev(imgs), n, n)
+    res, _ = api.align_batch(ctx, rq, ra, iq, ia, L, mode=mode, prec=1, top_k=top_k)
+    g = api.unpack_results(res)
+    oq, oa = oracle.tables(imgs, n, n)
+    o = oracle_results(oracle, oq[:nr], oa[:nr], oq, oa, L, mode=mode)
+    parity.check(g, o, L, parity.TAU_BF16, o["curve"])
+
+
 def test_all_pairs_mfma_same_set_sampled(api, ctx, oracle):
     """One set against itself (spectra computed once), 300 x 300 at L = 64,
     checked on a seeded sample of 400 pairs."""
