@@ -905,8 +905,10 @@ static sw_status fourier_setup(Ctx *c, const sw::Geo &geo, int64_t N, const doub
         if (st == SW_OK) st = get_table(c, geo.n, dirs);
     }
     if (st != SW_OK) return st;
-    // one slot per block that can be resident at once
-    const int64_t cap = (int64_t)sw::fourier_blocks_per_cu(S->L, S->Nf) * c->cu_count;
+    // one slot per block that can be resident at once, at most two per CU (a
+    // third block at L = 128 fits but costs 4 % through its scratch traffic)
+    const int64_t cap =
+        (int64_t)std::min(sw::fourier_blocks_per_cu(S->L, S->Nf), 2) * c->cu_count;
     *slots = (int)(N < cap ? N : cap);
     return SW_OK;
 }
