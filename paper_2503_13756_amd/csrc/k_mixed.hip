@@ -195,6 +195,7 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
     constexpr int NT = 256;                         // align kernels
     constexpr int NTT = kMixTablesThreads, TPW = kMixTablesTasks;  // tables kernel
     MixLaunch m{};
+    m.tpw = kMixTablesTasksSmall;
     int lmax = 8, nmax = 8, region = 0;
     int64_t slot = 0;
     size_t align_lds = 0;
@@ -208,6 +209,7 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
         it.R = R;
         const int ntasks = proj_ntasks(it.L, it.n);
         const bool one_group = ntasks <= (NTT / 64) * TPW;
+        if (ntasks > (NTT / 64) * kMixTablesTasksSmall) m.tpw = TPW;
         const int strip = kStripFloats;
         const int pmf = it.n * it.L;
         // fused when a single task group and the PMF fits beside nothing else
@@ -248,6 +250,10 @@ void prepare_mixed() {
     static const hipError_t a1 = hipFuncSetAttribute(
         (const void *)k_tables_mixed<NTT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize,
         150 * 1024);
+    static const hipError_t a0 = hipFuncSetAttribute(
+        (const void *)k_tables_mixed<NTT, kMixTablesTasksSmall>,
+        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)a0;
     static const hipError_t a2 = hipFuncSetAttribute(
         (const void *)k_refspec_mixed<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     static const hipError_t a3 = hipFuncSetAttribute(
@@ -265,9 +271,14 @@ hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const Mi
     constexpr int NT = 256, NTT = kMixTablesThreads, TPW = kMixTablesTasks;
     prepare_mixed();
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, 4);
-    hipLaunchKernelGGL((k_tables_mixed<NTT, TPW>), dim3((unsigned)grid), dim3(NTT), m.tables_lds, s,
-                       d_refs, d_imgs, counters + 0, scratch, m.slot_floats, m.region_floats,
-                       m.lmax, m.nmax);
+    if (m.tpw == kMixTablesTasksSmall)
+        hipLaunchKernelGGL((k_tables_mixed<NTT, kMixTablesTasksSmall>), dim3((unsigned)grid),
+                           dim3(NTT), m.tables_lds, s, d_refs, d_imgs, counters + 0, scratch,
+                           m.slot_floats, m.region_floats, m.lmax, m.nmax);
+    else
+        hipLaunchKernelGGL((k_tables_mixed<NTT, TPW>), dim3((unsigned)grid), dim3(NTT),
+                           m.tables_lds, s, d_refs, d_imgs, counters + 0, scratch,
+                           m.slot_floats, m.region_floats, m.lmax, m.nmax);
     hipLaunchKernelGGL((k_refspec_mixed<NT>), dim3((unsigned)kMaxMix), dim3(NT),
                        sizeof(float2) * (kMaxN + 2 * kFftElems), s, d_imgs);
     hipLaunchKernelGGL(k_gamma_mixed, dim3((unsigned)kMaxMix), dim3(256), 0, s, d_imgs);

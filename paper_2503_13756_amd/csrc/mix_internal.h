@@ -6,8 +6,10 @@
 namespace sw {
 
 constexpr int kMaxMix = 64;
-// block size and tasks per wave of the persistent tables kernel
-constexpr int kMixTablesThreads = 512, kMixTablesTasks = 6;  // stacks (or requests) per launch
+// block size and tasks per wave of the persistent tables kernel; launches
+// whose every item projects in one task group of five tasks per wave take
+// that smaller instance (fewer registers, no spills)
+constexpr int kMixTablesThreads = 512, kMixTablesTasks = 6, kMixTablesTasksSmall = 5;
 
 // One stack of images of one geometry aligned against one reference.
 struct MixItem {
@@ -43,6 +45,7 @@ struct MixGroup {
 };
 struct MixLaunch {
     int region_floats, lmax, nmax;
+    int tpw;  // tasks per wave of the tables kernel instance
     size_t tables_lds;
     int64_t slot_floats;
     size_t align_lds;

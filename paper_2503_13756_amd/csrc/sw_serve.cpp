@@ -418,7 +418,7 @@ hipError_t issue_step(Server *s, const std::vector<Req *> &rs, hipEvent_t done) 
     if (s->cfg.use_graphs) {
         const std::vector<int> key{g.L, g.n, g.Q, g.levels, gi.items[0].R, gi.items[0].TC,
                                    gi.items[0].fused, (int)mm.tables_lds, (int)mm.align_lds,
-                                   mm.region_floats, mm.lmax, mm.nmax};
+                                   mm.region_floats, mm.lmax, mm.nmax, mm.tpw};
         auto it = s->graphs.find(key);
         if (it == s->graphs.end()) {
             sw::prepare_mixed();
