@@ -37,6 +37,13 @@ __device__ __forceinline__ bf16x4_t as_bf16x4(uint32_t lo, uint32_t hi) {
     return v;
 }
 
+// LDS writes of this wave visible to its other lanes (no block barrier).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // (re, im) -> (im, -re) on a packed bf16 complex
 __device__ __forceinline__ uint32_t times_minus_i(uint32_t z) {
     return (z >> 16) | (((z & 0xffffu) ^ 0x8000u) << 16);
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
         Sl[t * SS + 2] -= (float)(s * zx);
         Sl[t * SS + 3] -= (float)(s * zy);
     }
-    __builtin_amdgcn_wave_barrier();  // rows of this wave only: no block barrier
+    wave_lds_fence();  // rows of this wave only: no block barrier
 
     // ---- inverse DFT over w on MFMA (FP32): C[p][l] = sum_k S[p][k] T[k][l]
     // with k = 2w (real part) or 2w + 1 (imaginary part) and
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     Sl[(64 * wave + 16 * rt + 4 * kq + v) * SS + 16 * ct + jl] = acc[rt][ct][v];
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_fence();
     }
 
     // ---- one pair per thread: the top-k lags of largest X.  Keys: X mapped
