@@ -54,7 +54,7 @@ def _load():
                                      P, P, P, P, P]
         lib.oracle_align.restype = None
         lib.oracle_align_rows.argtypes = [P, P, i64, P, P, i64, P, i64, i32, i32, i32, i32, i32,
-                                          P, P, P, P, P]
+                                          P, P, P, P, P, P]
         lib.oracle_align_rows.restype = None
         lib.oracle_ramp.argtypes = [P, i64, i32, i32, P]
         lib.oracle_ramp.restype = None
@@ -245,7 +245,8 @@ def align(ref_qt, ref_aux, img_qt, img_aux, L: int, pairs=None, mode: int = MODE
     """Exhaustive rotation scan with the closed-form translation.
 
     Returns a dict with rot_index [P], shift_px [P, 2], sw2sq [P], status [P],
-    and curve [P, n] when requested.  Pairs default to all ref x img in
+    and, when requested, curve [P, n] = D*(l) and shift_curve [P, n, 2] =
+    the closed-form shift s*(l) in pixels at every lag.  Pairs default to all ref x img in
     row-major order.  ramp=True: the tables are the stacked [2Q, n] tables of
     the ramp-filtered distance, whose objective sums the two parts."""
     ref_qt = np.ascontiguousarray(ref_qt, dtype=np.float64)
@@ -269,13 +270,15 @@ def align(ref_qt, ref_aux, img_qt, img_aux, L: int, pairs=None, mode: int = MODE
     out_d = np.zeros(P, np.float64)
     st = np.zeros(P, np.int32)
     curve = np.zeros((P, n), np.float64) if want_curve else None
+    scurve = np.zeros((P, n, 2), np.float64) if want_curve else None
     _load().oracle_align_rows(_ptr(ref_qt), _ptr(ref_aux), nr, _ptr(img_qt), _ptr(img_aux), ni,
                               _ptr(pairs), P, L, n, Q, rows, mode, _ptr(out_l), _ptr(out_s),
-                              _ptr(out_d), _ptr(st), _ptr(curve))
+                              _ptr(out_d), _ptr(st), _ptr(curve), _ptr(scurve))
     res = {"rot_index": out_l, "shift_px": out_s, "sw2sq": out_d, "status": st,
            "theta_rad": 2.0 * np.pi * out_l / n}
     if want_curve:
         res["curve"] = curve
+        res["shift_curve"] = scurve
     return res
 
 

@@ -378,13 +378,14 @@ static double oracle_max_sliced(const double *U, const double *V, int n, int Q, 
    l* = argmin D*(l), ties to the smallest l.
    Outputs per pair: out_l[p] = l*, out_s[p][2] = s*(l*) in pixels (x along
    +column, y along +row), out_d[p] = D*(l*), status[p], curve[p][n] = D*(.)
-   (nullable).  pairs: [P][2] (ref index, img index) or NULL for all ref x img
+   (nullable), shift_curve[p][n][2] = s*(.) in pixels (nullable; zero in
+   modes 1 and 2).  pairs: [P][2] (ref index, img index) or NULL for all ref x img
    in row-major order (p = r * n_img + g). */
 void oracle_align_rows(const double *ref_qt, const double *ref_aux, int64_t n_ref,
                        const double *img_qt, const double *img_aux, int64_t n_img,
                        const int64_t *pairs, int64_t n_pairs, int L, int n, int Q, int rows,
                        int mode, int32_t *out_l, double *out_s, double *out_d, int32_t *status,
-                       double *curve)
+                       double *curve, double *shift_curve)
 {
     double *cs = (double *)malloc(sizeof(double) * n);
     double *sn = (double *)malloc(sizeof(double) * n);
@@ -438,6 +439,10 @@ void oracle_align_rows(const double *ref_qt, const double *ref_aux, int64_t n_re
             double d = mode == 2 ? oracle_max_sliced(U, V, n, Q, rows, l)
                                  : oracle_objective(U, V, n, Q, rows, l, sx, sy, cs, sn);
             if (curve) curve[p * n + l] = d;
+            if (shift_curve) {
+                shift_curve[2 * (p * n + l)] = sx / h;
+                shift_curve[2 * (p * n + l) + 1] = sy / h;
+            }
             if (best < 0 || d < bestd) {
                 best = l;
                 bestd = d;
@@ -462,7 +467,7 @@ void oracle_align(const double *ref_qt, const double *ref_aux, int64_t n_ref,
                   int32_t *out_l, double *out_s, double *out_d, int32_t *status, double *curve)
 {
     oracle_align_rows(ref_qt, ref_aux, n_ref, img_qt, img_aux, n_img, pairs, n_pairs, L, n, Q, Q,
-                      mode, out_l, out_s, out_d, status, curve);
+                      mode, out_l, out_s, out_d, status, curve, NULL);
 }
 
 /* D(l, s) for one table pair at arbitrary (l, s), s in unit coordinates:

@@ -272,7 +272,11 @@ class Server:
 
         ref_img = np.ascontiguousarray(ref_img, dtype=np.float32)
         imgs = np.ascontiguousarray(imgs, dtype=np.float32)
+        if imgs.ndim != 3 or imgs.shape[1] != imgs.shape[2]:
+            raise ValueError(f"imgs must be [N, L, L], got shape {imgs.shape}")
         N, L = imgs.shape[0], imgs.shape[-1]
+        if ref_img.shape != (L, L):
+            raise ValueError(f"ref_img must be [{L}, {L}], got shape {ref_img.shape}")
         req = sw_request(ref_img.ctypes.data, imgs.ctypes.data, N,
                          geom(L, n or L, Q or L, levels), int(ref_key))
         t = ctypes.c_uint64()

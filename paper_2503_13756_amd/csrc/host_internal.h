@@ -47,6 +47,9 @@ struct Ctx {
     // -1: the number of compute units
     int small_batch = -1;
     bool generic_align = false;  // never use the n = 128 register-FFT kernel
+    // failure injection for tests of the serving runtime: the request with
+    // this ticket has its host-to-device copy reported as failed (0: none)
+    uint64_t serve_fail_ticket = 0;
     bool small(int64_t N) const { return N < (small_batch >= 0 ? small_batch : cu_count); }
     void *scratch = nullptr;
     size_t scratch_bytes = 0;

@@ -258,8 +258,11 @@ __device__ __forceinline__ void accumulate_row(const LaneTask &tk, float k2, flo
 
 // Accumulate one LDS strip into the accumulators of this wave's tasks.  Task
 // slots are the outer loop (a wave-uniform guard each) and rows the inner
-// loop, two rows per iteration (the second from A3n, so that the row index
-// steps once per pair), so the LDS reads of both rows are in flight together.
+// loop, two rows per iteration, so the LDS reads of both rows are in flight
+// together.  Pairs start at even image rows whatever the strip's first row:
+// row 2m sits at 2m r + A3 and row 2m + 1 at 2m r + A3n (the row index steps
+// once per pair), so every row's line position, and with it the result, is
+// the same for any strip height.
 template <int TPW>
 __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const LaneTask (&tasks)[TPW],
                                                  const float *lds, int i0, int rows,
@@ -288,8 +291,15 @@ __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const LaneT
             float s0 = acc[t][0], s1 = acc[t][1], s2 = acc[t][2], s3 = acc[t][3];
             // only the rows of this strip that the task's lines cross
             const int ra = max(tk.rlo - i0, 0), rb = min(tk.rhi - i0 + 1, rows);
-            float fi = (float)(i0 + ra);  // row index, exact in FP32
             int rr = ra;
+            if (rr < rb && ((i0 + rr) & 1)) {  // odd first row (wave-uniform)
+                const int ka = lbase + 4 * window_pos(-2, rr * P.RS);
+                const int kc = lbase + 4 * window_pos(L - 1, rr * P.RS);
+                accumulate_row(tk, k2, hi3, fmaf((float)(i0 + rr - 1), tk.r, tk.A3n), ka, kc, s16,
+                               m16, s0, s1, s2, s3);
+                ++rr;
+            }
+            float fi = (float)(i0 + rr);  // even row index, exact in FP32
             for (; rr + 1 < rb; rr += 2, fi += 2.f) {
                 const int ka = lbase + 4 * window_pos(-2, rr * P.RS);
                 const int kc = lbase + 4 * window_pos(L - 1, rr * P.RS);

@@ -670,6 +670,8 @@ sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
             c->small_batch = std::stoi(m[1]);
         if (std::regex_search(txt, m, std::regex("\"align_kernel\"\\s*:\\s*\"generic\"")))
             c->generic_align = true;
+        if (std::regex_search(txt, m, std::regex("\"serve_fail_ticket\"\\s*:\\s*(\\d+)")))
+            c->serve_fail_ticket = std::stoull(m[1]);
     }
     *ctx = c;
     return SW_OK;

@@ -81,12 +81,22 @@ class Arena {
 
 enum class RState { Pending, Admitted, Launched, Done, Cancelled, Failed };
 
+// A cached reference table.  Its tables are usable once the step of the
+// request that computes them (the producer) has completed without error;
+// until then only requests in that step or in later steps on the same
+// stream may read them.  A producer that fails before or during its step
+// leaves the entry without a producer: the next request of that key to be
+// launched computes the tables itself, and requests that were launched
+// behind the failed producer (gen changed since their launch) fail.
 struct RefEntry {
     uint64_t key = 0;
     size_t off = 0, bytes = 0;
     int L = 0, n = 0, Q = 0, levels = 0;
     int users = 0;
     uint64_t last_use = 0;
+    bool ready = false;     // written by a step that completed without error
+    uint64_t producer = 0;  // ticket of the request whose step writes it (0: none)
+    uint64_t gen = 0;       // bumped whenever a producer fails
 };
 
 struct Step {
@@ -136,6 +146,7 @@ struct Req {
            o_rqt = 0, o_raux = 0;  // absolute arena offsets
     uint64_t ref_key = 0;       // cache entry used (0 = own tables)
     bool ref_compute = false;   // this request's step computes the reference tables
+    uint64_t ref_gen = 0;       // generation of the cache entry at launch
     sw_result *host_out = nullptr;
     size_t host_cap = 0;  // size class of host_out in the pin pool
     hipEvent_t copied = nullptr;
@@ -249,6 +260,7 @@ void admit(Server *s, std::vector<Req *> &fresh) {
             e.n = g.n;
             e.Q = g.Q;
             e.levels = g.levels;
+            e.producer = q->ticket;
             s->cache[key] = e;
             q->ref_compute = true;
         } else if (cached) {
@@ -297,6 +309,60 @@ void admit(Server *s, std::vector<Req *> &fresh) {
         ++s->st.admitted;
         ++live;
     }
+}
+
+// A request that computes cached reference tables has failed (before or in
+// its step): the entry loses its producer, and requests launched behind it
+// are failed by the generation check at their completion.
+void producer_failed(Server *s, Req *q) {
+    if (!q->ref_key || !q->ref_compute) return;
+    auto it = s->cache.find(q->ref_key);
+    if (it == s->cache.end() || it->second.producer != q->ticket) return;
+    it->second.producer = 0;
+    it->second.ready = false;
+    ++it->second.gen;
+}
+
+// Before a step is issued (lock held): every request of the batch that reads
+// a cached reference table whose tables are neither ready nor being computed
+// by this batch or by a step in flight computes them itself.
+void assign_producers(Server *s, const std::vector<Req *> &batch) {
+    for (Req *q : batch) {
+        if (!q->ref_key) continue;
+        auto ce = s->cache.find(q->ref_key);
+        if (ce == s->cache.end()) continue;  // cannot happen while q uses it
+        RefEntry &e = ce->second;
+        if (q->ref_compute) {
+            e.producer = q->ticket;
+        } else if (!e.ready) {
+            bool alive = false;
+            for (Req *o : batch) alive |= o->ticket == e.producer && o->ref_compute;
+            if (!alive && e.producer) {
+                auto it = s->reqs.find(e.producer);
+                alive = it != s->reqs.end() && it->second->state == RState::Launched;
+            }
+            if (!alive) {
+                q->ref_compute = true;
+                e.producer = q->ticket;
+            }
+        }
+        q->ref_gen = e.gen;
+    }
+}
+
+// At the completion of a step without error (lock held): false when the
+// request read reference tables whose producer failed after it was launched.
+bool reference_ok(Server *s, Req *q) {
+    if (!q->ref_key) return true;
+    auto it = s->cache.find(q->ref_key);
+    if (it == s->cache.end()) return true;
+    RefEntry &e = it->second;
+    if (q->ref_compute && e.producer == q->ticket) {
+        e.ready = true;
+        e.producer = 0;
+        return true;
+    }
+    return q->ref_compute || e.gen == q->ref_gen;
 }
 
 void release_request(Server *s, Req *q) {
@@ -474,10 +540,13 @@ void scheduler(Server *s) {
                 auto it = s->reqs.find(tk);
                 if (it == s->reqs.end()) continue;
                 Req *r = it->second.get();
+                const bool ref_ok = q == hipSuccess && reference_ok(s, r);
+                if (q != hipSuccess) producer_failed(s, r);
                 release_request(s, r);
-                if (q != hipSuccess) {
+                if (q != hipSuccess || !ref_ok) {
                     r->state = RState::Failed;
-                    r->err = hipGetErrorString(q);
+                    r->err = q != hipSuccess ? hipGetErrorString(q)
+                                             : "the step computing its cached reference failed";
                     ++s->st.failed;
                 } else if (r->cancel) {
                     r->state = RState::Cancelled;
@@ -513,6 +582,8 @@ void scheduler(Server *s) {
                 if (e == hipSuccess) e = hipEventCreateWithFlags(&q->copied, hipEventDisableTiming);
                 if (e == hipSuccess) e = hipEventRecord(q->copied, s->copy_s);
                 if (e != hipSuccess) q->err = hipGetErrorString(e);
+                else if (q->ticket == s->ctx->serve_fail_ticket)
+                    q->err = "injected copy failure (serve_fail_ticket)";
             }
             lk.lock();
         }
@@ -532,6 +603,7 @@ void scheduler(Server *s) {
             for (auto it = rest.begin(); it != rest.end();) {
                 Req *q = s->reqs[*it].get();
                 if (!q->err.empty()) {
+                    producer_failed(s, q);
                     release_request(s, q);
                     q->state = RState::Failed;
                     ++s->st.failed;
@@ -542,6 +614,7 @@ void scheduler(Server *s) {
             }
             s->admitted = rest;
             if (batch.empty()) break;
+            assign_producers(s, batch);
             Step stp;
             hipError_t e = hipEventCreateWithFlags(&stp.done, hipEventDisableTiming);
             lk.unlock();
@@ -553,6 +626,7 @@ void scheduler(Server *s) {
             }
             if (e != hipSuccess) {
                 for (Req *q : batch) {
+                    producer_failed(s, q);
                     release_request(s, q);
                     q->state = RState::Failed;
                     q->err = hipGetErrorString(e);

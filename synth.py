@@ -102,6 +102,44 @@ def copies(rng, params, L, N, shift_px, jitter_px, snr):
     return out, truth_theta, truth_shift
 
 
+def raw_image(rng, clean, L, snr, corner=True, scale_range=(0.01, 100.0)):
+    """An unprocessed image: `clean` plus white noise at `snr` (when given),
+    NOT clipped, masked or normalised, times a log-uniform overall scale, with
+    (when `corner`) positive values uniform in [0, 2 max(clean)] on every
+    pixel outside radius 1 - h.  Draw order: noise field (L*L), scale, corner
+    field (L*L).  The positive-part rule and the disk support are left to the
+    code under test."""
+    x = clean.copy()
+    if snr is not None:
+        sd = math.sqrt(clean.var() / snr)
+        x = x + rng.normal(0.0, sd, size=(L, L))
+    scale = math.exp(rng.uniform(math.log(scale_range[0]), math.log(scale_range[1])))
+    if corner:
+        c = rng.uniform(0.0, 2.0 * clean.max(), size=(L, L))
+        x = np.where(disk_keep(L), x, c)
+    return (x * scale).astype(np.float32)
+
+
+def make_raw_stack(seed, L, N, K=6, shift_px=None, jitter_px=1.0, snr=1.0):
+    """Like make_stack, but reference and copies are raw (see raw_image): the
+    reference noisy as well, every image with about half its pixels negative,
+    mass outside the disk and its own scale.  Per copy: phi, t, jitter, then
+    raw_image's draws."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = 2.0 / L
+    shift_px = max(1.0, L / 16) if shift_px is None else shift_px
+    centres, sigmas, amps = blob_params(rng, K, L)
+    ref = raw_image(rng, render(centres, sigmas, amps, L), L, snr)
+    out = np.zeros((N, L, L), np.float32)
+    for g in range(N):
+        phi = rng.uniform(0.0, 2.0 * math.pi)
+        t = rng.uniform(-shift_px, shift_px, size=2) * h
+        eps = rng.normal(0.0, jitter_px, size=(K, 2)) * h
+        c2 = centres @ rot(phi).T + t[None, :] + eps
+        out[g] = raw_image(rng, render(c2, sigmas, amps, L), L, snr)
+    return ref, out
+
+
 def make_pair(seed=SEED_BASE, L=64, K=5, shift_px=4.0, jitter_px=1.0):
     """Single pair: reference A (K blobs) and one rotated/shifted copy B."""
     rng = np.random.Generator(np.random.PCG64(seed))

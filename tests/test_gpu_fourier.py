@@ -46,19 +46,29 @@ def blob_stack(L, N, seed):
     return ref, imgs
 
 
+def raw_stack(L, N, seed):
+    """Unprocessed inputs: negative pixels, mass outside the disk, any scale."""
+    return synth.make_raw_stack(seed, L, N)
+
+
 def proj_err(pmf, P0):
     """Largest deviation per image relative to its largest oracle value."""
     P0 = np.maximum(P0, 0.0)
     return np.abs(pmf - P0).max(axis=(1, 2)) / P0.max(axis=(1, 2))
 
 
+@pytest.mark.parametrize("kind", ["clean", "raw"])
 @pytest.mark.parametrize("L,n,Q", FGEOMS)
-def test_fourier_projection_parity(api, ctx, oracle, L, n, Q):
+def test_fourier_projection_parity(api, ctx, oracle, L, n, Q, kind):
     """Blob images and uniform noise: every clipped projection value against
-    the oracle's (clipped) exact DFT route."""
+    the oracle's (clipped) exact DFT route.  Raw inputs (negative pixels,
+    mass outside the disk) check the kernel's own positive part and mask."""
     N = 2 if L >= 128 else 4
-    _, imgs = blob_stack(L, N, 300 + L)
-    imgs = np.concatenate([imgs, synth.uniform_images(11, L, 1)])
+    if kind == "raw":
+        _, imgs = raw_stack(L, N + 1, 310 + L)
+    else:
+        _, imgs = blob_stack(L, N, 300 + L)
+        imgs = np.concatenate([imgs, synth.uniform_images(11, L, 1)])
     pmf = api.project_fourier(ctx, dev(imgs), n).cpu().numpy()
     P0, _ = oracle.fourier_project(imgs, n)
     err = proj_err(pmf, P0)
@@ -114,13 +124,15 @@ def test_fourier_rejects_other_sizes(api, ctx):
         api.project_fourier(ctx, dev(imgs), 24)
 
 
-@pytest.mark.parametrize("L,n,Q", [(32, 32, 32), (64, 64, 64), (128, 128, 128)])
-def test_fourier_tables_and_alignment(api, ctx, oracle, L, n, Q):
+@pytest.mark.parametrize("L,n,Q,kind", [(32, 32, 32, "clean"), (64, 64, 64, "clean"),
+                                        (128, 128, 128, "clean"), (64, 64, 64, "raw"),
+                                        (128, 128, 128, "raw")])
+def test_fourier_tables_and_alignment(api, ctx, oracle, L, n, Q, kind):
     """Images -> Fourier-slice tables -> alignment on the GPU against the
     oracle from the same images: tables, rotation (tie-aware), shift and
     distance."""
     N = 8 if L == 128 else 16
-    ref, imgs = blob_stack(L, N, 500 + L)
+    ref, imgs = (raw_stack if kind == "raw" else blob_stack)(L, N, 500 + L)
     rq, ra = api.tables_fourier(ctx, dev(ref[None]), n, Q)
     iq, ia = api.tables_fourier(ctx, dev(imgs), n, Q)
     oq, oa = oracle.fourier_tables(ref[None], n, Q)

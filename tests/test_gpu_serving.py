@@ -49,8 +49,15 @@ def oracle_for(oracle, ref, imgs, L):
 SIDES = [(64, 7), (96, 5), (128, 9), (192, 3), (256, 4), (64, 2)]
 
 
-def test_align_stacks_parity(api, ctx, oracle):
-    data = [stack(L, N, 2000 + i) for i, (L, N) in enumerate(SIDES)]
+def raw(L, N, seed):
+    """Unprocessed inputs: negative pixels, mass outside the disk, any scale."""
+    return synth.make_raw_stack(seed, L, N)
+
+
+@pytest.mark.parametrize("kind", ["clean", "raw"])
+def test_align_stacks_parity(api, ctx, oracle, kind):
+    make = raw if kind == "raw" else stack
+    data = [make(L, N, 2000 + i) for i, (L, N) in enumerate(SIDES)]
     outs = api.align_stacks(ctx, [(dev(r), dev(x)) for r, x in data])
     for (L, N), (r, x), o in zip(SIDES, data, outs):
         g = api.unpack_results(o["res"])
@@ -96,6 +103,31 @@ def test_autotune_table_roundtrip(api, ctx, tmp_path):
     c2.close()
 
 
+def strip_rows_max(L):
+    """Largest strip height of the projection at side L (8192 floats per
+    strip kind, rows of 4 ((L + 4) | 1) floats)."""
+    return min(L, 8192 // (4 * ((L + 4) | 1)))
+
+
+def test_strip_height_never_changes_results(api, ctx, tmp_path):
+    """Every admissible strip height of the mixed launches gives bitwise the
+    results and tables of the default: a row's line position depends on its
+    image row only, never on where a strip starts."""
+    data = [stack(L, N, 2350 + i) for i, (L, N) in enumerate([(64, 5), (128, 6), (256, 3),
+                                                             (96, 4)])]
+    base = api.align_stacks(ctx, [(dev(r), dev(x)) for r, x in data])
+    for L in (64, 96, 128, 256):
+        for R in range(1, strip_rows_max(L) + 1):
+            path = tmp_path / f"t{L}_{R}.json"
+            path.write_text('{"tiles": {"%d": {"R": %d}}}' % (L, R))
+            c = api.Context(0, tune_json=str(path))
+            got = api.align_stacks(c, [(dev(r), dev(x)) for r, x in data])
+            c.close()
+            for a, b in zip(got, base):
+                assert np.array_equal(a["qt"].cpu().numpy(), b["qt"].cpu().numpy()), (L, R)
+                assert np.array_equal(a["res"].cpu().numpy(), b["res"].cpu().numpy()), (L, R)
+
+
 # ---------------------------------------------------------------- serving
 def wait_all(srv, tickets, timeout=60.0):
     out, t0 = {}, time.time()
@@ -110,14 +142,15 @@ def wait_all(srv, tickets, timeout=60.0):
     return out
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_serving_alone_equals_mix(api, oracle, prec):
+@pytest.mark.parametrize("prec,kind", [(0, "clean"), (1, "clean"), (0, "raw")])
+def test_serving_alone_equals_mix(api, oracle, prec, kind):
     c = api.Context(0)
     srv = api.Server(c, hbm_budget_bytes=1 << 30, prec=prec)
-    A = stack(128, 12, 2400)
+    make = raw if kind == "raw" else stack
+    A = make(128, 12, 2400)
     alone = wait_all(srv, [srv.submit(*A)])
     ra = list(alone.values())[0]
-    mix = [stack(64, 30, 2401), A, stack(256, 5, 2402), stack(128, 20, 2403), A]
+    mix = [make(64, 30, 2401), A, make(256, 5, 2402), make(128, 20, 2403), A]
     ts = [srv.submit(r, x) for r, x in mix]
     got = wait_all(srv, ts)
     for k in (1, 4):  # A in the mix, twice
@@ -213,5 +246,51 @@ def test_serving_reference_cache_and_cancel(api):
     with pytest.raises(Exception):
         srv.poll(ts[3])
     wait_all(srv, ts[:3])
+    srv.stop()
+    c.close()
+
+
+def test_serving_cache_producer_failure_recomputes(api, oracle, tmp_path):
+    """The request that would compute a cached reference table fails on the
+    host (an injected copy failure, no device fault): a request with the same
+    key queued behind it computes the tables itself, and later requests of
+    that key hit the cache; all results match the oracle and the uncached
+    path."""
+    from paper_2503_13756_amd._abi import SwError
+
+    path = tmp_path / "fail.json"
+    path.write_text('{"serve_fail_ticket": 2}')
+    c = api.Context(0, tune_json=str(path))
+    srv = api.Server(c, hbm_budget_bytes=1 << 29, prec=0)
+    r, x = stack(64, 16, 2800)
+    plain = list(wait_all(srv, [srv.submit(r, x)]).values())[0]  # ticket 1
+    t2 = srv.submit(r, x, ref_key=91)      # ticket 2: its copy "fails"
+    t3 = srv.submit(r, x[:6], ref_key=91)  # queued behind it, same key
+    got3 = wait_all(srv, [t3])
+    with pytest.raises(SwError, match="injected"):
+        for _ in range(20000):
+            if srv.poll(t2) is not None:
+                break
+            time.sleep(0.001)
+    assert np.array_equal(got3[t3], plain[:6])
+    t4 = srv.submit(r, x, ref_key=91)
+    got4 = wait_all(srv, [t4])
+    assert np.array_equal(got4[t4], plain)
+    st = srv.stats()
+    assert st["failed"] == 1 and st["cache_hits"] >= 2
+    orc = oracle_for(oracle, r, x, 64)
+    parity.check(api.records_to_dict(got4[t4]), orc, 64, parity.TAU_FP32, orc["curve"])
+    srv.stop()
+    c.close()
+
+
+def test_serving_rejects_mismatched_shapes(api):
+    c = api.Context(0)
+    srv = api.Server(c, hbm_budget_bytes=1 << 26, prec=0)
+    r, x = stack(64, 3, 2900)
+    with pytest.raises(ValueError):
+        srv.submit(r[:32, :32], x)
+    with pytest.raises(ValueError):
+        srv.submit(r, x[:, :, :32])
     srv.stop()
     c.close()
