@@ -267,6 +267,24 @@ typedef struct {
 sw_status sw_align_batch(void *ctx, const sw_batch *b /*host*/, sw_result *out, float *curve,
                          void *stream);
 
+/* sw_align_batch for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   same arguments, same kernels, same results, but no allocation of any
+   kind.  Its angle tables and scratch live in one fixed array per GPU
+   (64 MiB of work area plus the angle tables of every admissible n_angles,
+   held from the first sw_ctx_create on that GPU until the process ends).
+   A call whose scratch need exceeds 64 MiB fails with SW_E_NOMEM before any
+   launch: the 1-vs-many and pair-list forms need 8 (n/2+1) Q bytes per
+   reference (plus 520 Q bytes per reference at n = 128: 133 KiB in all at
+   n = Q = 128), the all-pairs BF16 form 4 (n/2+1) Q bytes per table of
+   both sets plus 2 top_k bytes per pair (about 47 MiB for 2,000 x 2,000
+   tables at n = Q = 64).  All calls on
+   one GPU share the array: calls that overlap on one GPU (other streams,
+   other contexts, other threads) race and must be ordered by the caller.
+   Nothing in it needs clearing between calls. */
+sw_status sw_align_batch_noalloc(void *ctx, const sw_batch *b /*host*/, sw_result *out,
+                                 float *curve, void *stream);
+
 /* Uneven batch: stacks of images of different geometry, each aligned
    against its own reference image (steps 1-5 for every image of every
    stack).  All stacks go through persistent mixed-geometry launches (one

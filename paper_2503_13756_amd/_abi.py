@@ -92,6 +92,7 @@ SIGNATURES = [
     ("sw_project_fourier_at", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
     ("sw_tables_fourier_at", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P, P]),
     ("sw_align_batch", I32, [P, ctypes.POINTER(sw_batch), P, P, P]),
+    ("sw_align_batch_noalloc", I32, [P, ctypes.POINTER(sw_batch), P, P, P]),
     ("sw_align_stacks", I32, [P, ctypes.POINTER(sw_stack), I32, I32, I32, I32, P]),
     ("sw_autotune", I32, [P, ctypes.POINTER(ctypes.c_int32), I32, I64, ctypes.c_char_p]),
     ("sw_serve_start", I32, [P, ctypes.POINTER(sw_serve_cfg)]),

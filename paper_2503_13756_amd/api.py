@@ -190,18 +190,21 @@ def make_batch(ref_qt, ref_aux, img_qt, img_aux, L, pairs=None, mode=_abi.MODE_R
 
 def align_batch(ctx: Context, ref_qt, ref_aux, img_qt, img_aux, L, pairs=None,
                 mode=_abi.MODE_ROT_TRANS, prec=_abi.PREC_FP32, top_k=0, want_curve=False,
-                levels=_abi.LEVELS_MIDPOINT, stream=None, out=None, ramp=False):
-    """sw_align_batch.  Returns the raw [P, 6] int32 result records (see
-    `unpack_results`) and the [P, n] curve when requested.  ramp=True: the
-    tables are stacked ramp-filtered tables and sw2sq is the ramp-filtered
-    distance."""
+                levels=_abi.LEVELS_MIDPOINT, stream=None, out=None, ramp=False, noalloc=False,
+                curve_out=None):
+    """sw_align_batch (noalloc=True: sw_align_batch_noalloc).  Returns the raw
+    [P, 6] int32 result records (see `unpack_results`) and the [P, n] curve
+    when requested (into curve_out when given).  ramp=True: the tables are
+    stacked ramp-filtered tables and sw2sq is the ramp-filtered distance."""
     b, P = make_batch(ref_qt, ref_aux, img_qt, img_aux, L, pairs, mode, prec, top_k, levels,
                       ramp)
     dev = img_qt.device
     res = out if out is not None else torch.empty((P, 6), dtype=torch.int32, device=dev)
-    curve = torch.empty((P, b.geom.n_angles), dtype=torch.float32, device=dev) if want_curve else None
-    check(ctx._lib.sw_align_batch(ctx.handle, ctypes.byref(b), _ptr(res), _ptr(curve),
-                                  _stream(stream)))
+    curve = curve_out
+    if want_curve and curve is None:
+        curve = torch.empty((P, b.geom.n_angles), dtype=torch.float32, device=dev)
+    fn = ctx._lib.sw_align_batch_noalloc if noalloc else ctx._lib.sw_align_batch
+    check(fn(ctx.handle, ctypes.byref(b), _ptr(res), _ptr(curve), _stream(stream)))
     return res, curve
 
 

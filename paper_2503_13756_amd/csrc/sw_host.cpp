@@ -126,6 +126,83 @@ sw_status get_table(Ctx *ctx, int n, const sw::AngleTable **out) {
     return SW_OK;
 }
 
+// ---- the allocation-free alignment entry point (sw_align_batch_noalloc) ----
+// Its device memory is one file-scope array per GPU: the angle tables of every
+// admissible n_angles (written once per device at set-up) followed by the
+// work area that sw_align_batch takes from the context scratch (reference
+// spectra and n = 128 coefficients, or the bfloat16 spectra and candidate
+// lags of the all-pairs path).  In host code `scratch` only names the
+// symbol; its device address comes from hipGetSymbolAddress, per device.
+constexpr size_t kNoAllocAngleBytes = 128 * 1024;
+constexpr size_t kNoAllocWorkBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocAngleBytes + kNoAllocWorkBytes];
+
+struct NoAllocDevice {
+    sw_status status = SW_OK;  // of the set-up on this device
+    std::string err;
+    char *work = nullptr;      // device address of the work area
+    std::map<int, sw::AngleTable> tables;
+};
+static std::mutex g_noalloc_mu;
+static std::map<int, NoAllocDevice> g_noalloc;  // per device
+
+// Set-up on the current device (once per device): the array's device
+// address, and the angle tables of every admissible n copied into it.
+static void noalloc_setup(int device) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc.count(device)) return;
+    NoAllocDevice &d = g_noalloc[device];
+    char *base = nullptr;
+    hipError_t e = hipGetSymbolAddress((void **)&base, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !base) {
+        d.status = SW_E_DEVICE;
+        d.err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return;
+    }
+    size_t off = 0;
+    for (int n = 8; n <= sw::kMaxN; n += 8) {
+        if (!only_2_3(n)) continue;
+        std::vector<double> c, sn;
+        angle_values(n, c, sn);
+        std::vector<float2> t32(n);
+        std::vector<double2> t64(n);
+        for (int m = 0; m < n; ++m) {
+            t32[m] = make_float2((float)c[m], (float)(-sn[m]));
+            t64[m] = make_double2(c[m], -sn[m]);
+        }
+        sw::AngleTable t;
+        t.n = n;
+        t.d64 = (double2 *)(base + off);
+        off += sizeof(double2) * n;
+        t.d32 = (float2 *)(base + off);
+        off += (sizeof(float2) * n + 15) & ~(size_t)15;
+        if (off > kNoAllocAngleBytes) {
+            d.status = SW_E_DEVICE;
+            d.err = "angle tables exceed their part of the no-alloc scratch";
+            return;
+        }
+        e = hipMemcpy(t.d64, t64.data(), sizeof(double2) * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(t.d32, t32.data(), sizeof(float2) * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            d.status = SW_E_DEVICE;
+            d.err = std::string("hipMemcpy(no-alloc angle tables): ") + hipGetErrorString(e);
+            return;
+        }
+        d.tables[n] = t;
+    }
+    d.work = base + kNoAllocAngleBytes;
+}
+
+static sw_status noalloc_device(int device, NoAllocDevice **out) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc.find(device);
+    if (it == g_noalloc.end())
+        return fail(SW_E_INVALID, "the no-alloc scratch of device %d is not set up", device);
+    if (it->second.status != SW_OK) return fail(it->second.status, "%s", it->second.err.c_str());
+    *out = &it->second;
+    return SW_OK;
+}
+
 // Work order of the projection for (L, n): every (slot, bin) item gets the
 // range of image rows where a pixel inside the disk has non-zero weight for
 // its line (pixel (i, j) weighs 1 - c |j - u(i)| with u(i) the column where
@@ -651,6 +728,9 @@ sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
                 delete c;
                 return hip_fail(e, "hipEventCreate");
             }
+        // the no-alloc entry point's scratch on this device (a failure is
+        // reported by that entry point, every other call works without it)
+        noalloc_setup(device);
     }
     if (tune_json && *tune_json) {
         std::ifstream f(tune_json);
@@ -1006,8 +1086,11 @@ sw_status sw_tables_fourier_at(void *ctx, const float *img, int64_t N, const sw_
     return tables_fourier(ctx, img, N, g, theta, qt, aux, stream);
 }
 
-sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *curve,
-                         void *stream) {
+// sw_align_batch and sw_align_batch_noalloc: with noalloc the angle table
+// and the scratch come from the file-scope array of the device, and a call
+// needing more scratch than it holds fails.
+static sw_status align_batch_impl(void *ctx, const sw_batch *b, sw_result *out, float *curve,
+                                  void *stream, bool noalloc) {
     if (!ctx) return fail(SW_E_INVALID, "ctx is NULL");
     if (!b) return fail(SW_E_INVALID, "batch is NULL");
     sw::Geo geo;
@@ -1047,7 +1130,23 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
     DeviceGuard dg(c->device);
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
     const sw::AngleTable *t;
-    if ((st = get_table(c, geo.n, &t)) != SW_OK) return st;
+    NoAllocDevice *na = nullptr;
+    if (noalloc) {
+        if ((st = noalloc_device(c->device, &na)) != SW_OK) return st;
+        t = &na->tables.at(geo.n);  // every admissible n is there
+    } else if ((st = get_table(c, geo.n, &t)) != SW_OK) {
+        return st;
+    }
+    // the call's scratch: the context's (grown on demand) or the array's
+    auto take_scratch = [&](size_t bytes, void **p) -> sw_status {
+        if (!noalloc) return get_scratch(c, bytes, (hipStream_t)stream, p);
+        if (bytes > kNoAllocWorkBytes)
+            return fail(SW_E_NOMEM,
+                        "the call needs %zu bytes of scratch; sw_align_batch_noalloc holds %zu",
+                        bytes, kNoAllocWorkBytes);
+        *p = na->work;
+        return SW_OK;
+    };
     hipStream_t s = (hipStream_t)stream;
     if (b->mode == SW_MODE_MAX_SLICED) {
         sw::PairArgs a{};
@@ -1082,7 +1181,7 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
         const size_t img_bytes = same_set ? 0 : (per * (size_t)b->n_img + 255) & ~(size_t)255;
         const size_t cand_bytes = sizeof(int16_t) * (size_t)P * top_k;
         void *scr;
-        if ((st = get_scratch(c, ref_bytes + img_bytes + cand_bytes, s, &scr)) != SW_OK) return st;
+        if ((st = take_scratch(ref_bytes + img_bytes + cand_bytes, &scr)) != SW_OK) return st;
         char *base = (char *)scr;
         uint32_t *spec_ref = (uint32_t *)base;
         uint32_t *spec_img = same_set ? spec_ref : (uint32_t *)(base + ref_bytes);
@@ -1117,7 +1216,7 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
     const bool fast128 = sw::align128_supported(geo) && !c->generic_align;
     const size_t gam_bytes = fast128 ? sw::align128_scratch_bytes(geo, b->n_ref) : 0;
     void *spec;
-    if ((st = get_scratch(c, spec_bytes + gam_bytes, s, &spec)) != SW_OK) return st;
+    if ((st = take_scratch(spec_bytes + gam_bytes, &spec)) != SW_OK) return st;
     hipError_t e = sw::launch_spectrum(b->ref_qt, b->n_ref, geo, *t, spec, 0, s);
     if (e != hipSuccess) return hip_fail(e, "k_spectrum launch");
     sw::PairArgs a;
@@ -1147,6 +1246,16 @@ sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *cu
         if (e != hipSuccess) return hip_fail(e, "k_scale_results launch");
     }
     return SW_OK;
+}
+
+sw_status sw_align_batch(void *ctx, const sw_batch *b, sw_result *out, float *curve,
+                         void *stream) {
+    return align_batch_impl(ctx, b, out, curve, stream, false);
+}
+
+sw_status sw_align_batch_noalloc(void *ctx, const sw_batch *b, sw_result *out, float *curve,
+                                 void *stream) {
+    return align_batch_impl(ctx, b, out, curve, stream, true);
 }
 
 sw_status sw_align_stacks(void *ctx, const sw_stack *stacks, int32_t n_stacks, int32_t mode,
