@@ -355,11 +355,16 @@ typedef struct {
     uint64_t ref_key;     /* 0 = reference tables not cached */
 } sw_request;
 
+/* Counters since sw_serve_start.  waited_memory / waited_slot: admitted
+   requests that, at the head of the queue, had to wait because the arena
+   had no room for them / because max_slots requests were in flight (a
+   request may count in both). */
 typedef struct {
     uint64_t submitted, admitted, completed, cancelled, failed;
     uint64_t steps, graph_launches, cache_hits, evictions;
     int64_t pending, in_flight;
     size_t arena_used, arena_peak, arena_size;
+    uint64_t waited_memory, waited_slot;
 } sw_serve_stats;
 
 sw_status sw_serve_start(void *ctx, const sw_serve_cfg *cfg /*host*/);

@@ -65,7 +65,8 @@ class sw_serve_stats(ctypes.Structure):
                                                "evictions")] + \
                [("pending", ctypes.c_int64), ("in_flight", ctypes.c_int64),
                 ("arena_used", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t),
-                ("arena_size", ctypes.c_size_t)]
+                ("arena_size", ctypes.c_size_t), ("waited_memory", ctypes.c_uint64),
+                ("waited_slot", ctypes.c_uint64)]
 
 
 class SwError(RuntimeError):

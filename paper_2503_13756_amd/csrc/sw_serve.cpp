@@ -147,6 +147,7 @@ struct Req {
     uint64_t ref_key = 0;       // cache entry used (0 = own tables)
     bool ref_compute = false;   // this request's step computes the reference tables
     uint64_t ref_gen = 0;       // generation of the cache entry at launch
+    bool waited_memory = false, waited_slot = false;  // held at the head of the queue
     sw_result *host_out = nullptr;
     size_t host_cap = 0;  // size class of host_out in the pin pool
     hipEvent_t copied = nullptr;
@@ -228,7 +229,12 @@ bool alloc_evicting(Server *s, size_t bytes, size_t *off) {
 void admit(Server *s, std::vector<Req *> &fresh) {
     int64_t live = (int64_t)s->admitted.size();
     for (auto &stp : s->steps) live += (int64_t)stp.tickets.size();
-    while (!s->pending.empty() && live < s->cfg.max_slots) {
+    for (;;) {
+        if (s->pending.empty()) break;
+        if (live >= s->cfg.max_slots) {
+            s->reqs[s->pending.front()]->waited_slot = true;
+            break;
+        }
         Req *q = s->reqs[s->pending.front()].get();
         const sw::Geo &g = q->geo;
         const uint64_t key = q->r.ref_key;
@@ -245,10 +251,14 @@ void admit(Server *s, std::vector<Req *> &fresh) {
         size_t off = 0, need = request_bytes(q->r, g, own_ref);
         size_t ref_off = 0, ref_bytes = up(4 * (size_t)g.Q * g.n) + up(32);
         if (key && !cached) {
-            if (!alloc_evicting(s, ref_bytes, &ref_off)) break;
+            if (!alloc_evicting(s, ref_bytes, &ref_off)) {
+                q->waited_memory = true;
+                break;
+            }
         }
         if (!alloc_evicting(s, need, &off)) {
             if (key && !cached) s->arena.release(ref_off, ref_bytes);
+            q->waited_memory = true;
             break;
         }
         if (key && !cached) {
@@ -307,6 +317,8 @@ void admit(Server *s, std::vector<Req *> &fresh) {
         s->admitted.push_back(q->ticket);
         fresh.push_back(q);
         ++s->st.admitted;
+        s->st.waited_memory += q->waited_memory;
+        s->st.waited_slot += q->waited_slot;
         ++live;
     }
 }
