@@ -4,6 +4,7 @@
 // last strip the block writes the PMF table into the same LDS region and
 // inverts its columns there (quant_dev.h).  Results are identical in form to
 // the stand-alone projection followed by the stand-alone quantile stage.
+#include "proj2_dev.h"
 #include "proj_dev.h"
 #include "quant_dev.h"
 #include "ramp_dev.h"
@@ -39,6 +40,48 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
     __syncthreads();
     quantile_phase<NT>([&](int k, int b) { return region[k * L + b]; }, L, n, Q, T.levels, T.TC,
                        d64, Ut, colS, qt + g * (int64_t)Q * n, aux ? aux + 4 * g : nullptr);
+}
+
+// The same for two images per block (proj2_dev.h): one line position, three
+// weights and one LDS address per row serve both images.  The projections
+// stay in registers until the strips are done; then each image in turn
+// writes its PMF table into the region and inverts it.  Results are bitwise
+// those of k_tables.  Only for geometries with one task group of at most six
+// tasks per wave.
+template <int NT, int TPW>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_tables2(
+    const float *__restrict__ img, int64_t N, TablesShape T, const float2 *__restrict__ d32,
+    const double2 *__restrict__ d64, float *__restrict__ qt, double *__restrict__ aux) {
+    constexpr int NW = NT / 64;
+    extern __shared__ __align__(16) double ldsd[];
+    const int64_t g0 = 2 * (int64_t)blockIdx.x;
+    if (g0 >= N) return;
+    const int nimg = N - g0 >= 2 ? 2 : 1;
+    const ProjShape &P = T.P;
+    const int L = P.L, n = P.n, Q = T.Q;
+    float *region = (float *)ldsd;
+    double *colS = ldsd + T.region_floats / 2;
+    float *Ut = (float *)(colS + 2 * n);
+    const float *F[2] = {img + g0 * (int64_t)L * L, img + (g0 + nimg - 1) * (int64_t)L * L};
+    float acc[2][TPW][4];
+    int bad[2];
+    project_images2<NT, TPW, 2>(F, nimg, P, d32, region, acc, bad);
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        if (g < nimg) {  // block-uniform
+            __syncthreads();  // strips, or the previous image's PMF, no longer read
+            if (!bad[g])
+                emit_outputs<TPW>(P, 0, wave, NW, lane, acc[g],
+                                  [&](int k, int b, float v) { region[k * L + b] = v; });
+            else
+                for (int t = threadIdx.x; t < n * L; t += NT) region[t] = __int_as_float(0x7fc00000);
+            __syncthreads();
+            quantile_phase<NT>([&](int k, int b) { return region[k * L + b]; }, L, n, Q, T.levels,
+                               T.TC, d64, Ut, colS, qt + (g0 + g) * (int64_t)Q * n,
+                               aux ? aux + 4 * (g0 + g) : nullptr);
+        }
+    }
 }
 
 // Fused ramp-filtered tables (ramp-filtered SW of Sec. 2.3): the projection
@@ -162,8 +205,20 @@ static hipError_t launch_tables_t(const float *img, int64_t N, const TablesShape
     return hipGetLastError();
 }
 
+template <int NT, int TPW>
+static hipError_t launch_tables2_t(const float *img, int64_t N, const TablesShape &T, size_t lds,
+                                   const AngleTable &t, float *qt, double *aux, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_tables2<NT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
+    (void)attr;
+    hipLaunchKernelGGL((k_tables2<NT, TPW>), dim3((unsigned)((N + 1) / 2)), dim3(NT), lds, s, img,
+                       N, T, t.d32, t.d64, qt, aux);
+    return hipGetLastError();
+}
+
 hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t,
-                         const ProjPlan &pp, float *qt, double *aux, hipStream_t s) {
+                         const ProjPlan &pp, float *qt, double *aux, hipStream_t s,
+                         int per_block) {
     if (N <= 0) return hipSuccess;
     TablesShape T;
     size_t lds = tables_lds_bytes(g, 512, &T);
@@ -173,6 +228,12 @@ hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t
     T.P.trow = pp.trow;
     if (lds != 0 && lds <= 79 * 1024) {
         const int w = tasks_per_wave(T.P.ntasks, 512);
+        if (per_block == 2 && T.region_floats * 4 >= 2 * kImg2Bytes) {
+            if (w <= 2) return launch_tables2_t<512, 2>(img, N, T, lds, t, qt, aux, s);
+            if (w <= 4) return launch_tables2_t<512, 4>(img, N, T, lds, t, qt, aux, s);
+            if (w <= 5) return launch_tables2_t<512, 5>(img, N, T, lds, t, qt, aux, s);
+            if (w <= 6) return launch_tables2_t<512, 6>(img, N, T, lds, t, qt, aux, s);
+        }
         if (w <= 2) return launch_tables_t<512, 2>(img, N, T, lds, t, qt, aux, s);
         if (w <= 4) return launch_tables_t<512, 4>(img, N, T, lds, t, qt, aux, s);
         if (w <= 5) return launch_tables_t<512, 5>(img, N, T, lds, t, qt, aux, s);

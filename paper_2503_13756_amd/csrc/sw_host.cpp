@@ -750,6 +750,8 @@ sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
             c->small_batch = std::stoi(m[1]);
         if (std::regex_search(txt, m, std::regex("\"align_kernel\"\\s*:\\s*\"generic\"")))
             c->generic_align = true;
+        if (std::regex_search(txt, m, std::regex("\"tables_images_per_block\"\\s*:\\s*([12])")))
+            c->tables_per_block = std::stoi(m[1]);
         if (std::regex_search(txt, m, std::regex("\"serve_fail_ticket\"\\s*:\\s*(\\d+)")))
             c->serve_fail_ticket = std::stoull(m[1]);
     }
@@ -851,7 +853,7 @@ sw_status sw_tables(void *ctx, const float *img, int64_t N, const sw_geom *g, fl
     // and invert with 16 waves per image, through scratch.
     const bool small = c->small(N);
     if (!small && sw::tables_fused_fits(geo)) {
-        hipError_t e = sw::launch_tables(img, N, geo, *t, *pp, qt, aux, s);
+        hipError_t e = sw::launch_tables(img, N, geo, *t, *pp, qt, aux, s, c->tables_per_block);
         return e == hipSuccess ? SW_OK : hip_fail(e, "k_tables launch");
     }
     // Otherwise the PMF table of one image does not fit in LDS: project and

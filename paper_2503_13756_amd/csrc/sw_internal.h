@@ -97,8 +97,11 @@ hipError_t launch_scale_results(Result *out, int64_t P, float *curve, int n, flo
 // Fused image -> quantile table; only for geometries where
 // tables_fused_fits() holds (the PMF table must fit in LDS).
 bool tables_fused_fits(Geo g);
+// per_block: images per block, 2 (weights shared by two images, where the
+// geometry allows it) or 1; the results are the same.
 hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t,
-                         const ProjPlan &pp, float *qt, double *aux, hipStream_t s);
+                         const ProjPlan &pp, float *qt, double *aux, hipStream_t s,
+                         int per_block = 2);
 // Angle spectra of quantile tables: spec[g][w][j] complex, w in [0, n/2],
 // j in [0, Q); bf16 != 0 stores bfloat16 pairs instead of float pairs.
 hipError_t launch_spectrum(const float *qt, int64_t N, Geo g, const AngleTable &t, void *spec,

@@ -25,13 +25,15 @@ def api():
 
 @pytest.fixture(scope="module")
 def ctxs(api, tmp_path_factory):
-    """Contexts for the two launch policies of the image stages: one block
-    per image (fused tables kernel) and several blocks per image (split
-    projection, then the 16-wave quantile kernel)."""
+    """Contexts for the launch policies of the image stages: the fused tables
+    kernel (two images per block where the geometry allows it, or one), and
+    several blocks per image (split projection, then the 16-wave quantile
+    kernel)."""
     out = {}
-    for name, thr in (("perimage", 0), ("split", 1 << 30)):
+    for name, txt in (("perimage", '{"small_batch": 0}'), ("split", '{"small_batch": 1073741824}'),
+                      ("one", '{"small_batch": 0, "tables_images_per_block": 1}')):
         path = tmp_path_factory.mktemp("tune") / f"{name}.json"
-        path.write_text('{"small_batch": %d}' % thr)
+        path.write_text(txt)
         out[name] = api.Context(0, tune_json=str(path))
     yield out
     for c in out.values():
@@ -109,17 +111,22 @@ def test_quantile_parity(api, ctxs, oracle, L, n, Q, levels, policy):
 @pytest.mark.parametrize("kind", ["clean", "raw"])
 @pytest.mark.parametrize("L,n,Q", GEOMS)
 def test_tables_fused_equals_staged(api, ctxs, L, n, Q, kind):
-    """Fused, staged and split launches give bitwise-equal tables."""
-    _, imgs = inputs(kind, L, 6, 300 + L)
+    """Fused (two images or one per block), staged and split launches give
+    bitwise-equal tables; an odd count leaves the last two-image block with
+    one image."""
+    _, imgs = inputs(kind, L, 7, 300 + L)
+    imgs[3, 2, 5] = np.nan  # a non-finite image beside a finite one in its block
     x = dev(imgs)
     ctx, cs = ctxs["perimage"], ctxs["split"]
     q1, a1 = api.tables(ctx, x, n, Q)
     q2, a2 = api.quantiles(ctx, api.project(ctx, x, n), Q)
     q3, a3 = api.tables(cs, x, n, Q)
     q4, a4 = api.quantiles(cs, api.project(ctx, x, n), Q)
-    for q, a in ((q2, a2), (q3, a3), (q4, a4)):
-        assert np.array_equal(q1.cpu().numpy(), q.cpu().numpy())
-        assert np.array_equal(a1.cpu().numpy(), a.cpu().numpy())
+    q5, a5 = api.tables(ctxs["one"], x, n, Q)
+    assert np.isnan(a1.cpu().numpy()[3, 0]) and not np.isnan(a1.cpu().numpy()[2, 0])
+    for q, a in ((q2, a2), (q3, a3), (q4, a4), (q5, a5)):
+        assert np.array_equal(q1.cpu().numpy(), q.cpu().numpy(), equal_nan=True)
+        assert np.array_equal(a1.cpu().numpy(), a.cpu().numpy(), equal_nan=True)
 
 
 def oracle_results(oracle, rq, ra, iq, ia, L, pairs=None, mode=0):
