@@ -384,28 +384,40 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
         const float2 dk = tw[k];
         const float *Uc = U + (int64_t)j0 * n + k;
         for (int c0 = 0; c0 < K; c0 += 2) {
-            const int c1 = c0 + 1 < K ? c0 + 1 : c0;
             const float *va = vl + ((k + cand[c0]) & (n - 1));
-            const float *vb = vl + ((k + cand[c1]) & (n - 1));
             const float sa = cs[c0].x * dk.x + cs[c0].y * dk.y;
-            const float sb = cs[c1].x * dk.x + cs[c1].y * dk.y;
-            float pa = 0.f, pb = 0.f;
+            float pa = 0.f;
+            if (c0 + 1 < K) {  // two candidates per pass (block-uniform)
+                const int c1 = c0 + 1;
+                const float *vb = vl + ((k + cand[c1]) & (n - 1));
+                const float sb = cs[c1].x * dk.x + cs[c1].y * dk.y;
+                float pb = 0.f;
 #pragma unroll 8
-            for (int jr = jt; jr < rows; jr += kRows) {
-                const float u = Uc[jr * n];
-                const float da = u - va[jr * n] - sa;
-                const float db = u - vb[jr * n] - sb;
-                pa += da * da;
-                pb += db * db;
-            }
+                for (int jr = jt; jr < rows; jr += kRows) {
+                    const float u = Uc[jr * n];
+                    const float da = u - va[jr * n] - sa;
+                    const float db = u - vb[jr * n] - sb;
+                    pa += da * da;
+                    pb += db * db;
+                }
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                pa += __shfl_xor(pa, off, 64);
-                pb += __shfl_xor(pb, off, 64);
-            }
-            if (lane == 0) {
-                red[wave][c0] += pa;
-                if (c0 + 1 < K) red[wave][c0 + 1] += pb;
+                for (int off = 32; off >= 1; off >>= 1) {
+                    pa += __shfl_xor(pa, off, 64);
+                    pb += __shfl_xor(pb, off, 64);
+                }
+                if (lane == 0) {
+                    red[wave][c0] += pa;
+                    red[wave][c1] += pb;
+                }
+            } else {  // the last candidate of an odd count alone
+#pragma unroll 8
+                for (int jr = jt; jr < rows; jr += kRows) {
+                    const float da = Uc[jr * n] - va[jr * n] - sa;
+                    pa += da * da;
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) pa += __shfl_xor(pa, off, 64);
+                if (lane == 0) red[wave][c0] += pa;
             }
         }
     }

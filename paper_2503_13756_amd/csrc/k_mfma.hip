@@ -25,17 +25,8 @@
 
 namespace sw {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ bf16x4_t as_bf16x4(uint32_t lo, uint32_t hi) {
-    bf16x4_t v;
-    v[0] = (short)(lo & 0xffffu);
-    v[1] = (short)(lo >> 16);
-    v[2] = (short)(hi & 0xffffu);
-    v[3] = (short)(hi >> 16);
-    return v;
-}
 
 // LDS writes of this wave visible to its other lanes (no block barrier).
 __device__ __forceinline__ void wave_lds_fence() {
@@ -66,31 +57,59 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
     const int64_t g0 = (int64_t)blockIdx.x * 16, r0 = (int64_t)blockIdx.y * 16;
     for (int i = threadIdx.x; i < N; i += 256) tw[i] = tw32[i];
 
+    // Spectral products on the gfx950 bf16 MFMA with 32 K entries (16
+    // complex values) per instruction: lane l holds row l % 16 (reference)
+    // or column l % 16 (image) and the complex values 16 s + 4 (l / 16) ..
+    // + 3 of K step s, one 16-byte load each.  The spectra of frequency
+    // w + 4 are fetched into registers while those of w are multiplied.
+    constexpr int KS = N / 16;  // K steps (Q == N on this path)
     const int q = lane >> 4;
     const int64_t ra = r0 + (lane & 15), gb = g0 + (lane & 15);
     const bool va = ra < n_ref, vb = gb < n_img;
-    const uint32_t *pa = spec_ref + (va ? ra : 0) * (int64_t)Wn * Q;
-    const uint32_t *pb = spec_img + (vb ? gb : 0) * (int64_t)Wn * Q;
-    for (int w = wave; w < Wn; w += 4) {
-        f32x4_t acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
-        const uint32_t *ar = pa + (int64_t)w * Q;
-        const uint32_t *br = pb + (int64_t)w * Q;
-        for (int s = 0; s < Q / 8; ++s) {
-            const int j = 8 * s + 2 * q;  // two complex values = four K entries
-            uint2 av = make_uint2(0u, 0u), bv = make_uint2(0u, 0u);
-            if (va) av = *(const uint2 *)(ar + j);
-            if (vb) bv = *(const uint2 *)(br + j);
-            const bf16x4_t A = as_bf16x4(av.x, av.y);
-            const bf16x4_t B = as_bf16x4(bv.x, bv.y);
-            const bf16x4_t Bi = as_bf16x4(times_minus_i(bv.x), times_minus_i(bv.y));
-            acc_re = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc_re, 0, 0, 0);
-            acc_im = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bi, acc_im, 0, 0, 0);
-        }
+    const uint4 *pa = (const uint4 *)(spec_ref + (va ? ra : 0) * (int64_t)Wn * Q) + q;
+    const uint4 *pb = (const uint4 *)(spec_img + (vb ? gb : 0) * (int64_t)Wn * Q) + q;
+    const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+    uint4 a_cur[KS], b_cur[KS], a_nxt[KS], b_nxt[KS];
+    auto fetch = [&](int w, uint4(&A)[KS], uint4(&B)[KS]) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int pr = (4 * q + v) * 16 + (lane & 15);  // tile pair: ref-major
-            Sl[pr * SS + 2 * w] = acc_re[v];
-            Sl[pr * SS + 2 * w + 1] = acc_im[v];
+        for (int s = 0; s < KS; ++s) {
+            A[s] = pa[(int64_t)w * (N / 4) + 4 * s];
+            B[s] = pb[(int64_t)w * (N / 4) + 4 * s];
+        }
+    };
+    // Fully unrolled over this wave's frequencies w = wave + 4 i: every fetch
+    // is issued (the one past the last frequency refetches it), so exactly
+    // one frequency's fetch is in flight while the previous one is
+    // multiplied.
+    constexpr int NI = (Wn + 3) / 4;
+    fetch(wave, a_cur, b_cur);  // wave < 4 < Wn
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int w = wave + 4 * i;
+        uint4(&A0)[KS] = (i & 1) ? a_nxt : a_cur;
+        uint4(&B0)[KS] = (i & 1) ? b_nxt : b_cur;
+        uint4(&A1)[KS] = (i & 1) ? a_cur : a_nxt;
+        uint4(&B1)[KS] = (i & 1) ? b_cur : b_nxt;
+        if (i + 1 < NI) fetch(min(w + 4, Wn - 1), A1, B1);
+        if (w < Wn) {  // wave-uniform
+            f32x4_t acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const uint4 av = va ? A0[s] : zero4, bv = vb ? B0[s] : zero4;
+                const uint4 bi = make_uint4(times_minus_i(bv.x), times_minus_i(bv.y),
+                                            times_minus_i(bv.z), times_minus_i(bv.w));
+                const bf16x8_t A = __builtin_bit_cast(bf16x8_t, av);
+                acc_re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    A, __builtin_bit_cast(bf16x8_t, bv), acc_re, 0, 0, 0);
+                acc_im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    A, __builtin_bit_cast(bf16x8_t, bi), acc_im, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int pr = (4 * q + v) * 16 + (lane & 15);  // tile pair: ref-major
+                Sl[pr * SS + 2 * w] = acc_re[v];
+                Sl[pr * SS + 2 * w + 1] = acc_im[v];
+            }
         }
     }
     __syncthreads();
