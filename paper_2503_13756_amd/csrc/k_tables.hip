@@ -65,7 +65,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     const float *F[2] = {img + g0 * (int64_t)L * L, img + (g0 + nimg - 1) * (int64_t)L * L};
     float acc[2][TPW][4];
     int bad[2];
-    project_images2<NT, TPW, 2>(F, nimg, P, d32, region, acc, bad);
+    project_images2<NT, TPW, 2>(F, nimg, P, d32, region, 0, acc, bad);
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
     for (int g = 0; g < 2; ++g) {

@@ -190,12 +190,13 @@ __device__ __forceinline__ void s4_accumulate(const LaneTask (&tasks)[TPW], int 
     }
 }
 
-// Projection of `nimg` <= IMG images (one task group: P.ntasks <= NW * TPW)
-// into the accumulators; lds holds IMG strip buffers of kImg2Bytes.  bad[g]
-// is set when image g holds a non-finite value.
+// Projection of `nimg` <= IMG images for the task group starting at task
+// tg0 (tasks tg0 + wave + t NW, t < TPW) into the accumulators; lds holds IMG
+// strip buffers of kImg2Bytes.  bad[g] is set when image g holds a
+// non-finite value.
 template <int NT, int TPW, int IMG>
 __device__ void project_images2(const float *const (&F)[IMG], int nimg, const ProjShape &P,
-                                const float2 *__restrict__ dtab, float *lds,
+                                const float2 *__restrict__ dtab, float *lds, int tg0,
                                 float (&acc)[IMG][TPW][4], int (&bad)[IMG]) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -206,12 +207,13 @@ __device__ void project_images2(const float *const (&F)[IMG], int nimg, const Pr
 #pragma unroll
         for (int t = 0; t < TPW; ++t) acc[g][t][0] = acc[g][t][1] = acc[g][t][2] = acc[g][t][3] = 0.f;
     }
-    const int mine = P.ntasks - wave;
+    const int mine = P.ntasks - tg0 - wave;
     const int my_tasks = mine > 0 ? min(TPW, (mine + NW - 1) / NW) : 0;
     LaneTask tasks[TPW];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) tasks[t] = make_task(P, dtab, wave + t * NW, lane);
+    for (int t = 0; t < TPW; ++t) tasks[t] = make_task(P, dtab, tg0 + wave + t * NW, lane);
     // the padding positions (and a missing image's strips) stay zero
+    __syncthreads();  // the caller may have used the region
     for (int q = threadIdx.x; q < IMG * kImg2Bytes / 16; q += NT)
         *(float4 *)(lds + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
     Strip4Regs<NT, IMG> xs;
