@@ -29,39 +29,67 @@ if ROOT not in sys.path:
 import synth  # noqa: E402
 
 METRIC = "alignments/s at L=128, plain FP32 vs served BF16 form; p50/p99 latency"
+LEGS = ("ramp", "msw", "fourier", "all_pairs", "uneven", "single", "serving", "serving_mixed")
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 
-# HBM traffic of the fused tables kernel on this workload, from two rocprofv3
-# counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a plain copy kernel; only
-# used while the kernel's sources are the ones the counters were taken on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tables_L128_10k_hbm.txt")
-TABLES_SOURCES = ["k_tables.hip", "proj_dev.h", "quant_dev.h", "sw_internal.h"]
+# Per-kernel figures from committed rocprofv3 summaries (profiles/): HBM
+# traffic from two counter passes (FETCH_SIZE, WRITE_SIZE) scaled by a plain
+# copy kernel, MFMA counters, kernel durations.  A kernel's figures are used
+# only while its sources hash to what the summary records.
+PROFILES = os.path.join(ROOT, "profiles")
+HBM_FILE = os.path.join(PROFILES, "hbm_traffic_L128_10k_and_all_pairs.txt")
+MFMA_FILE = os.path.join(PROFILES, "mfma_k_corr_mfma_all_pairs_2000.txt")
+STATS_FILE = os.path.join(PROFILES, "kernels_all_legs_stats.txt")
+KERNEL_SOURCES = {
+    "k_tables2": ["k_tables.hip", "proj2_dev.h", "proj_dev.h", "quant_dev.h", "sw_internal.h"],
+    "k_project": ["k_project.hip", "proj_dev.h", "sw_internal.h"],
+    "k_quantile": ["k_quantile.hip", "quant_dev.h", "sw_internal.h"],
+    "k_align128": ["k_align128.hip", "align128_dev.h", "align_dev.h", "sw_internal.h"],
+    "k_spectrum": ["k_align.hip", "align_dev.h", "sw_internal.h"],
+    "k_corr_mfma": ["k_mfma.hip", "sw_internal.h"],
+    "k_rescore_tiles": ["k_mfma.hip", "sw_internal.h"],
+}
 
 
-def tables_sources_sha256():
+def sources_sha256(kernel):
     import hashlib
 
     h = hashlib.sha256()
-    for name in TABLES_SOURCES:
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2503_13756_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """(bytes per launch, note) from the counter summary, or (None, why)."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None, "no counter summary"
-    kv = {}
-    with open(TRAFFIC_FILE) as f:
+def read_sections(path):
+    """{section: {key: value}} of a summary file ("[name]" headers, "key:
+    value" lines, "#" comments)."""
+    out, cur = {}, None
+    if not os.path.exists(path):
+        return out
+    with open(path) as f:
         for line in f:
-            if ":" in line and not line.startswith("#"):
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("[") and line.endswith("]"):
+                cur = out.setdefault(line[1:-1], {})
+            elif ":" in line and cur is not None:
                 k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    if kv.get("sources_sha256") != tables_sources_sha256():
+                cur[k.strip()] = v.strip()
+    return out
+
+
+def profile_figures(path, kernel):
+    """(figures, source note) of a kernel from a summary file, or (None, why)."""
+    sec = read_sections(path).get(kernel)
+    if sec is None:
+        return None, f"no summary for {kernel}"
+    if sec.get("sources_sha256") != sources_sha256(kernel):
         return None, "kernel changed since the counters were taken"
-    return float(kv["traffic_bytes_per_launch"]), os.path.relpath(TRAFFIC_FILE, ROOT)
+    return sec, os.path.relpath(path, ROOT)
 
 
 def log(msg):
@@ -89,6 +117,10 @@ def parse():
     p.add_argument("--out", default=None, help="also write the JSON line to this file")
     p.add_argument("--skip-extra", action="store_true",
                    help="only the 1-vs-10,000 workload (for profiling runs)")
+    p.add_argument("--leg", action="append", choices=LEGS, default=None,
+                   help="run only these further workloads (repeatable); default: all of them")
+    p.add_argument("--no-h2d", action="store_true",
+                   help="skip the host-resident (PCIe-inclusive) run of the headline workload")
     p.add_argument("--requests", type=int, default=2000, help="serving trace length (L = 128)")
     p.add_argument("--requests-mixed", type=int, default=2000,
                    help="serving trace length (L in {64, 128, 256})")
@@ -96,6 +128,9 @@ def parse():
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize":
+        summarize(sys.argv[2:])
+        return
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path "
@@ -209,8 +244,11 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
     if roof["kernel"] == "k_tables":
+        roof["kernel"] = "k_tables2"  # two images per block
         roof["algorithmic_bytes"] = bytes_tables
-        roof["traffic"], roof["traffic_source"] = measured_traffic()
+        fig, note = profile_figures(HBM_FILE, "k_tables2")
+        roof["traffic"] = float(fig["traffic_bytes"]) if fig else None
+        roof["traffic_source"] = note
 
     if args.copy_probe:
         # a plain elementwise kernel over 512 MiB (reads 512 MiB, writes
@@ -237,36 +275,46 @@ def main():
         "input_generation_s": t_gen,
     }
 
-    log("host-resident images: chunked copies overlapped with the path")
-    line["value_h2d"] = bench_h2d(api, ctx, torch, w, res32, L, n, Q)
+    if not args.no_h2d:
+        log("host-resident images: chunked copies overlapped with the path")
+        line["value_h2d"] = bench_h2d(api, ctx, torch, w, res32, L, n, Q)
 
+    legs = set(args.leg) if args.leg else (set() if args.skip_extra else set(LEGS))
     extra_res = {}
-    if not args.skip_extra:
+    if "ramp" in legs:
         log("ramp-filtered SW2")
         line["ramp_filtered"], extra_res["ramp"] = bench_ramp(api, ctx, torch, ref, imgs, L, n, Q,
                                                               ms32)
+    if "msw" in legs:
         log("max-sliced SW2")
         line["max_sliced"], extra_res["msw"] = bench_msw(api, ctx, torch, rq, ra, iq, ia, L,
                                                          seg32[0] + seg32[1])
+    if "fourier" in legs:
         log("Fourier-slice projector")
         line["fourier_slice"], extra_res["fourier"] = bench_fourier(api, ctx, torch, ref, imgs, pmf,
                                                                     L, n, Q, seg32[0] + seg32[1])
-        del pmf, iq, ia, res
-        torch.cuda.empty_cache()
+    del pmf, iq, ia, res
+    torch.cuda.empty_cache()
+    if "all_pairs" in legs:
         log("all pairs")
         line["all_pairs"], extra_res["all_pairs"] = bench_all_pairs(api, ctx, torch)
         torch.cuda.empty_cache()
+    if "uneven" in legs:
         log("uneven stacks")
         line["uneven_stacks"], extra_res["uneven"] = bench_uneven(api, ctx, torch)
         torch.cuda.empty_cache()
+    if "single" in legs:
         log("single pair")
         line["single_pair"] = single_pair(api, ctx, torch)
+    if "serving" in legs:
         log("serving trace")
         line["serving"] = bench_serving(api, torch, args.requests, budget=1 << 30)
         torch.cuda.empty_cache()
+    if "serving_mixed" in legs:
         log("serving trace, mixed L")
         line["serving_mixed_L"] = bench_serving(api, torch, args.requests_mixed, Ls=(64, 128, 256),
                                                 distinct=1000, budget=4 << 30)
+    line["stage_rooflines"] = stage_rooflines(line, N, L, n, Q)
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, res32, res16, L, n, Q)
@@ -291,6 +339,172 @@ def main():
         with open(args.out, "w") as f:
             f.write(s + "\n")
     ctx.close()
+
+
+def stage_rooflines(line, N, L, n, Q):
+    """Every stage of the headline path (and of the all-pairs path when that
+    leg ran) against the roofline that bounds it: achieved = algorithmic
+    bytes or flops per launch / the launch's duration, next to the measured
+    HBM traffic and MFMA counters of the committed rocprofv3 summaries.
+    Durations: HIP events of this run where a stage is one library call, else
+    the kernel-trace summary (named in `duration`)."""
+    st = line["stages_ms"]
+    M = disk_pixels(L)
+    out = []
+
+    def add(kernel, bound, work, ms, note, extra=None):
+        unit = {"hbm": "GB/s", "alu": "TFLOP/s", "mfma": "TFLOP/s"}[bound]
+        peak = {"hbm": PEAK_HBM_GBS, "alu": PEAK_FP32_TFLOPS, "mfma": PEAK_BF16_TFLOPS}[bound]
+        scale = 1e-9 if bound == "hbm" else 1e-12
+        ach = work / (ms * 1e-3) * scale
+        e = {"kernel": kernel, "bound": bound, "achieved": ach, "peak": peak, "unit": unit,
+             "frac": ach / peak, "ms": ms, "duration": note,
+             ("algorithmic_bytes" if bound == "hbm" else "algorithmic_flops"): work}
+        fig, src = profile_figures(HBM_FILE, kernel)
+        e["traffic"] = float(fig["traffic_bytes"]) if fig else None
+        e["traffic_source"] = src
+        if e["traffic"]:
+            e["traffic_gbs"] = e["traffic"] / (ms * 1e-3) * 1e-9
+            e["traffic_frac_of_hbm"] = e["traffic_gbs"] / PEAK_HBM_GBS
+        if extra:
+            e.update(extra)
+        out.append(e)
+
+    flops_proj = 4.0 * (n // 2) * M * N
+    add("k_tables2", "alu", flops_proj, st["tables_imgs_ms"], "HIP events (images -> tables)")
+    add("k_project", "alu", flops_proj, st["staged_project_ms"], "HIP events (staged projection)")
+    add("k_quantile", "hbm", (4.0 * n * L + 4.0 * Q * n + 32.0) * N, st["staged_quantiles_ms"],
+        "HIP events (staged quantiles)")
+    add("k_align128", "hbm", (4.0 * Q * n + 24.0) * N, st["align_ms"],
+        "HIP events (reference spectrum, coefficients and k_align128)")
+    ap = line.get("all_pairs")
+    if ap:
+        NA, LA = 2000, 64
+        P = NA * NA
+        stats = read_sections(STATS_FILE)
+        for kernel, bound, work in (
+                ("k_spectrum", "hbm", (4.0 * LA * LA + 4.0 * (LA // 2 + 1) * LA) * NA),
+                ("k_corr_mfma", "mfma", ap["mfma_flops_per_step"]),
+                ("k_rescore_tiles", "alu", 4 * 3.0 * LA * LA * P)):
+            fig, src = profile_figures(STATS_FILE, kernel)
+            if not fig:
+                out.append({"kernel": kernel, "bound": bound, "achieved": None, "note": src})
+                continue
+            extra = None
+            if kernel == "k_corr_mfma":
+                mf, msrc = profile_figures(MFMA_FILE, kernel)
+                extra = {"mfma_util_pct": float(mf["mfma_util_pct"]) if mf else None,
+                         "mfma_bf16_flops_counted": float(mf["mfma_bf16_flops"]) if mf else None,
+                         "mfma_source": msrc}
+            add(kernel, bound, work, float(fig["avg_us"]) * 1e-3, f"kernel trace ({src})", extra)
+        del stats
+    return out
+
+
+def summarize(argv):
+    """Summaries of rocprofv3 CSV output for profiles/ (text on stdout):
+      summarize hbm FETCH_DIR WRITE_DIR "command"  HBM bytes per dispatch of the
+          path's kernels, each counter scaled by what it reads for the plain
+          512 MiB elementwise kernel of --copy-probe (512 MiB read + written)
+      summarize mfma PMC_DIR "command"             MFMA counters of k_corr_mfma
+      summarize sq PMC_DIR[,PMC_DIR2] "command"    SQ counters of k_tables2
+      summarize stats TRACE_DIR "command"          kernel durations
+    Per kernel the dispatches with the largest grid are taken (the full
+    workloads), averaged; every section records the kernel's source hash."""
+    import csv
+    import glob
+
+    kind, rest = argv[0], argv[1:]
+
+    def counters(d):
+        rows = []
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += list(csv.DictReader(open(path)))
+        agg = {}
+        for r in rows:
+            key = (r["Kernel_Name"], int(r["Grid_Size"]))
+            a = agg.setdefault(key, {"dispatches": set()})
+            a["dispatches"].add(r["Dispatch_Id"])
+            a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        return agg
+
+    def pick(agg, pattern):
+        best = None
+        for (name, grid), a in agg.items():
+            if pattern in name and (best is None or grid > best[1]):
+                best = (name, grid, a)
+        return best
+
+    def per_dispatch(a, c):
+        return a[c] / len(a["dispatches"])
+
+    print(f"# rocprofv3 summary ({kind}); command(s): {rest[-1]}")
+    print("# values per dispatch (summed over the device by rocprofv3), averaged over the "
+          "dispatches of the largest grid of each kernel")
+    if kind == "hbm":
+        fa, wa = counters(rest[0]), counters(rest[1])
+        cf = pick(fa, "neg_kernel")
+        cw = pick(wa, "neg_kernel")
+        ff = (512 << 10) / per_dispatch(cf[2], "FETCH_SIZE")   # KiB read by the copy
+        wf = (512 << 10) / per_dispatch(cw[2], "WRITE_SIZE")   # KiB written
+        print(f"[calibration]\ncopy_kernel: {cf[0][:80]}\nfetch_factor: {ff:.4f}\n"
+              f"write_factor: {wf:.4f}")
+        for k in KERNEL_SOURCES:
+            f, w = pick(fa, f"sw::{k}<"), pick(wa, f"sw::{k}<")
+            if not f or not w:
+                continue
+            fk, wk = per_dispatch(f[2], "FETCH_SIZE"), per_dispatch(w[2], "WRITE_SIZE")
+            print(f"[{k}]\nkernel: {f[0][:100]}\ngrid: {f[1]}\ndispatches: {len(f[2]['dispatches'])}\n"
+                  f"fetch_kib: {fk:.1f}\nwrite_kib: {wk:.1f}\n"
+                  f"traffic_bytes: {1024 * (fk * ff + wk * wf):.0f}\n"
+                  f"sources_sha256: {sources_sha256(k)}")
+    elif kind in ("mfma", "sq"):
+        aggs = [counters(d) for d in rest[0].split(",")]
+        k = "k_corr_mfma" if kind == "mfma" else "k_tables2"
+        print(f"[{k}]")
+        for agg in aggs:
+            b = pick(agg, f"sw::{k}<")
+            print(f"kernel: {b[0][:100]}\ngrid: {b[1]}\ndispatches: {len(b[2]['dispatches'])}")
+            for c in sorted(x for x in b[2] if x != "dispatches"):
+                print(f"{c}: {per_dispatch(b[2], c):.1f}")
+            if kind == "mfma" and "SQ_INSTS_VALU_MFMA_MOPS_BF16" in b[2]:
+                print(f"mfma_bf16_flops: {512 * per_dispatch(b[2], 'SQ_INSTS_VALU_MFMA_MOPS_BF16'):.0f}")
+                print(f"mfma_f32_flops: {512 * per_dispatch(b[2], 'SQ_INSTS_VALU_MFMA_MOPS_F32'):.0f}")
+                # busy cycles of all 1024 SIMDs over the active cycles of one XCD
+                # (GRBM_GUI_ACTIVE comes summed over the 8 XCDs)
+                busy = per_dispatch(b[2], "SQ_VALU_MFMA_BUSY_CYCLES")
+                active = per_dispatch(b[2], "GRBM_GUI_ACTIVE") / 8
+                print(f"mfma_util_pct: {100 * busy / (active * 1024):.1f}")
+            if kind == "sq" and "SQ_INSTS_VALU" in b[2]:
+                imgs = b[1] // 512 * 2  # two images per 512-thread block
+                print(f"valu_wave_instructions_per_image: {per_dispatch(b[2], 'SQ_INSTS_VALU') / imgs:.0f}")
+            if "SQ_LDS_BANK_CONFLICT" in b[2]:
+                print("lds_bank_conflict_share_of_lds_active: "
+                      f"{b[2]['SQ_LDS_BANK_CONFLICT'] / b[2]['SQ_LDS_IDX_ACTIVE']:.3f}")
+        print(f"sources_sha256: {sources_sha256(k)}")
+    elif kind == "stats":
+        rows = []
+        for path in glob.glob(os.path.join(rest[0], "**", "*kernel_trace.csv"), recursive=True):
+            rows += list(csv.DictReader(open(path)))
+        by = {}
+        for r in rows:
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            by.setdefault(r["Kernel_Name"], []).append((grid, d))
+        tot = sum(d for v in by.values() for _, d in v)
+        print(f"{'kernel':88s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}")
+        for name, v in sorted(by.items(), key=lambda kv: -sum(d for _, d in kv[1]))[:40]:
+            ds = [d for _, d in v]
+            print(f"{name[:88]:88s} {len(ds):6d} {sum(ds) / len(ds):10.2f} {min(ds):10.2f} "
+                  f"{max(ds):10.2f} {100 * sum(ds) / tot:6.2f}")
+        for k in KERNEL_SOURCES:
+            cand = [(n_, v) for n_, v in by.items() if f"sw::{k}<" in n_]
+            if not cand:
+                continue
+            gmax = max(g for _, v in cand for g, _ in v)
+            ds = [d for _, v in cand for g, d in v if g == gmax]
+            print(f"[{k}]\ngrid: {gmax}\ncalls: {len(ds)}\navg_us: {sum(ds) / len(ds):.2f}\n"
+                  f"sources_sha256: {sources_sha256(k)}")
 
 
 def timed(torch, fn, K, W=1):
