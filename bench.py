@@ -856,7 +856,7 @@ def all_pairs_error(w, g, L, S=1000):
     return out
 
 
-def bench_uneven(api, ctx, torch, total=50000, distinct=64):
+def bench_uneven(api, ctx, torch, total=50000, distinct=200):
     """Stacks of L in {64, 96, 128, 192, 256} with sizes drawn uniformly in
     [100, 5000] until 50,000 images, each with its own reference, through the
     mixed persistent launches.  Each stack holds `distinct` rendered copies of
@@ -867,9 +867,13 @@ def bench_uneven(api, ctx, torch, total=50000, distinct=64):
         x = torch.from_numpy(imgs).cuda()
         reps = (size + len(imgs) - 1) // len(imgs)
         dev.append((torch.from_numpy(ref).cuda(), x.repeat(reps, 1, 1)[:size].contiguous()))
-    # strip-row tile per L, measured once on this device (a plan step, untimed)
+    # launch tiles per L (strip rows, tasks per wave, alignment blocks per CU),
+    # measured once on this device (a plan step, untimed)
+    import tempfile
+
     t0 = time.perf_counter()
-    api.autotune(ctx, sorted({s[0] for s in stacks}))
+    tiles_path = os.path.join(tempfile.mkdtemp(), "tiles.json")
+    api.autotune(ctx, sorted({s[0] for s in stacks}), out_json=tiles_path)
     t_tune = time.perf_counter() - t0
     ms = timed(torch, lambda: api.align_stacks(ctx, dev, prec=1), 3)
     outs = api.align_stacks(ctx, dev, prec=1)
@@ -885,12 +889,12 @@ def bench_uneven(api, ctx, torch, total=50000, distinct=64):
     return ({"workload": f"{len(stacks)} stacks, {n} images, L in {{64,96,128,192,256}}, sizes "
                          "U[100,5000], own reference each, FP32 tables, bf16 correlation, top-4 "
                          "FP32 rescore, strip tiles autotuned per L", "images": n, "ms_per_step": ms,
-             "autotune_s": t_tune,
+             "autotune_s": t_tune, "tiles": json.load(open(tiles_path))["tiles"],
              "value": n / (ms * 1e-3), "unit": "alignments/s", "per_L": per_L},
             (stacks, res))
 
 
-def uneven_parity(stacks, res, S=50):
+def uneven_parity(stacks, res, S=200):
     """GPU results of the uneven stacks against the FP64 oracle on the first
     S images of every stack (the distinct rendered copies)."""
     from oracle import oracle as O

@@ -311,10 +311,17 @@ sw_status sw_align_stacks(void *ctx, const sw_stack *stacks /*host*/, int32_t n_
                           int32_t mode, int32_t prec, int32_t top_k, void *stream);
 
 /* Autotuner: for each side L in Ls (geometry n = Q = L), times the mixed
-   pipeline on n_images synthetic images for every admissible projection
-   strip height and keeps the fastest.  The table is kept in the context and,
-   when out_json is given, written there as {"tiles": {"L": {"R": rows}}};
-   pass that file to sw_ctx_create to reuse it.  Synchronises the device. */
+   pipeline on n_images synthetic images and picks, one after the other, the
+   projection strip height, the tables kernel's tasks per wave (5 or 6: the
+   number of task groups an image is restaged for) and the blocks per
+   compute unit of the per-pair alignment kernel (2, 4, 6 or 8), each the
+   fastest given the ones before.  None of them changes a result.  The table
+   is kept in the context and, when out_json is given, written there as
+   {"tiles": {"L": {"R": rows, "tpw": tasks, "align_bpc": blocks, "ms": t}}}
+   (tpw and align_bpc only when they differ from the defaults); pass that
+   file to sw_ctx_create to reuse it.  A mixed launch of several L takes the
+   tasks per wave and alignment blocks of its L with the most projection
+   work.  Synchronises the device. */
 sw_status sw_autotune(void *ctx, const int32_t *Ls /*host*/, int32_t nL, int64_t n_images,
                       const char *out_json /*host, nullable*/);
 

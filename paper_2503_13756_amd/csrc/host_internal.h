@@ -42,7 +42,27 @@ struct Ctx {
     // slice-point tables for explicit angles: (L, n, the angles' bytes) -> table
     std::map<std::string, void *> fourier_dir_targets;
     std::map<std::string, sw::AngleTable> fourier_dir_angles;  // their direction tables
-    std::map<int, int> tile_R;  // projection strip rows per L (autotuner)
+    std::map<int, int> tile_R;     // projection strip rows per L (autotuner)
+    std::map<int, int> tile_tpw;   // tables kernel tasks per wave per L (autotuner)
+    std::map<int, int> tile_abpc;  // alignment blocks per compute unit per L (autotuner)
+    // the launch knobs of a mixed launch: those tuned for the L with the most
+    // projection work (images x L^3) among the given (L, images) pairs
+    sw::MixKnobs knobs_for(const std::vector<std::pair<int, int64_t>> &items) const {
+        sw::MixKnobs k;
+        int best = -1;
+        double work = -1.0;
+        for (auto &it : items) {
+            const double w = (double)it.second * it.first * it.first * it.first;
+            if (w > work) {
+                work = w;
+                best = it.first;
+            }
+        }
+        auto a = tile_tpw.find(best), b = tile_abpc.find(best);
+        if (a != tile_tpw.end()) k.tpw = a->second;
+        if (b != tile_abpc.end()) k.align_bpc = b->second;
+        return k;
+    }
     // batches of fewer images take the split (many blocks per image) launches;
     // -1: the number of compute units
     int small_batch = -1;

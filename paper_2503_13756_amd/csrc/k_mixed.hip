@@ -191,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_align_mixed(const MixGroup *__restrict__
 
 // LDS and scratch needs of a set of items; fills the per-item tile fields
 // (fused, TC) and returns the launch parameters.
-MixLaunch plan_mixed(MixItem *items, int nitems) {
+MixLaunch plan_mixed(MixItem *items, int nitems, MixKnobs knobs) {
     constexpr int NT = 256;                         // align kernels
     constexpr int NTT = kMixTablesThreads, TPW = kMixTablesTasks;  // tables kernel
     MixLaunch m{};
@@ -236,6 +236,17 @@ MixLaunch plan_mixed(MixItem *items, int nitems) {
         it.TC = pick_tc(it.n, it.Q, budget - fixed);
         qmax = max(qmax, it.Q * (it.TC + 1));
     }
+    // tables kernel instance: both handle any item (more task groups with
+    // fewer tasks per wave); the knob overrides the smallest-that-fits rule
+    if (knobs.tpw == kMixTablesTasksSmall || knobs.tpw == TPW) {
+        // the region must still hold the fused PMFs: fused needs one group
+        bool ok = true;
+        for (int i = 0; i < nitems; ++i)
+            if (items[i].fused && proj_ntasks(items[i].L, items[i].n) > (NTT / 64) * knobs.tpw)
+                ok = false;
+        if (ok) m.tpw = knobs.tpw;
+    }
+    m.align_bpc = knobs.align_bpc >= 1 && knobs.align_bpc <= 8 ? knobs.align_bpc : 8;
     m.region_floats = region;
     m.lmax = lmax;
     m.nmax = nmax;
@@ -285,9 +296,10 @@ hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const Mi
     // four 40 KiB blocks of the register-FFT kernel per compute unit
     hipLaunchKernelGGL((k_align128_mixed<NT>), dim3((unsigned)(2 * grid)), dim3(NT), 0, s, d_imgs,
                        counters + 3);
-    // small LDS tiles: four blocks of the LDS-FFT kernel per compute unit
-    hipLaunchKernelGGL((k_align_mixed<NT>), dim3((unsigned)(4 * grid)), dim3(NT), m.align_lds, s,
-                       d_imgs, counters + 2);
+    // small LDS tiles: several blocks of the LDS-FFT kernel per compute unit
+    // (grid = 2 blocks per compute unit; align_bpc per compute unit here)
+    hipLaunchKernelGGL((k_align_mixed<NT>), dim3((unsigned)(m.align_bpc * (grid / 2))), dim3(NT),
+                       m.align_lds, s, d_imgs, counters + 2);
     return hipGetLastError();
 }
 

@@ -49,9 +49,16 @@ struct MixLaunch {
     size_t tables_lds;
     int64_t slot_floats;
     size_t align_lds;
+    int align_bpc;  // blocks per compute unit of the per-pair (LDS-FFT) alignment kernel
 };
-// Fills the per-item tile fields (R clamped, TC, fused) and the launch sizes.
-MixLaunch plan_mixed(MixItem *items, int nitems);
+// Launch knobs of the autotuner (0: the default); none changes a result.
+struct MixKnobs {
+    int tpw = 0;        // kMixTablesTasksSmall or kMixTablesTasks
+    int align_bpc = 0;  // 1 .. 8
+};
+// Fills the per-item tile fields (R clamped, TC, fused) and the launch sizes;
+// knobs, when set, choose the tables kernel instance and the alignment grid.
+MixLaunch plan_mixed(MixItem *items, int nitems, MixKnobs knobs = MixKnobs());
 // Reference tables and spectra (group d_refs) and image tables (group d_imgs)
 // from one work queue, spectra of cached references, alignment (group
 // d_imgs).  counters: 4 device words; scratch: grid * slot_floats floats.

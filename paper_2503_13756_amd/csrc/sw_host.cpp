@@ -580,9 +580,10 @@ hipEvent_t ring_event(Ctx *c, sw::MixGroup *host) {
 }
 
 // Align up to kMaxMix stacks in one set of mixed launches.  Stacks must be
-// validated.  R_override > 0 forces the projection strip rows (autotuner).
+// validated.  R_override > 0 forces the projection strip rows, and knobs (if
+// given) the launch knobs (autotuner); otherwise the context's tuned values.
 sw_status run_stack_chunk(Ctx *c, const sw_stack *const *st, int n, int mode, int bf16, int top_k,
-                          int R_override, hipStream_t s) {
+                          int R_override, hipStream_t s, const sw::MixKnobs *knobs = nullptr) {
     sw::MixGroup *hg;
     sw_status stt = ring_slot(c, &hg);
     if (stt != SW_OK) return stt;
@@ -649,7 +650,9 @@ sw_status run_stack_chunk(Ctx *c, const sw_stack *const *st, int n, int mode, in
     gi.total = first;
     gr.split = 0;
     gi.split = split;
-    sw::MixLaunch m = sw::plan_mixed(gi.items, n);
+    std::vector<std::pair<int, int64_t>> sizes;
+    for (int i = 0; i < n; ++i) sizes.emplace_back(gi.items[i].L, gi.items[i].count);
+    sw::MixLaunch m = sw::plan_mixed(gi.items, n, knobs ? *knobs : c->knobs_for(sizes));
     for (int i = 0; i < n; ++i) {
         gr.items[i].R = gi.items[i].R;
         gr.items[i].TC = gi.items[i].TC;
@@ -741,10 +744,17 @@ sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
         std::stringstream ss;
         ss << f.rdbuf();
         const std::string txt = ss.str();
-        const std::regex re("\"(\\d+)\"\\s*:\\s*\\{\\s*\"R\"\\s*:\\s*(\\d+)");
+        // "L": {"R": rows[, "tpw": tasks][, "align_bpc": blocks] ...}
+        const std::regex re("\"(\\d+)\"\\s*:\\s*\\{\\s*\"R\"\\s*:\\s*(\\d+)"
+                            "(\\s*,\\s*\"tpw\"\\s*:\\s*(\\d+))?"
+                            "(\\s*,\\s*\"align_bpc\"\\s*:\\s*(\\d+))?");
         for (auto it = std::sregex_iterator(txt.begin(), txt.end(), re); it != std::sregex_iterator();
-             ++it)
-            c->tile_R[std::stoi((*it)[1])] = std::stoi((*it)[2]);
+             ++it) {
+            const int L = std::stoi((*it)[1]);
+            c->tile_R[L] = std::stoi((*it)[2]);
+            if ((*it)[4].matched) c->tile_tpw[L] = std::stoi((*it)[4]);
+            if ((*it)[6].matched) c->tile_abpc[L] = std::stoi((*it)[6]);
+        }
         std::smatch m;
         if (std::regex_search(txt, m, std::regex("\"small_batch\"\\s*:\\s*(\\d+)")))
             c->small_batch = std::stoi(m[1]);
@@ -1308,7 +1318,7 @@ sw_status sw_autotune(void *ctx, const int32_t *Ls, int32_t nL, int64_t n_images
     Ctx *c = as_ctx(ctx);
     DeviceGuard dg(c->device);
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-    std::map<int, int> best_R;
+    std::map<int, int> best_R, best_tpw, best_bpc;  // 0: the default
     std::map<int, float> best_ms;
     for (int li = 0; li < nL; ++li) {
         const int L = Ls[li];
@@ -1332,29 +1342,68 @@ sw_status sw_autotune(void *ctx, const int32_t *Ls, int32_t nL, int64_t n_images
         if (e == hipSuccess) e = sw::launch_fill_synthetic(img, (int64_t)nimg, nullptr);
         sw_stack k{img, img, (int64_t)n_images, g, rqt, raux, qt, aux, out};
         const sw_stack *kp = &k;
-        const int Rmax = std::min(L, sw::strip_rows_max(L));
-        const int cands[] = {2, 4, 6, 8, 12, 16, 24, 32, 0};  // 0: the largest that fits
-        for (int R : cands) {
-            if (e != hipSuccess) break;
-            if (R == 0) R = Rmax;
-            else if (R >= Rmax) continue;
+        // time one configuration: best of three runs after a warm-up
+        auto measure = [&](int R, const sw::MixKnobs &kn) -> float {
             float tbest = 1e30f;
             for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
                 e = hipEventRecord(e0, nullptr);
                 if (e == hipSuccess) {
-                    st = run_stack_chunk(c, &kp, 1, SW_MODE_ROT_TRANS, 0, 1, R, nullptr);
+                    st = run_stack_chunk(c, &kp, 1, SW_MODE_ROT_TRANS, 0, 1, R, nullptr, &kn);
                     if (st != SW_OK) e = hipErrorUnknown;
                 }
                 if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.f;
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (rep > 0 && ms < tbest) tbest = ms;  // first run warms up
+                if (rep > 0 && ms < tbest) tbest = ms;  // the first run warms up
             }
-            if (e == hipSuccess && (best_R.find(L) == best_R.end() || tbest < best_ms[L])) {
-                best_R[L] = R;
-                best_ms[L] = tbest;
+            return tbest;
+        };
+        // coordinate descent: strip rows, then tasks per wave of the tables
+        // kernel, then blocks per compute unit of the per-pair alignment
+        sw::MixKnobs kn;
+        const int Rmax = std::min(L, sw::strip_rows_max(L));
+        int bR = 0;
+        float bms = 1e30f;
+        const int cands[] = {2, 4, 6, 8, 12, 16, 24, 32, 0};  // 0: the largest that fits
+        for (int R : cands) {
+            if (e != hipSuccess) break;
+            if (R == 0) R = Rmax;
+            else if (R >= Rmax) continue;
+            const float ms = measure(R, kn);
+            if (e == hipSuccess && ms < bms) {
+                bms = ms;
+                bR = R;
             }
+        }
+        int btpw = 0;
+        for (int tpw : {sw::kMixTablesTasksSmall, sw::kMixTablesTasks}) {
+            if (e != hipSuccess) break;
+            sw::MixKnobs k2 = kn;
+            k2.tpw = tpw;
+            const float ms = measure(bR, k2);
+            if (e == hipSuccess && ms < bms) {
+                bms = ms;
+                btpw = tpw;
+            }
+        }
+        kn.tpw = btpw;
+        int bbpc = 0;
+        for (int bpc : {2, 4, 6, 8}) {
+            if (e != hipSuccess) break;
+            sw::MixKnobs k2 = kn;
+            k2.align_bpc = bpc;
+            const float ms = measure(bR, k2);
+            if (e == hipSuccess && ms < bms) {
+                bms = ms;
+                bbpc = bpc;
+            }
+        }
+        if (e == hipSuccess) {
+            best_R[L] = bR;
+            best_ms[L] = bms;
+            best_tpw[L] = btpw;
+            best_bpc[L] = bbpc;
         }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
@@ -1366,15 +1415,25 @@ sw_status sw_autotune(void *ctx, const int32_t *Ls, int32_t nL, int64_t n_images
         (void)hipFree(out);
         if (e != hipSuccess) return hip_fail(e, "autotune run");
     }
-    for (auto &kv : best_R) c->tile_R[kv.first] = kv.second;
+    for (auto &kv : best_R) {
+        const int L = kv.first;
+        c->tile_R[L] = kv.second;
+        if (best_tpw[L]) c->tile_tpw[L] = best_tpw[L];
+        else c->tile_tpw.erase(L);
+        if (best_bpc[L]) c->tile_abpc[L] = best_bpc[L];
+        else c->tile_abpc.erase(L);
+    }
     if (out_json && *out_json) {
         std::ofstream f(out_json);
         if (!f) return fail(SW_E_INVALID, "cannot write %s", out_json);
         f << "{\"tiles\": {";
         bool firstk = true;
         for (auto &kv : best_R) {
-            f << (firstk ? "" : ", ") << "\"" << kv.first << "\": {\"R\": " << kv.second
-              << ", \"ms\": " << best_ms[kv.first] << ", \"images\": " << n_images << "}";
+            const int L = kv.first;
+            f << (firstk ? "" : ", ") << "\"" << L << "\": {\"R\": " << kv.second;
+            if (best_tpw[L]) f << ", \"tpw\": " << best_tpw[L];
+            if (best_bpc[L]) f << ", \"align_bpc\": " << best_bpc[L];
+            f << ", \"ms\": " << best_ms[L] << ", \"images\": " << n_images << "}";
             firstk = false;
         }
         f << "}}\n";

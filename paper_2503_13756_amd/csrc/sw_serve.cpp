@@ -467,7 +467,7 @@ hipError_t issue_step(Server *s, const std::vector<Req *> &rs, hipEvent_t done) 
     gi.total = first;
     gr.split = 0;
     gi.split = fast ? first : 0;
-    sw::MixLaunch m = sw::plan_mixed(gi.items, gi.nitems);
+    sw::MixLaunch m = sw::plan_mixed(gi.items, gi.nitems, c->knobs_for({{g.L, first}}));
     for (int i = 0; i < gr.nitems; ++i) {
         gr.items[i].R = gi.items[0].R;
         gr.items[i].TC = gi.items[0].TC;
@@ -496,7 +496,7 @@ hipError_t issue_step(Server *s, const std::vector<Req *> &rs, hipEvent_t done) 
     if (s->cfg.use_graphs) {
         const std::vector<int> key{g.L, g.n, g.Q, g.levels, gi.items[0].R, gi.items[0].TC,
                                    gi.items[0].fused, (int)mm.tables_lds, (int)mm.align_lds,
-                                   mm.region_floats, mm.lmax, mm.nmax, mm.tpw};
+                                   mm.region_floats, mm.lmax, mm.nmax, mm.tpw, mm.align_bpc};
         auto it = s->graphs.find(key);
         if (it == s->graphs.end()) {
             sw::prepare_mixed();

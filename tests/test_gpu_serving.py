@@ -93,6 +93,7 @@ def test_autotune_table_roundtrip(api, ctx, tmp_path):
     assert set(tiles) == {"64", "128"}
     for L, v in tiles.items():
         assert 1 <= v["R"] <= int(L) and v["ms"] > 0
+        assert v.get("tpw", 5) in (5, 6) and v.get("align_bpc", 8) in (2, 4, 6, 8)
     c2 = api.Context(0, tune_json=path)
     data = [stack(L, N, 2300 + i) for i, (L, N) in enumerate(SIDES[:3])]
     a = api.align_stacks(c2, [(dev(r), dev(x)) for r, x in data])
@@ -109,23 +110,29 @@ def strip_rows_max(L):
     return min(L, 8192 // (4 * ((L + 4) | 1)))
 
 
-def test_strip_height_never_changes_results(api, ctx, tmp_path):
+def test_tiles_never_change_results(api, ctx, tmp_path):
     """Every admissible strip height of the mixed launches gives bitwise the
-    results and tables of the default: a row's line position depends on its
-    image row only, never on where a strip starts."""
+    results and tables of the default (a row's line position depends on its
+    image row only, never on where a strip starts), and so do both tasks-per-
+    wave instances of the tables kernel (more or fewer task groups) and every
+    alignment grid."""
     data = [stack(L, N, 2350 + i) for i, (L, N) in enumerate([(64, 5), (128, 6), (256, 3),
                                                              (96, 4)])]
     base = api.align_stacks(ctx, [(dev(r), dev(x)) for r, x in data])
-    for L in (64, 96, 128, 256):
-        for R in range(1, strip_rows_max(L) + 1):
-            path = tmp_path / f"t{L}_{R}.json"
-            path.write_text('{"tiles": {"%d": {"R": %d}}}' % (L, R))
-            c = api.Context(0, tune_json=str(path))
-            got = api.align_stacks(c, [(dev(r), dev(x)) for r, x in data])
-            c.close()
-            for a, b in zip(got, base):
-                assert np.array_equal(a["qt"].cpu().numpy(), b["qt"].cpu().numpy()), (L, R)
-                assert np.array_equal(a["res"].cpu().numpy(), b["res"].cpu().numpy()), (L, R)
+    cases = [(L, R, 0, 0) for L in (64, 96, 128, 256) for R in range(1, strip_rows_max(L) + 1)]
+    # the other knobs: tables tasks per wave and alignment blocks per CU
+    # (the launch takes them from its L with the most projection work: 256)
+    cases += [(256, 0, tpw, bpc) for tpw in (5, 6) for bpc in (1, 2, 4, 6, 8)]
+    for L, R, tpw, bpc in cases:
+        path = tmp_path / f"t{L}_{R}_{tpw}_{bpc}.json"
+        extra = (f', "tpw": {tpw}' if tpw else "") + (f', "align_bpc": {bpc}' if bpc else "")
+        path.write_text('{"tiles": {"%d": {"R": %d%s}}}' % (L, R or strip_rows_max(L), extra))
+        c = api.Context(0, tune_json=str(path))
+        got = api.align_stacks(c, [(dev(r), dev(x)) for r, x in data])
+        c.close()
+        for a, b in zip(got, base):
+            assert np.array_equal(a["qt"].cpu().numpy(), b["qt"].cpu().numpy()), (L, R, tpw, bpc)
+            assert np.array_equal(a["res"].cpu().numpy(), b["res"].cpu().numpy()), (L, R, tpw, bpc)
 
 
 # ---------------------------------------------------------------- serving
