@@ -47,8 +47,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
 // stay in registers until the strips are done; then each image in turn
 // writes its PMF table into the region and inverts it.  Results are bitwise
 // those of k_tables.  Only for geometries with one task group of at most six
-// tasks per wave.
-template <int NT, int TPW>
+// tasks per wave.  QM: the column inversion compiled (quant_mode_for(L)); the
+// second image's projections are live across the first image's phase.
+template <int NT, int TPW, int QM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_tables2(
     const float *__restrict__ img, int64_t N, TablesShape T, const float2 *__restrict__ d32,
     const double2 *__restrict__ d64, float *__restrict__ qt, double *__restrict__ aux) {
@@ -77,8 +78,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
             else
                 for (int t = threadIdx.x; t < n * L; t += NT) region[t] = __int_as_float(0x7fc00000);
             __syncthreads();
-            quantile_phase<NT>([&](int k, int b) { return region[k * L + b]; }, L, n, Q, T.levels,
-                               T.TC, d64, Ut, colS, qt + (g0 + g) * (int64_t)Q * n,
+            quantile_phase<NT, QM>([&](int k, int b) { return region[k * L + b]; }, L, n, Q,
+                                   T.levels, T.TC, d64, Ut, colS, qt + (g0 + g) * (int64_t)Q * n,
                                aux ? aux + 4 * (g0 + g) : nullptr);
         }
     }
@@ -205,15 +206,24 @@ static hipError_t launch_tables_t(const float *img, int64_t N, const TablesShape
     return hipGetLastError();
 }
 
+template <int NT, int TPW, int QM>
+static hipError_t launch_tables2_q(const float *img, int64_t N, const TablesShape &T, size_t lds,
+                                   const AngleTable &t, float *qt, double *aux, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute((const void *)k_tables2<NT, TPW, QM>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       152 * 1024);
+    (void)attr;
+    hipLaunchKernelGGL((k_tables2<NT, TPW, QM>), dim3((unsigned)((N + 1) / 2)), dim3(NT), lds, s,
+                       img, N, T, t.d32, t.d64, qt, aux);
+    return hipGetLastError();
+}
+
 template <int NT, int TPW>
 static hipError_t launch_tables2_t(const float *img, int64_t N, const TablesShape &T, size_t lds,
                                    const AngleTable &t, float *qt, double *aux, hipStream_t s) {
-    static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)k_tables2<NT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
-    (void)attr;
-    hipLaunchKernelGGL((k_tables2<NT, TPW>), dim3((unsigned)((N + 1) / 2)), dim3(NT), lds, s, img,
-                       N, T, t.d32, t.d64, qt, aux);
-    return hipGetLastError();
+    if (quant_mode_for(T.P.L) == kQuantHalf)
+        return launch_tables2_q<NT, TPW, kQuantHalf>(img, N, T, lds, t, qt, aux, s);
+    return launch_tables2_q<NT, TPW, kQuantWave>(img, N, T, lds, t, qt, aux, s);
 }
 
 hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t,

@@ -2,11 +2,12 @@
 // then the inverse CDF by linear interpolation; generalised inverse
 // inf{t : F(t) >= z} of App. A).
 //
-// One block per image, one wave per column at a time.  A column of L <= 256
-// bins is held as up to four values per lane; the mass and the cumulative
-// sums are accumulated in FP64 (lane-local sums, then a wave-wide DPP scan of
-// the lane totals), so each lane holds the normalised CDF at the right edges
-// of its own bins.  Levels are then assigned from the bins' side rather than
+// One block per image.  A column is inverted by half a wave (32 lanes, two
+// columns per wave at a time) for L <= 128 and by a whole wave for larger L,
+// so a lane holds at most four bins.  The mass and the cumulative sums are
+// accumulated in FP64 (lane-local sums, then a DPP scan of the lane totals
+// across the half or the wave), so each lane holds the normalised CDF at the
+// right edges of its own bins.  Levels are then assigned from the bins' side rather than
 // searched for: level z_j falls in the first bin whose right-edge CDF reaches
 // it, so a lane counts the levels at or below each of its edges and
 // interpolates the levels in between.  Quantiles
@@ -56,6 +57,37 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return read_lane_d(wave_inclusive_scan_d(v), 63);
 }
 
+// Inclusive scan within each half (lanes 0-31, 32-63) of the wave: shifts
+// by 1, 2, 4, 8 inside each row of 16 lanes, then the first row's total of
+// each half carried into its second row.  Fixed order, deterministic.
+__device__ __forceinline__ double half_inclusive_scan_d(double v) {
+    v += dpp_d<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_d<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_d<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_d<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    return v;
+}
+
+// Lane hl of this lane's group (the half `half` of the wave, or the wave).
+template <bool HALF>
+__device__ __forceinline__ double read_group_lane_d(double v, int hl, int half) {
+    if (!HALF) return read_lane_d(v, hl);
+    const double a = read_lane_d(v, hl), b = read_lane_d(v, 32 + hl);
+    return half ? b : a;
+}
+
+template <bool HALF>
+__device__ __forceinline__ double group_inclusive_scan_d(double v) {
+    return HALF ? half_inclusive_scan_d(v) : wave_inclusive_scan_d(v);
+}
+
+// Sum over this lane's group (same value on the group's lanes).
+template <bool HALF>
+__device__ __forceinline__ double group_sum_d(double v, int half) {
+    return read_group_lane_d<HALF>(group_inclusive_scan_d<HALF>(v), HALF ? 31 : 63, half);
+}
+
 // Number of levels z_j <= c, for z_j = (j + 1/2)/Q (midpoint) or j/Q
 // (left): floor(c Q + 1/2) or floor(c Q) + 1, clamped to [0, Q].  Monotone
 // in c, so the counts at consecutive bin edges partition the levels; a level
@@ -74,24 +106,27 @@ __device__ __forceinline__ double div_by(double h, double den) {
     return h * r;
 }
 
-// Invert one column, M bins per lane (M = ceil(L / 64)).  `col` reads bin b
-// of the column (FP32).  Writes the quantile of every level j into
-// Ut[j * ldt + kl] and returns the lane's partial (sum of quantiles, sum of
-// squares) in *su, *sq, and the column mass (same value on all lanes).
-template <int M, typename ColFn>
+// Invert one column with a group of G lanes (G = 32: the half `half` of the
+// wave; G = 64: the whole wave), M = ceil(L / G) bins per lane; lane hl of
+// the group holds bins hl M .. hl M + M - 1.  `col` reads bin b of the column
+// (FP32).  Writes the quantile of every level j into Ut[j * ldt + kl] and
+// returns the lane's partial (sum of quantiles, sum of squares) in *su, *sq,
+// and the column mass (same value on the group's lanes).
+template <int M, bool HALF, typename ColFn>
 __device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut, int ldt, int kl,
-                                  int lane, double *su, double *sq) {
+                                  int hl, int half, double *su, double *sq) {
+    constexpr int G = HALF ? 32 : 64;
     double v[M];
     double run = 0.0;
 #pragma unroll
     for (int t = 0; t < M; ++t) {
-        const int b = lane * M + t;
+        const int b = hl * M + t;
         double x = 0.0;
         if (b < L) x = (double)col(b);
         run += x;
         v[t] = run;  // lane-local inclusive sums
     }
-    const double excl = wave_inclusive_scan_d(run) - run;
+    const double excl = group_inclusive_scan_d<HALF>(run) - run;
     // mass = cumulative sum at the last bin, taken from the lane holding it
     const int last_lane = (L - 1) / M;
     const int last_t = (L - 1) - last_lane * M;
@@ -99,7 +134,7 @@ __device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut
 #pragma unroll
     for (int t = 1; t < M; ++t)
         if (t == last_t) lastv = v[t];
-    const double mass = read_lane_d(excl + lastv, last_lane);
+    const double mass = read_group_lane_d<HALF>(excl + lastv, last_lane, half);
     const double h = 2.0 / (double)L;
     const double invQ = 1.0 / (double)Q;
     const double z0 = levels ? 0.0 : 0.5 * invQ;       // z_j = j / Q + z0
@@ -108,7 +143,7 @@ __device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut
     if (!(mass > 0.0)) {
         // empty (or non-finite) column: the inverse of a zero CDF, as in the
         // lower-bound rule with every CDF value 0
-        for (int j = lane; j < Q; j += 64) {
+        for (int j = hl; j < Q; j += G) {
             const int b = (levels && j == 0) ? 0 : L - 1;
             const float uf = (float)(-1.0 + (double)b * h);
             Ut[j * ldt + kl] = uf;
@@ -117,36 +152,34 @@ __device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut
         }
     } else {
         const double invm = 1.0 / mass;
-        double c[M];
-#pragma unroll
-        for (int t = 0; t < M; ++t) c[t] = (excl + v[t]) * invm;  // C at the right edge of bin
-        // the CDF reaches exactly 1 at the right edge of the last bin
-#pragma unroll
-        for (int t = 0; t < M; ++t)
-            if (lane * M + t == L - 1) c[t] = 1.0;
+        // C at the right edge of bin b = hl M + t; exactly 1 at the last bin
+        auto cdf = [&](int t) {
+            return hl * M + t == L - 1 ? 1.0 : (excl + v[t]) * invm;
+        };
         // C at the left edge of this lane's first bin: the previous lane's
-        // last right edge (0 on lane 0)
-        const double cm = c[M - 1];
+        // last right edge (0 on the first lane of the group)
+        const double cm = cdf(M - 1);
         const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(cm), 0x138, 0xf, 0xf, false);
         const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(cm), 0x138, 0xf, 0xf, false);
         double cl = __hiloint2double(hi, lo);  // wave_shr:1
-        int jl = lane == 0 ? 0 : levels_at_or_below(cl, Q, zshift);
+        if (hl == 0) cl = 0.0;  // with halves, lane 32 got lane 31's edge
+        int jl = hl == 0 ? 0 : levels_at_or_below(cl, Q, zshift);
 #pragma unroll
         for (int t = 0; t < M; ++t) {
-            const int b = lane * M + t;
+            const int b = hl * M + t;
             if (b < L) {
-                const double cr = c[t];
+                const double cr = cdf(t);
                 const int jr = levels_at_or_below(cr, Q, zshift);
                 const double tl = fma((double)b, h, -1.0), tr = tl + h;
                 const double den = cr - cl;
                 const double slope = den > 0.0 ? div_by(h, den) : 0.0;
-                // the offset z - cl inside the bin in FP64, the interpolation
-                // and the clamp to the bin in FP32 (the result's precision)
+                // the offset z - cl inside the bin in FP64 (advanced by 1/Q
+                // per level), the interpolation and the clamp to the bin in
+                // FP32 (the result's precision)
                 const float tlf = (float)tl, trf = (float)tr, slf = (float)slope;
-                for (int j = jl; j < jr; ++j) {
-                    const double z = fma((double)j, invQ, z0);
-                    const float uf =
-                        __builtin_amdgcn_fmed3f(fmaf((float)(z - cl), slf, tlf), tlf, trf);
+                double zc = fma((double)jl, invQ, z0) - cl;
+                for (int j = jl; j < jr; ++j, zc += invQ) {
+                    const float uf = __builtin_amdgcn_fmed3f(fmaf((float)zc, slf, tlf), tlf, trf);
                     Ut[j * ldt + kl] = uf;
                     s1 += (double)uf;
                     s2 = fma((double)uf, (double)uf, s2);
@@ -162,44 +195,54 @@ __device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut
     return mass;
 }
 
-template <typename ColFn>
+// HALF: L <= 128; otherwise 128 < L <= 256.  Either way M <= 4.
+template <bool HALF, typename ColFn>
 __device__ __forceinline__ double invert_column(ColFn col, int L, int Q, int levels, float *Ut,
-                                                int ldt, int kl, int lane, double *su,
+                                                int ldt, int kl, int hl, int half, double *su,
                                                 double *sq) {
-    const int m = (L + 63) >> 6;  // bins per lane, <= 4 (wave-uniform)
-    if (m == 1) return invert_column_m<1>(col, L, Q, levels, Ut, ldt, kl, lane, su, sq);
-    if (m == 2) return invert_column_m<2>(col, L, Q, levels, Ut, ldt, kl, lane, su, sq);
-    if (m == 3) return invert_column_m<3>(col, L, Q, levels, Ut, ldt, kl, lane, su, sq);
-    return invert_column_m<4>(col, L, Q, levels, Ut, ldt, kl, lane, su, sq);
+    const int m = HALF ? (L + 31) >> 5 : (L + 63) >> 6;  // bins per lane (wave-uniform)
+    switch (m) {
+    case 1: return invert_column_m<1, HALF>(col, L, Q, levels, Ut, ldt, kl, hl, half, su, sq);
+    case 2: return invert_column_m<2, HALF>(col, L, Q, levels, Ut, ldt, kl, hl, half, su, sq);
+    case 3: return invert_column_m<3, HALF>(col, L, Q, levels, Ut, ldt, kl, hl, half, su, sq);
+    default: return invert_column_m<4, HALF>(col, L, Q, levels, Ut, ldt, kl, hl, half, su, sq);
+    }
 }
 
-// The whole CDF/quantile phase of one image, shared by the stand-alone,
-// fused and mixed kernels.  col(k, b) reads bin b of column k.  LDS: Ut
-// (Q * (TC + 1) floats), colS (2 n doubles).
-// Column sums are stored per column and reduced by wave 0 in a fixed order,
-// so the per-image scalars do not depend on the block size or tile width.
-template <int NT, typename ColFn>
-__device__ void quantile_phase(ColFn col, int L, int n, int Q, int levels, int TC,
-                               const double2 *__restrict__ d64, float *Ut, double *colS,
-                               float *__restrict__ U, double *__restrict__ A) {
+// Invert the TC columns k0 .. k0 + TC - 1 of a tile: with halves, columns
+// 2 p and 2 p + 1 go to the two halves of wave p (TC is even).
+template <int NT, bool HALF, typename ColFn>
+__device__ __forceinline__ void invert_tile(ColFn col, int L, int Q, int levels, int TC, int k0,
+                                            float *Ut, double *colS, double *mass0) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int hl = HALF ? lane & 31 : lane, half = HALF ? lane >> 5 : 0;
+    const int per_wave = HALF ? 2 : 1;
+    for (int p = wave; per_wave * p < TC; p += NW) {
+        const int kl = per_wave * p + half, k = k0 + kl;
+        double su, sq;
+        const double mass = invert_column<HALF>([&](int b) { return col(k, b); }, L, Q, levels,
+                                                Ut, TC + 1, kl, hl, half, &su, &sq);
+        if (k == 0) *mass0 = mass;
+        su = group_sum_d<HALF>(su, half);
+        sq = group_sum_d<HALF>(sq, half);
+        if (hl == 0) {
+            colS[2 * k] = su;
+            colS[2 * k + 1] = sq;
+        }
+    }
+}
+
+// All tiles of columns of one image: invert a tile into Ut, then write it
+// out as rows of the [Q][n] table (angle fastest).  Returns the mass of
+// column 0 (on the lanes that inverted it).
+template <int NT, bool HALF, typename ColFn>
+__device__ double quantile_tiles(ColFn col, int L, int n, int Q, int levels, int TC, float *Ut,
+                                 double *colS, float *__restrict__ U) {
     const int ldt = TC + 1;
     double mass0 = 0.0;
     for (int k0 = 0; k0 < n; k0 += TC) {
-        for (int kl = wave; kl < TC; kl += NW) {
-            const int k = k0 + kl;
-            double su, sq;
-            const double mass = invert_column([&](int b) { return col(k, b); }, L, Q, levels, Ut,
-                                              ldt, kl, lane, &su, &sq);
-            if (k == 0) mass0 = mass;
-            su = wave_sum_d(su);
-            sq = wave_sum_d(sq);
-            if (lane == 0) {
-                colS[2 * k] = su;
-                colS[2 * k + 1] = sq;
-            }
-        }
+        invert_tile<NT, HALF>(col, L, Q, levels, TC, k0, Ut, colS, &mass0);
         __syncthreads();
         for (int idx = threadIdx.x; idx < Q * TC; idx += NT) {
             const int j = idx / TC, kl = idx - j * TC;
@@ -207,6 +250,34 @@ __device__ void quantile_phase(ColFn col, int L, int n, int Q, int levels, int T
         }
         __syncthreads();
     }
+    return mass0;
+}
+
+// Which column inversion a kernel compiles: both, chosen by L at run time,
+// or only the half-wave one (the caller guarantees L <= 128) or only the
+// whole-wave one (L > 128).  A kernel that keeps other values live across
+// the phase compiles one, so that its registers are those of one body.
+enum QuantMode { kQuantAuto = 0, kQuantHalf = 1, kQuantWave = 2 };
+
+__host__ __device__ inline QuantMode quant_mode_for(int L) {
+    return L <= 128 ? kQuantHalf : kQuantWave;
+}
+
+// The whole CDF/quantile phase of one image, shared by the stand-alone,
+// fused and mixed kernels.  col(k, b) reads bin b of column k.  LDS: Ut
+// (Q * (TC + 1) floats), colS (2 n doubles).
+// Column sums are stored per column and reduced by wave 0 in a fixed order,
+// so the per-image scalars do not depend on the block size or tile width.
+template <int NT, int QM = kQuantAuto, typename ColFn>
+__device__ void quantile_phase(ColFn col, int L, int n, int Q, int levels, int TC,
+                               const double2 *__restrict__ d64, float *Ut, double *colS,
+                               float *__restrict__ U, double *__restrict__ A) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double mass0;
+    if (QM == kQuantHalf || (QM == kQuantAuto && L <= 128))
+        mass0 = quantile_tiles<NT, true>(col, L, n, Q, levels, TC, Ut, colS, U);
+    else
+        mass0 = quantile_tiles<NT, false>(col, L, n, Q, levels, TC, Ut, colS, U);
     if (wave == 0) {
         double e = 0.0, x = 0.0, y = 0.0;
         for (int k = lane; k < n; k += 64) {
