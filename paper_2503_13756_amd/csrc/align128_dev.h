@@ -304,30 +304,41 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
                 (__attribute__((address_space(3))) void *)((float *)xb + 256 * q), 16, 0, 0);
     }
 
-    // --- inverse transform over w, translation correction, objective per lag
+    // --- inverse transform over w, translation correction, objective per lag.
+    // Lags l and l + 64 share every twiddle (e^{2 pi i w 64 / n} = (-1)^w):
+    // a task sums the even and the odd w of its quarter apart and gives both.
     const double nq = (double)n * (double)Q;
-    for (int t = threadIdx.x; t < n * 4; t += NT) {
+    for (int t = threadIdx.x; t < n * 2; t += NT) {
         const int l = t >> 2, part = t & 3;
-        float sum = 0.f;
-        const int w0 = 1 + 16 * part, w1 = part == 3 ? 63 : w0 + 15;
+        float se = 0.f, so = 0.f;
+        const int w0 = 1 + 16 * part, w1 = part == 3 ? 63 : w0 + 15;  // w0 odd
         int m = (w0 * l) & (n - 1);
-        for (int w = w0; w <= w1; ++w) {
-            const float2 tt = tw[m];
-            sum += S[w].x * tt.x + S[w].y * tt.y;  // Re(S e^{+2 pi i w l / n})
+        for (int w = w0; w <= w1; w += 2) {
+            const float2 t1 = tw[m];
+            so += S[w].x * t1.x + S[w].y * t1.y;  // Re(S e^{+2 pi i w l / n})
+            m = (m + l) & (n - 1);
+            if (w + 1 <= w1) {
+                const float2 t2 = tw[m];
+                se += S[w + 1].x * t2.x + S[w + 1].y * t2.y;
+            }
             m = (m + l) & (n - 1);
         }
+        float sum = se + so, sum64 = se - so;
         sum += __shfl_xor(sum, 1, 64);
         sum += __shfl_xor(sum, 2, 64);
-        if (part == 0) {
+        sum64 += __shfl_xor(sum64, 1, 64);
+        sum64 += __shfl_xor(sum64, 2, 64);
+        if (part < 2) {  // part 0: lag l, part 1: lag l + 64
+            const int lp = l + 64 * part;
             const float a0 = S[0].x + ((l & 1) ? -S[n / 2].x : S[n / 2].x);
-            const double Cl = ((double)a0 + 2.0 * (double)sum) / (double)n;
+            const double Cl = ((double)a0 + 2.0 * (double)(part ? sum64 : sum)) / (double)n;
             double d = (au[1] + av[1] - 2.0 * Cl) / nq;
             if (job.mode == 0) {
-                const double2 b = trans_moment(au, av, tw64[l]);
+                const double2 b = trans_moment(au, av, tw64[lp]);
                 d -= 2.0 * (b.x * b.x + b.y * b.y);
             }
-            D[l] = d;
-            if (curve) curve[l] = (float)d;
+            D[lp] = d;
+            if (curve) curve[lp] = (float)d;
         }
     }
     __syncthreads();
