@@ -29,7 +29,8 @@ if ROOT not in sys.path:
 import synth  # noqa: E402
 
 METRIC = "alignments/s at L=128, plain FP32 vs served BF16 form; p50/p99 latency"
-LEGS = ("ramp", "msw", "fourier", "all_pairs", "uneven", "single", "serving", "serving_mixed")
+LEGS = ("ramp", "msw", "fourier", "all_pairs", "uneven", "single", "table4", "serving",
+        "serving_mixed")
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
@@ -306,6 +307,9 @@ def main():
     if "single" in legs:
         log("single pair")
         line["single_pair"] = single_pair(api, ctx, torch)
+    if "table4" in legs:
+        log("1 vs 1,031 at L=39")
+        line["table4_context"], extra_res["table4"] = table4_context(api, ctx, torch)
     if "serving" in legs:
         log("serving trace")
         line["serving"] = bench_serving(api, torch, args.requests, budget=1 << 30)
@@ -329,6 +333,9 @@ def main():
         if "fourier" in extra_res:
             log("Fourier-slice parity (oracle)")
             line["cpu_baseline"]["fourier_parity"] = fourier_parity(w, extra_res["fourier"], L, n, Q)
+        if "table4" in extra_res:
+            log("L=39 parity (oracle)")
+            line["cpu_baseline"]["table4_parity"] = table4_parity(*extra_res["table4"])
         if "msw" in extra_res:
             log("max-sliced parity (oracle)")
             line["cpu_baseline"]["max_sliced_parity"] = msw_parity(w, extra_res["msw"], L, n, Q)
@@ -945,6 +952,50 @@ def single_pair(api, ctx, torch, reps=50):
             "latency_ms": dt * 1e3, "rot_index": int(g["rot_index"][0]),
             "shift_px": [float(v) for v in g["shift_px"][0]], "sw2sq": float(g["sw2sq"][0]),
             "paper_context": "0.0027 s per pair at L=64 on CPU (Table 3)"}
+
+
+def table4_context(api, ctx, torch, reps=20):
+    """1 reference + 1,031 images at L = 39 (the digits' size and count in the
+    paper's Table 4), n = Q = 48: host images (pinned) to results back on the
+    host, synchronised per job; the oracle's parity on every pair."""
+    L, n, Q, N = 39, 48, 48, 1031
+    ref, imgs, _, _ = synth.make_stack(1005, L, N, K=8, shift_px=6.0, jitter_px=1.0, snr=1.0)
+    r_h = torch.from_numpy(ref[None].copy()).pin_memory()
+    x_h = torch.from_numpy(np.ascontiguousarray(imgs)).pin_memory()
+
+    def one():
+        r = r_h.cuda(non_blocking=True)
+        x = x_h.cuda(non_blocking=True)
+        rq, ra = api.tables(ctx, r, n, Q)
+        iq, ia = api.tables(ctx, x, n, Q)
+        res, _ = api.align_batch(ctx, rq, ra, iq, ia, L)
+        return res.cpu()
+
+    for _ in range(3):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = one()
+    dt = (time.perf_counter() - t0) / reps
+    return ({"workload": "1 reference + 1031 images, L=39, n=Q=48, 8 blobs, +-6 px, SNR 1; "
+                         "pinned host images to host results, synchronised per job",
+             "ms": dt * 1e3, "alignments_per_s": N / dt,
+             "paper_context": "0.586 s for SW2, 1 vs 1031 digits at L=39 on CPU (Table 4)"},
+            (ref, imgs, api.unpack_results(res), n, Q, L))
+
+
+def table4_parity(ref, imgs, g, n, Q, L):
+    """The oracle on every pair of the L = 39 job."""
+    from oracle import oracle as O
+    from tests import parity
+
+    o = O.align_images(ref, imgs, n, Q, want_curve=True)
+    try:
+        rep = parity.check(g, o, L, parity.TAU_FP32, o["curve"])
+        return f"{rep['pairs']} pairs ok, exact rotation {rep['exact_rot']}"
+    except AssertionError as e:
+        return "FAILED: " + str(e)[:300]
 
 
 def _pool(L, N, seed, distinct=None):

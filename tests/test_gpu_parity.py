@@ -73,8 +73,10 @@ def inputs(kind, L, N, seed):
     return raw_stack(L, N, seed) if kind == "raw" else blob_stack(L, N, seed)
 
 
-GEOMS = [(16, 16, 16), (40, 24, 20), (64, 64, 64), (96, 96, 96), (128, 128, 128),
-         (64, 128, 48), (192, 192, 192), (256, 256, 256)]
+# odd sides too: L = 39 is the digits' size in the paper's timings (Table 4)
+# with a radix-3 angle count, L = 127 takes the n = 128 register-FFT path
+GEOMS = [(16, 16, 16), (39, 48, 48), (40, 24, 20), (64, 64, 64), (96, 96, 96),
+         (127, 128, 128), (128, 128, 128), (64, 128, 48), (192, 192, 192), (256, 256, 256)]
 
 
 @pytest.mark.parametrize("kind", ["clean", "raw"])
