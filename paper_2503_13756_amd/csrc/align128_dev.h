@@ -120,6 +120,91 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int kA128Stride = 18;  // complex per lane row of the transpose buffer (16 + pad)
 constexpr int kA128VRow = 132;   // floats per staged table row (128 + pad)
 
+// Spectrum of the packed row of lane group `grp`, whose two table rows are
+// staged at varea + 2 grp kA128VRow (rows kA128VRow floats apart): lane l8
+// ends with Z[2 l8 + tau + 16 s] in u_tau[s].  buf: the group's 8 x
+// kA128Stride transpose buffer (it may overlap the staged rows: they are read
+// first).  Wave-synchronous.
+__device__ __forceinline__ void a128_row_spectrum(const float *varea, float2 *buf,
+                                                  const float2 *tw, int grp, int l8,
+                                                  float2 (&u0)[8], float2 (&u1)[8]) {
+    constexpr int n = 128;
+    float2 x[16];
+    const float *zr = varea + 2 * grp * kA128VRow + l8;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) x[m] = make_float2(zr[8 * m], zr[kA128VRow + 8 * m]);
+    wave_lds_sync();
+    dft16(x);
+    // l8 t < n: the twiddle addresses are formed here from an opaque copy of
+    // l8 rather than kept live across the caller's loop (15 registers)
+    int lt = l8;
+    asm volatile("" : "+v"(lt));
+#pragma unroll
+    for (int t = 1; t < 16; ++t) x[t] = cmul(x[t], tw[lt * t]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        *(float4 *)(buf + l8 * kA128Stride + 2 * k) =
+            make_float4(x[2 * k].x, x[2 * k].y, x[2 * k + 1].x, x[2 * k + 1].y);
+    wave_lds_sync();
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+        const float4 q = *(const float4 *)(buf + l * kA128Stride + 2 * l8);
+        u0[l] = make_float2(q.x, q.y);
+        u1[l] = make_float2(q.z, q.w);
+    }
+    wave_lds_sync();
+    dft8(u0);
+    dft8(u1);
+}
+
+// Spectral dot of packed row p into the lane's 16 slots (slot tau 8 + s holds
+// frequency f = 2 l8 + tau + 16 s; f > 64 accumulates conj(Z) beta into
+// S(128 - f)); lane 0 of the group also adds conj(Z(0)) beta_p(0) and
+// Z(64) alpha_p(64).  bf16: operands rounded to bfloat16 first.
+__device__ __forceinline__ void a128_dot(float2 (&acc)[16], const float2 (&u0)[8],
+                                         const float2 (&u1)[8], const float2 *__restrict__ G,
+                                         const float2 *__restrict__ GX, int p, int l8, int bf16) {
+    const float4 *gp = (const float4 *)(G + (int64_t)p * kA128Slots + l8 * 16);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float4 gq = gp[k];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int slot = 2 * k + h, tau = slot >> 3, s = slot & 7;
+            float2 z = tau ? u1[s] : u0[s];
+            float2 c = h ? make_float2(gq.z, gq.w) : make_float2(gq.x, gq.y);
+            if (bf16) {
+                z = bf16r2(z);
+                c = bf16r2(c);
+            }
+            if (s >= 4) z.y = -z.y;  // conj(Z) beta for f > 64
+            acc[slot].x += z.x * c.x - z.y * c.y;
+            acc[slot].y += z.x * c.y + z.y * c.x;
+        }
+    }
+    if (l8 == 0) {
+        // f = 0 also takes conj(Z) beta_p(0); f = 64 also takes Z alpha_p(64)
+        float2 z0 = u0[0], z4 = u0[4];
+        float2 c0 = GX[2 * p], c4 = GX[2 * p + 1];
+        if (bf16) {
+            z0 = bf16r2(z0);
+            z4 = bf16r2(z4);
+            c0 = bf16r2(c0);
+            c4 = bf16r2(c4);
+        }
+        acc[0].x += z0.x * c0.x + z0.y * c0.y;
+        acc[0].y += z0.x * c0.y - z0.y * c0.x;
+        acc[4].x += z4.x * c4.x - z4.y * c4.y;
+        acc[4].y += z4.x * c4.y + z4.y * c4.x;
+    }
+}
+
+// Slot of frequency f in a lane group's buffer of partial sums: lane
+// (f mod 16) / 2, entry (f mod 2) 8 + f / 16.
+__device__ __forceinline__ int a128_slot(int f) {
+    return ((f & 15) >> 1) * kA128Stride + (f & 1) * 8 + (f >> 4);
+}
+
 // LDS of one block of the n = 128 alignment.
 template <int NT>
 struct A128Lds {
@@ -202,65 +287,9 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
         }
         wave_lds_sync();
         const int p = pbase + grp;
-        const bool active = p < P2;
-        float2 x[16];
-        const float *zr = varea + 2 * grp * kA128VRow + l8;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) x[m] = make_float2(zr[8 * m], zr[kA128VRow + 8 * m]);
-        wave_lds_sync();
-        dft16(x);
-#pragma unroll
-        for (int t = 1; t < 16; ++t) x[t] = cmul(x[t], tw[(l8 * t) & (n - 1)]);
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            *(float4 *)(buf + l8 * kA128Stride + 2 * k) =
-                make_float4(x[2 * k].x, x[2 * k].y, x[2 * k + 1].x, x[2 * k + 1].y);
-        wave_lds_sync();
         float2 u0[8], u1[8];
-#pragma unroll
-        for (int l = 0; l < 8; ++l) {
-            const float4 q = *(const float4 *)(buf + l * kA128Stride + 2 * l8);
-            u0[l] = make_float2(q.x, q.y);
-            u1[l] = make_float2(q.z, q.w);
-        }
-        wave_lds_sync();
-        dft8(u0);
-        dft8(u1);
-        // lane l8 now holds Z[2 l8 + tau + 16 s] in u_tau[s]
-        if (!active) continue;
-        const float4 *gp = (const float4 *)(G + (int64_t)p * kA128Slots + l8 * 16);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const float4 gq = gp[k];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int slot = 2 * k + h, tau = slot >> 3, s = slot & 7;
-                float2 z = tau ? u1[s] : u0[s];
-                float2 c = h ? make_float2(gq.z, gq.w) : make_float2(gq.x, gq.y);
-                if (bf16) {
-                    z = bf16r2(z);
-                    c = bf16r2(c);
-                }
-                if (s >= 4) z.y = -z.y;  // conj(Z) beta for f > 64
-                acc[slot].x += z.x * c.x - z.y * c.y;
-                acc[slot].y += z.x * c.y + z.y * c.x;
-            }
-        }
-        if (l8 == 0) {
-            // f = 0 also takes conj(Z) beta_p(0); f = 64 also takes Z alpha_p(64)
-            float2 z0 = u0[0], z4 = u0[4];
-            float2 c0 = GX[2 * p], c4 = GX[2 * p + 1];
-            if (bf16) {
-                z0 = bf16r2(z0);
-                z4 = bf16r2(z4);
-                c0 = bf16r2(c0);
-                c4 = bf16r2(c4);
-            }
-            acc[0].x += z0.x * c0.x + z0.y * c0.y;
-            acc[0].y += z0.x * c0.y - z0.y * c0.x;
-            acc[4].x += z4.x * c4.x - z4.y * c4.y;
-            acc[4].y += z4.x * c4.y + z4.y * c4.x;
-        }
+        a128_row_spectrum(varea, buf, tw, grp, l8, u0, u1);
+        if (p < P2) a128_dot(acc, u0, u1, G, GX, p, l8, bf16);
     }
     // --- partial sums of every lane group to LDS, then S(w) for w = 0..64
 #pragma unroll
@@ -452,6 +481,246 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
         res->theta_rad = (float)(6.283185307179586 * (double)best_l / (double)n);
         res->shift_px[0] = bsx * 0.5f * L;
         res->shift_px[1] = bsy * 0.5f * L;
+        res->sw2sq = best;
+        res->status = 0;
+    }
+}
+
+// The same alignment with one pair per wave: the transforms and the spectral
+// dot as in align128_pair, the eight lane groups' partial sums added through
+// the wave's LDS, lags l and l + 64 per lane, the top K lags by a butterfly
+// over the lanes, and the FP32 rescore from image rows staged 16 at a time.
+// No block barrier: the waves of a block run independent pairs.  xb: the
+// wave's kA128WaveElems float2 of LDS; tw: the angle table in LDS.
+constexpr int kA128WaveElems = 8 * 8 * kA128Stride;
+
+__device__ void align128_wave(const A128Job &job, float2 *xb, const float2 *tw) {
+    constexpr int n = 128;
+    const int Q = job.Q, P2 = Q / 2;
+    // an opaque copy of the lane index: in a persistent caller, the per-lane
+    // addresses derived from it are formed per pair instead of being kept
+    // live (or spilled) across pairs
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const int l8 = lane & 7, grp = lane >> 3;
+    if (job.status) {
+        if (lane == 0) {
+            job.res->rot_index = 0;
+            job.res->theta_rad = 0.f;
+            job.res->shift_px[0] = job.res->shift_px[1] = 0.f;
+            job.res->sw2sq = __int_as_float(0x7fc00000);
+            job.res->status = job.status;
+        }
+        if (job.curve) {
+            job.curve[lane] = __int_as_float(0x7fc00000);
+            job.curve[lane + 64] = __int_as_float(0x7fc00000);
+        }
+        return;
+    }
+    const float *U = job.U, *V = job.V;
+    const double *au = job.au, *av = job.av;
+    float *varea = (float *)xb;
+    float2 *buf = xb + grp * 8 * kA128Stride;
+
+    // 16 table rows [r0, r0 + 16) of V into varea (rows kA128VRow apart,
+    // coalesced 16-byte loads; rows past Q read as zero)
+    // (lane: row lane / 32 + 2 i, 16-byte column lane mod 32 for i < 8, so
+    // that every address is one per-lane base plus a constant)
+    const int srow = lane >> 5, sc4 = 4 * (lane & 31);
+    float *sdst = varea + srow * kA128VRow + sc4;
+    auto stage = [&](int r0) {
+        const float *src = V + (int64_t)(r0 + srow) * n + sc4;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r0 + srow + 2 * i < Q) v = *(const float4 *)(src + 2 * i * n);
+            *(float4 *)(sdst + 2 * i * kA128VRow) = v;
+        }
+        wave_lds_sync();
+    };
+
+    // --- angle FFTs of the packed rows and the spectral dot
+    float2 acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = make_float2(0.f, 0.f);
+    for (int pbase = 0; pbase < P2; pbase += 8) {
+        stage(2 * pbase);
+        const int p = pbase + grp;
+        float2 u0[8], u1[8];
+        a128_row_spectrum(varea, buf, tw, grp, l8, u0, u1);
+        if (p < P2) a128_dot(acc, u0, u1, job.G, job.GX, p, l8, job.bf16);
+    }
+
+    // --- the groups' partial sums, then S(w): lane t forms T(t) and
+    // T(t + 64), S(w) = T(w) + T(128 - w) for 1 <= w <= 63, S(0) = T(0),
+    // S(64) = T(64)
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        *(float4 *)(buf + l8 * kA128Stride + 2 * k) =
+            make_float4(acc[2 * k].x, acc[2 * k].y, acc[2 * k + 1].x, acc[2 * k + 1].y);
+    wave_lds_sync();
+    float2 t1 = make_float2(0.f, 0.f), t2 = make_float2(0.f, 0.f);
+    {
+        const int i1 = a128_slot(lane), i2 = a128_slot(lane + 64);
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            t1 = cadd(t1, xb[g * 8 * kA128Stride + i1]);
+            t2 = cadd(t2, xb[g * 8 * kA128Stride + i2]);
+        }
+    }
+    const float ox = __shfl(t2.x, (64 - lane) & 63, 64), oy = __shfl(t2.y, (64 - lane) & 63, 64);
+    wave_lds_sync();
+    float2 *S = xb;  // 65 values
+    S[lane] = lane == 0 ? t1 : make_float2(t1.x + ox, t1.y + oy);
+    if (lane == 0) S[64] = t2;
+    wave_lds_sync();
+
+    // --- inverse transform for lags l = lane and l + 64 (e^{2 pi i w 64 / n}
+    // = (-1)^w), translation correction, objective
+    const int l = lane;
+    float se = 0.f, so = 0.f;
+    {
+        int m = l;  // w l mod n for w = 1
+        for (int w = 1; w < 64; w += 2) {
+            const float2 a = tw[m], sa = S[w];
+            so += sa.x * a.x + sa.y * a.y;  // Re(S e^{+2 pi i w l / n})
+            m = (m + l) & (n - 1);
+            if (w < 63) {
+                const float2 b = tw[m], sb = S[w + 1];
+                se += sb.x * b.x + sb.y * b.y;
+            }
+            m = (m + l) & (n - 1);
+        }
+    }
+    const double nq = (double)n * (double)Q;
+    double dl[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int lp = l + 64 * h;
+        const float a0 = S[0].x + ((l & 1) ? -S[n / 2].x : S[n / 2].x);
+        const double Cl = ((double)a0 + 2.0 * (double)(h ? se - so : se + so)) / (double)n;
+        double d = (au[1] + av[1] - 2.0 * Cl) / nq;
+        if (job.mode == 0) {
+            const double2 b = trans_moment(au, av, job.d64[lp]);
+            d -= 2.0 * (b.x * b.x + b.y * b.y);
+        }
+        dl[h] = d;
+        if (job.curve) job.curve[lp] = (float)d;
+    }
+
+    // --- top-K lags (ties to the smaller lag), the same on every lane
+    const int K = job.top_k;
+    int cand[kMaxTopK];
+    {
+        double v0 = dl[0], v1 = dl[1];
+#pragma unroll
+        for (int c = 0; c < kMaxTopK; ++c) {
+            cand[c] = 0;
+            if (c < K) {
+                double v = v0;
+                int i = lane;
+                argmin_merge(v, i, v1, lane + 64);
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const double v2 = __shfl_xor(v, off, 64);
+                    const int i2 = __shfl_xor(i, off, 64);
+                    argmin_merge(v, i, v2, i2);
+                }
+                cand[c] = __builtin_amdgcn_readfirstlane(i);
+                if (i == lane) v0 = __builtin_inf();
+                if (i == lane + 64) v1 = __builtin_inf();
+            }
+        }
+    }
+
+    // --- FP32 rescore of the candidates: direct residual sum, lane columns
+    // k = 2 lane, 2 lane + 1, rows staged 16 at a time
+    float2 cs[kMaxTopK];
+    float sh0[kMaxTopK], sh1[kMaxTopK], part[kMaxTopK];
+    const int k0 = 2 * lane;
+    const float2 dk0 = tw[k0], dk1 = tw[k0 + 1];
+#pragma unroll
+    for (int c = 0; c < kMaxTopK; ++c) {
+        cs[c] = make_float2(0.f, 0.f);
+        if (c < K && job.mode == 0) {
+            const double2 b = trans_moment(au, av, job.d64[cand[c]]);
+            cs[c] = make_float2((float)(2.0 * b.x), (float)(2.0 * b.y));
+        }
+        sh0[c] = cs[c].x * dk0.x + cs[c].y * dk0.y;
+        sh1[c] = cs[c].x * dk1.x + cs[c].y * dk1.y;
+        part[c] = 0.f;
+    }
+    // rows in chunks of 8, double-buffered in the wave's LDS (rows of n
+    // floats) by memory-to-LDS copies: the next chunk's rows and the
+    // reference rows it needs are in flight while the current chunk is summed
+    float *vb0 = (float *)xb, *vb1 = vb0 + 8 * n;
+    auto issue = [&](int r0, float *dst, float2 (&u)[8]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)  // 1 KiB = two rows per copy (Q is even)
+            if (r0 + 2 * q < Q)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(V + (int64_t)(r0 + 2 * q) * n + 4 * lane),
+                    (__attribute__((address_space(3))) void *)(dst + 2 * q * n), 16, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            u[r] = r0 + r < Q ? *(const float2 *)(U + (int64_t)(r0 + r) * n + k0)
+                              : make_float2(0.f, 0.f);
+    };
+    auto sum_chunk = [&](int r0, const float *vb, const float2 (&u)[8]) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (r0 + r < Q) {
+                const float *vr = vb + r * n;
+#pragma unroll
+                for (int c = 0; c < kMaxTopK; ++c) {
+                    if (c < K) {
+                        const float d0 = u[r].x - vr[(k0 + cand[c]) & (n - 1)] - sh0[c];
+                        const float d1 = u[r].y - vr[(k0 + 1 + cand[c]) & (n - 1)] - sh1[c];
+                        part[c] = fmaf(d0, d0, part[c]);
+                        part[c] = fmaf(d1, d1, part[c]);
+                    }
+                }
+            }
+        }
+    };
+    float2 ua[8], ub[8];
+    wave_lds_sync();  // S is no longer read
+    issue(0, vb0, ua);
+    for (int r0 = 0; r0 < Q; r0 += 16) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): chunk r0 has landed
+        wave_lds_sync();
+        if (r0 + 8 < Q) issue(r0 + 8, vb1, ub);
+        sum_chunk(r0, vb0, ua);
+        if (r0 + 8 >= Q) break;
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // chunk r0 + 8 has landed
+        wave_lds_sync();
+        if (r0 + 16 < Q) issue(r0 + 16, vb0, ua);
+        sum_chunk(r0 + 8, vb1, ub);
+    }
+    int best_l = 0;
+    float best = 0.f, bsx = 0.f, bsy = 0.f;
+#pragma unroll
+    for (int c = 0; c < kMaxTopK; ++c) {
+        if (c < K) {
+            float t = part[c];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+            const float v = t / (float)nq;
+            if (c == 0 || v < best || (v == best && cand[c] < best_l)) {
+                best = v;
+                best_l = cand[c];
+                bsx = cs[c].x;
+                bsy = cs[c].y;
+            }
+        }
+    }
+    if (lane == 0) {
+        const float Lf = (float)job.L;
+        Result *res = job.res;
+        res->rot_index = best_l;
+        res->theta_rad = (float)(6.283185307179586 * (double)best_l / (double)n);
+        res->shift_px[0] = bsx * 0.5f * Lf;
+        res->shift_px[1] = bsy * 0.5f * Lf;
         res->sw2sq = best;
         res->status = 0;
     }

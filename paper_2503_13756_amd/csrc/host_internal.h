@@ -67,6 +67,7 @@ struct Ctx {
     // -1: the number of compute units
     int small_batch = -1;
     bool generic_align = false;  // never use the n = 128 register-FFT kernel
+    bool align128_per_wave = true;  // n = 128: one pair per wave (else per block)
     int tables_per_block = 2;    // images per block of the fused tables kernel (1 or 2)
     // failure injection for tests of the serving runtime: the request with
     // this ticket has its host-to-device copy reported as failed (0: none)

@@ -122,15 +122,27 @@ __global__ __launch_bounds__(256) void k_gamma_mixed(const MixGroup *__restrict_
     }
 }
 
-// n = 128 items (work items [0, split)): register-FFT alignment.
-template <int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_align128_mixed(
+// n = 128 items (work items [0, split)): register-FFT alignment, one image
+// per wave (align128_wave); each wave pulls its own work items.  The items
+// with n = 128 come first and share the angle table of n = 128, which the
+// block keeps in LDS.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_align128_mixed(
     const MixGroup *__restrict__ G, unsigned long long *counter) {
-    __shared__ A128Lds<NT> sm;
-    __shared__ int64_t wslot;
+    __shared__ float2 tw[128];
+    __shared__ __attribute__((aligned(16))) float2 wl[NW * kA128WaveElems];
     const int64_t split = G->split;
+    if (split <= 0) return;  // block-uniform
+    const float2 *d32 = G->items[0].d32;
+    for (int i = threadIdx.x; i < 128; i += 64 * NW) tw[i] = d32[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (;;) {
-        const int64_t w = next_work<NT>(counter, &wslot);
+        unsigned long long got = 0;
+        if (lane == 0) got = atomicAdd(counter, 1ull);
+        const int64_t w = (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane(
+                                         (unsigned)(got >> 32)) << 32) |
+                                    (unsigned)__builtin_amdgcn_readfirstlane((unsigned)got));
         if (w >= split) break;
         const MixItem &it = G->items[find_item(G, w)];
         const int64_t gi = w - it.first;
@@ -155,7 +167,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         if (isnan(job.au[0]) || isnan(job.av[0])) status = 2;
         else if (!(job.au[0] > 0.0) || !(job.av[0] > 0.0)) status = 1;
         job.status = status;
-        align128_pair<NT>(job, sm);
+        align128_wave(job, wl + wave * kA128WaveElems, tw);
     }
 }
 
@@ -293,8 +305,8 @@ hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const Mi
     hipLaunchKernelGGL((k_refspec_mixed<NT>), dim3((unsigned)kMaxMix), dim3(NT),
                        sizeof(float2) * (kMaxN + 2 * kFftElems), s, d_imgs);
     hipLaunchKernelGGL(k_gamma_mixed, dim3((unsigned)kMaxMix), dim3(256), 0, s, d_imgs);
-    // four 40 KiB blocks of the register-FFT kernel per compute unit
-    hipLaunchKernelGGL((k_align128_mixed<NT>), dim3((unsigned)(2 * grid)), dim3(NT), 0, s, d_imgs,
+    // four 37 KiB blocks of four waves of the register-FFT kernel per compute unit
+    hipLaunchKernelGGL((k_align128_mixed<4>), dim3((unsigned)(2 * grid)), dim3(256), 0, s, d_imgs,
                        counters + 3);
     // small LDS tiles: several blocks of the LDS-FFT kernel per compute unit
     // (grid = 2 blocks per compute unit; align_bpc per compute unit here)

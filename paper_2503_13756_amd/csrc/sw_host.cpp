@@ -760,6 +760,8 @@ sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
             c->small_batch = std::stoi(m[1]);
         if (std::regex_search(txt, m, std::regex("\"align_kernel\"\\s*:\\s*\"generic\"")))
             c->generic_align = true;
+        if (std::regex_search(txt, m, std::regex("\"align_kernel\"\\s*:\\s*\"block128\"")))
+            c->align128_per_wave = false;
         if (std::regex_search(txt, m, std::regex("\"tables_images_per_block\"\\s*:\\s*([12])")))
             c->tables_per_block = std::stoi(m[1]);
         if (std::regex_search(txt, m, std::regex("\"serve_fail_ticket\"\\s*:\\s*(\\d+)")))
@@ -1247,7 +1249,8 @@ static sw_status align_batch_impl(void *ctx, const sw_batch *b, sw_result *out, 
     a.out = (sw::Result *)out;
     a.curve = curve;
     if (fast128) {
-        e = sw::launch_align128(a, geo, *t, (float2 *)((char *)spec + spec_bytes), s);
+        e = sw::launch_align128(a, geo, *t, (float2 *)((char *)spec + spec_bytes), s,
+                                c->align128_per_wave);
         if (e != hipSuccess) return hip_fail(e, "k_gamma128 / k_align128 launch");
     } else {
         e = sw::launch_align_pairs(a, geo, *t, s);

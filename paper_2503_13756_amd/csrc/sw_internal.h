@@ -126,11 +126,12 @@ bool msw_supported(Geo g);
 hipError_t launch_align_msw(const PairArgs &a, Geo g, hipStream_t s);
 // The same for n = 128 with register-resident angle FFTs; needs a coefficient
 // scratch of align128_scratch_bytes() (a.ref_spec must hold the references'
-// FP32 spectra).
+// FP32 spectra).  per_wave: one pair per wave (k_align128w) instead of one
+// pair per block (k_align128).
 bool align128_supported(Geo g);
 size_t align128_scratch_bytes(Geo g, int64_t n_ref);
 hipError_t launch_align128(const PairArgs &a, Geo g, const AngleTable &t, float2 *gam,
-                           hipStream_t s);
+                           hipStream_t s, bool per_wave = true);
 
 // All reference x image pairs on MFMA (bfloat16 spectra, FP32 accumulate),
 // top-k lags per pair, then an FP32 rescore of those lags.

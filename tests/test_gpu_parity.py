@@ -358,6 +358,51 @@ def ctx_generic(api, tmp_path_factory):
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_block(api, tmp_path_factory):
+    """Context that runs the n = 128 register-FFT alignment one pair per
+    block instead of one pair per wave."""
+    path = tmp_path_factory.mktemp("tune") / "block128.json"
+    path.write_text('{"align_kernel": "block128"}')
+    c = api.Context(0, tune_json=str(path))
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("Q", [48, 128, 256])
+@pytest.mark.parametrize("mode,prec,top_k", [(0, 0, 1), (1, 0, 3), (0, 1, 4), (0, 0, 8)])
+def test_align128_wave_and_block_agree(api, ctx, ctx_block, oracle, Q, mode, prec, top_k):
+    """One pair per wave and one pair per block: the same arithmetic summed in
+    another order, so the same lags and distances to FP32 rounding, and both
+    within the oracle's tolerance; pair lists with an out-of-range index and a
+    self pair."""
+    L, n = 127, 128
+    ref, imgs = blob_stack(L, 21, 1300 + Q)
+    x = dev(np.concatenate([ref[None], imgs]))
+    q, a = api.tables(ctx, x, n, Q)
+    pairs = np.array([[0, i] for i in range(1, 22)] + [[4, 4], [7, 2], [0, 99]], np.int64)
+    r1, c1 = api.align_batch(ctx, q, a, q, a, L, pairs=dev(pairs), mode=mode, prec=prec,
+                             top_k=top_k, want_curve=True)
+    r2, c2 = api.align_batch(ctx_block, q, a, q, a, L, pairs=dev(pairs), mode=mode, prec=prec,
+                             top_k=top_k, want_curve=True)
+    g1, g2 = api.unpack_results(r1), api.unpack_results(r2)
+    assert g1["status"][-1] == 3 and g2["status"][-1] == 3
+    assert np.isnan(c1.cpu().numpy()[-1]).all() and np.isnan(c2.cpu().numpy()[-1]).all()
+    oq, oa = oracle.tables(np.concatenate([ref[None], imgs]), n, Q)
+    o = oracle.align(oq, oa, oq, oa, L, pairs=pairs[:-1], mode=mode, want_curve=True)
+    tau = parity.TAU_FP32 if prec == 0 else parity.TAU_BF16
+    for g in (g1, g2):
+        parity.check({k: v[:-1] for k, v in g.items()}, o, L, tau, o["curve"])
+        assert g["sw2sq"][21] == 0.0 and g["rot_index"][21] == 0  # the self pair
+    ok = g1["status"] == 0
+    same = ok & (g1["rot_index"] == g2["rot_index"])
+    assert same.sum() >= ok.sum() - 1
+    assert np.allclose(g1["sw2sq"][same], g2["sw2sq"][same], rtol=1e-5, atol=1e-9)
+    c1, c2 = c1.cpu().numpy()[:-1], c2.cpu().numpy()[:-1]
+    floor = 1e-5 * np.abs(c2).max(axis=1, keepdims=True)
+    assert np.all(np.abs(c1 - c2) <= 1e-4 * np.abs(c2) + floor)
+
+
 @pytest.mark.parametrize("Q", [48, 128, 256])
 @pytest.mark.parametrize("mode,prec,top_k", [(0, 0, 1), (1, 0, 3), (0, 1, 4), (0, 0, 8)])
 def test_align128_matches_oracle_and_generic(api, ctx, ctx_generic, oracle, Q, mode, prec, top_k):
