@@ -47,7 +47,7 @@ KERNEL_SOURCES = {
     "k_tables2": ["k_tables.hip", "proj2_dev.h", "proj_dev.h", "quant_dev.h", "sw_internal.h"],
     "k_project": ["k_project.hip", "proj_dev.h", "sw_internal.h"],
     "k_quantile": ["k_quantile.hip", "quant_dev.h", "sw_internal.h"],
-    "k_align128": ["k_align128.hip", "align128_dev.h", "align_dev.h", "sw_internal.h"],
+    "k_align128w": ["k_align128.hip", "align128_dev.h", "align_dev.h", "sw_internal.h"],
     "k_spectrum": ["k_align.hip", "align_dev.h", "sw_internal.h"],
     "k_corr_mfma": ["k_mfma.hip", "sw_internal.h"],
     "k_rescore_tiles": ["k_mfma.hip", "sw_internal.h"],
@@ -223,7 +223,7 @@ def main():
     seg16 = np.array([seg16[0], seg16[0] + seg16[1], seg16[2]])
     # dominant kernel: per-launch durations from the events
     t_tables = seg32[1] * 1e-3  # s, one k_tables launch over N images
-    t_align = seg32[2] * 1e-3   # s, k_spectrum (1 reference) + k_align128
+    t_align = seg32[2] * 1e-3   # s, k_spectrum (1 reference) + k_align128w
     M = disk_pixels(L)
     flops_tables = 4.0 * (n // 2) * M * N          # two FMAs per masked pixel and computed angle
     bytes_tables = 4.0 * L * L * N + 4.0 * Q * n * N + 32.0 * N
@@ -382,8 +382,8 @@ def stage_rooflines(line, N, L, n, Q):
     add("k_project", "alu", flops_proj, st["staged_project_ms"], "HIP events (staged projection)")
     add("k_quantile", "hbm", (4.0 * n * L + 4.0 * Q * n + 32.0) * N, st["staged_quantiles_ms"],
         "HIP events (staged quantiles)")
-    add("k_align128", "hbm", (4.0 * Q * n + 24.0) * N, st["align_ms"],
-        "HIP events (reference spectrum, coefficients and k_align128)")
+    add("k_align128w", "hbm", (4.0 * Q * n + 24.0) * N, st["align_ms"],
+        "HIP events (reference spectrum, coefficients and k_align128w)")
     ap = line.get("all_pairs")
     if ap:
         NA, LA = 2000, 64
