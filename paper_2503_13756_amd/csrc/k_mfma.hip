@@ -47,14 +47,22 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
                                                    int top_k, const double *__restrict__ ref_aux,
                                                    const double *__restrict__ img_aux,
                                                    const float2 *__restrict__ tw32,
-                                                   int16_t *__restrict__ cand) {
+                                                   int16_t *__restrict__ cand, int slice) {
     constexpr int Wn = N / 2 + 1;
     constexpr int SS = 2 * Wn + 1;  // odd LDS row stride
     extern __shared__ __align__(16) float lds[];
     float *Sl = lds;                           // [256 pairs][SS]
     float2 *tw = (float2 *)(lds + 256 * SS);  // [N]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t g0 = (int64_t)blockIdx.x * 16, r0 = (int64_t)blockIdx.y * 16;
+    // XCD-aware tile order: blocks go to the eight XCDs in turn, so block b
+    // runs on XCD b mod 8; XCD x takes the image tiles [x slice, (x + 1)
+    // slice) against every reference tile, image tile fastest, so that its
+    // L2 holds one slice of the image spectra and each reference tile is
+    // fetched once per slice pass.
+    const int64_t b = blockIdx.x, loc = b >> 3;
+    const int64_t it = (b & 7) * slice + loc % slice, rt = loc / slice;
+    if (it * 16 >= n_img) return;  // block-uniform, before any barrier
+    const int64_t g0 = it * 16, r0 = rt * 16;
     for (int i = threadIdx.x; i < N; i += 256) tw[i] = tw32[i];
 
     // Spectral products on the gfx950 bf16 MFMA with 32 K entries (16
@@ -394,9 +402,14 @@ static hipError_t launch_mfma_t(const MfmaArgs &a, Geo g, const AngleTable &t, h
     static const hipError_t attr1 = hipFuncSetAttribute(
         (const void *)k_corr_mfma<N, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     (void)attr1;
-    dim3 grid1((unsigned)((a.n_img + 15) / 16), (unsigned)((a.n_ref + 15) / 16));
-    hipLaunchKernelGGL((k_corr_mfma<N, KMAX>), grid1, dim3(256), lds1, s, a.spec_ref, a.spec_img,
-                       a.n_ref, a.n_img, g.Q, a.mode, a.top_k, a.ref_aux, a.img_aux, t.d32, a.cand);
+    // a 1-D grid of 8 slices of image tiles times the reference tiles
+    const int64_t tiles_img = (a.n_img + 15) / 16, tiles_ref = (a.n_ref + 15) / 16;
+    const int64_t slice = (tiles_img + 7) / 8;
+    const int64_t nblocks = 8 * slice * tiles_ref;
+    if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_corr_mfma<N, KMAX>), dim3((unsigned)nblocks), dim3(256), lds1, s,
+                       a.spec_ref, a.spec_img, a.n_ref, a.n_img, g.Q, a.mode, a.top_k, a.ref_aux,
+                       a.img_aux, t.d32, a.cand, (int)slice);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // blocks of eight images x TR references; TR chosen so that the grid
