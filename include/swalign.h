@@ -354,6 +354,9 @@ typedef struct {
     int32_t mode;            /* sw_mode */
     int32_t max_queue;       /* waiting requests before SW_E_BUSY */
     int32_t use_graphs;      /* 1: replay captured graphs, 0: plain launches */
+    int32_t max_per_step;    /* requests per launch sequence (0: max_slots, at most 64);
+                                below max_slots, the copies of the next step's requests
+                                overlap the current step's kernels */
 } sw_serve_cfg;
 
 typedef struct {

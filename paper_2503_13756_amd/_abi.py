@@ -51,7 +51,8 @@ class sw_stack(ctypes.Structure):
 class sw_serve_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("top_k", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("max_queue", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
+                ("max_queue", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+                ("max_per_step", ctypes.c_int32)]
 
 
 class sw_request(ctypes.Structure):

@@ -263,10 +263,11 @@ class Server:
     wrapper keeps a reference to them."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots=64, prec=_abi.PREC_BF16_SPLIT,
-                 top_k=0, mode=_abi.MODE_ROT_TRANS, max_queue=4096, use_graphs=True):
+                 top_k=0, mode=_abi.MODE_ROT_TRANS, max_queue=4096, use_graphs=True,
+                 max_per_step=0):
         self.ctx = ctx
         cfg = sw_serve_cfg(int(hbm_budget_bytes), int(max_slots), int(prec), int(top_k), int(mode),
-                           int(max_queue), 1 if use_graphs else 0)
+                           int(max_queue), 1 if use_graphs else 0, int(max_per_step))
         check(ctx._lib.sw_serve_start(ctx.handle, ctypes.byref(cfg)))
         self._live = {}
 

@@ -3,7 +3,7 @@
 // A scheduler thread per context admits requests from a FIFO queue while
 // they fit in a first-fit HBM arena and a slot is free, copies their images
 // on a copy stream, and issues "steps" on a compute stream: every admitted
-// request of one geometry (up to kMaxMix) goes into one sequence of mixed
+// request of one geometry (up to max_per_step) goes into one sequence of mixed
 // persistent kernels (reference tables, reference spectra, image tables,
 // alignment).  The sequence is captured once per geometry as a hipGraph and
 // replayed; each replay reads new descriptor contents that were copied into a
@@ -608,7 +608,8 @@ void scheduler(Server *s) {
                 Req *q = s->reqs[tk].get();
                 const bool same = q->geo.L == g0.L && q->geo.n == g0.n && q->geo.Q == g0.Q &&
                                   q->geo.levels == g0.levels;
-                if (same && (int)batch.size() < sw::kMaxMix && q->err.empty()) batch.push_back(q);
+                if (same && (int)batch.size() < s->cfg.max_per_step && q->err.empty())
+                    batch.push_back(q);
                 else rest.push_back(tk);
             }
             // requests whose copy failed are finished as failures
@@ -716,6 +717,9 @@ sw_status sw_serve_start(void *ctx, const sw_serve_cfg *cfg) {
     if (!s) return fail(SW_E_NOMEM, "out of host memory");
     s->cfg = *cfg;
     if (s->cfg.max_slots <= 0 || s->cfg.max_slots > sw::kMaxMix * 4) s->cfg.max_slots = sw::kMaxMix;
+    if (s->cfg.max_per_step <= 0 || s->cfg.max_per_step > s->cfg.max_slots)
+        s->cfg.max_per_step = s->cfg.max_slots;
+    if (s->cfg.max_per_step > sw::kMaxMix) s->cfg.max_per_step = sw::kMaxMix;
     if (s->cfg.max_queue <= 0) s->cfg.max_queue = 4096;
     if (s->cfg.top_k == 0) s->cfg.top_k = s->cfg.prec == SW_PREC_BF16_SPLIT ? 4 : 1;
     if (s->cfg.top_k < 1 || s->cfg.top_k > sw::kMaxTopK) {

@@ -204,6 +204,28 @@ def test_serving_admission_by_budget_and_backpressure(api):
     c.close()
 
 
+def test_serving_steps_in_flight_match_one_step(api):
+    """max_per_step below max_slots: several steps in flight at once (the
+    next step's copies beside the current step's kernels), each request's
+    results the same as with every request in one step."""
+    reqs = [stack(128, 5 + 3 * i, 2700 + i) for i in range(7)] + [stack(64, 11, 2710)]
+    res = {}
+    for per_step in (0, 2):
+        c = api.Context(0)
+        srv = api.Server(c, hbm_budget_bytes=1 << 29, prec=1, max_slots=8, max_per_step=per_step)
+        ts = [srv.submit(r, x) for r, x in reqs]
+        got = wait_all(srv, ts)
+        res[per_step] = [got[t] for t in ts]
+        st = srv.stats()
+        assert st["completed"] == len(reqs)
+        if per_step:
+            assert st["steps"] >= 4  # at most two requests of one L per step
+        srv.stop()
+        c.close()
+    for a, b in zip(res[0], res[2]):
+        assert np.array_equal(a, b)
+
+
 def test_serving_graph_replays_match_plain_launches(api):
     reqs = [stack(64, 9, 2600 + i) for i in range(4)] + [stack(96, 6, 2610)]
     res = {}
