@@ -330,9 +330,11 @@ sw_status sw_autotune(void *ctx, const int32_t *Ls /*host*/, int32_t nL, int64_t
 /* Serving: continuous batching of alignment requests (1 reference image +
    N images each, host memory).  A scheduler thread owned by the context
    admits queued requests in arrival order while the request fits in the HBM
-   budget and a slot is free, copies its images to the device, and launches
-   all admitted requests of one geometry together through the mixed
-   persistent kernels, replayed from a captured graph; requests that arrive
+   budget and a slot is free, copies its images to the device on a copy
+   stream, and launches the admitted requests of one geometry together (at
+   most max_per_step per step) through the mixed persistent kernels,
+   replayed from a captured graph; with fewer per step than slots, the next
+   step's copies run while the current step computes; requests that arrive
    while others run are admitted as slots and memory free up, so their work
    shares launches and overlaps on the device.  Reference tables with a
    non-zero ref_key stay cached in HBM (evicted least recently used when
