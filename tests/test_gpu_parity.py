@@ -176,6 +176,26 @@ def test_end_to_end_parity(api, ctx, oracle, L, n, Q, kind):
     print(rep)
 
 
+@pytest.mark.parametrize("L,n,Q,kind", [(256, 512, 512, "clean"), (256, 512, 512, "raw"),
+                                         (96, 384, 8, "raw"), (8, 8, 8, "clean"),
+                                         (9, 24, 12, "clean")])
+def test_extreme_geometries_end_to_end(api, ctx, oracle, L, n, Q, kind):
+    """The largest admissible geometry (L = 256, n = Q = 512: the angle FFT
+    at its largest power of two, the fused tables beyond LDS), the largest
+    radix-3 angle count with the fewest quantiles, and the smallest sides
+    (L = 8, odd L = 9): images to results against the oracle."""
+    ref, imgs = inputs(kind, L, 3, 950 + L + n)
+    rq, ra = api.tables(ctx, dev(ref[None]), n, Q)
+    iq, ia = api.tables(ctx, dev(imgs), n, Q)
+    res, _ = api.align_batch(ctx, rq, ra, iq, ia, L)
+    g = api.unpack_results(res)
+    orq, ora = oracle.tables(ref, n, Q)
+    oiq, oia = oracle.tables(imgs, n, Q)
+    o = oracle_results(oracle, orq, ora, oiq, oia, L)
+    assert np.abs(iq.cpu().numpy() - oiq).max() < 2e-6 * max(1.0, np.abs(oiq).max())
+    parity.check(g, o, L, parity.TAU_FP32, o["curve"])
+
+
 def test_single_pair_workload(api, ctx, oracle):
     """The single-pair workload (L = 64, 5 blobs, +-4 px) end to end."""
     w = synth.workload(0)
