@@ -140,15 +140,22 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
     }
     wave_lds_fence();  // rows of this wave only: no block barrier
 
-    // ---- inverse DFT over w on MFMA (FP32): C[p][l] = sum_k S[p][k] T[k][l]
-    // with k = 2w (real part) or 2w + 1 (imaginary part) and
+    // ---- inverse DFT over w on the bf16 MFMA with split operands:
+    // C[p][l] = sum_k S[p][k] T[k][l] with k = 2w (real part) or 2w + 1
+    // (imaginary part) and
     //   T[2w][l] = c_w cos(2 pi w l / N) / N,  T[2w + 1][l] = -c_w sin(2 pi w l / N) / N,
-    // c_w = 1 at w = 0 and N/2 (whose imaginary rows are 0), else 2.  Wave v
-    // owns pairs 64 v .. 64 v + 63 (four 16-pair row tiles) and writes C over
-    // its own S rows; only this wave reads or writes them from here on.
+    // c_w = 1 at w = 0 and N/2 (whose imaginary rows are 0), else 2.  Each
+    // FP32 operand x is split into bf16 parts x = hi + lo (hi = x rounded,
+    // lo = the rest rounded), and C = S_hi T_hi + S_hi T_lo + S_lo T_hi with
+    // FP32 accumulation: about 16 bits of the operands, far finer than the
+    // bf16 spectra S came from (the lags only feed the candidate list; the
+    // rescore is exact FP32).  Wave v owns pairs 64 v .. 64 v + 63 (four
+    // 16-pair row tiles) and writes C over its own S rows; only this wave
+    // reads or writes them from here on.  Lane l holds K entries
+    // 32 st + 8 (l / 16) .. + 7 of step st for row / column l % 16.
     {
-        constexpr int KS = (2 * Wn + 3) / 4;  // k-steps of four
-        constexpr int CT = N / 16;            // lag tiles
+        constexpr int KS = (2 * Wn + 31) / 32;  // k-steps of 32
+        constexpr int CT = N / 16;              // lag tiles
         const int kq = lane >> 4, jl = lane & 15;
         f32x4_t acc[4][CT];
 #pragma unroll
@@ -156,22 +163,52 @@ __global__ __launch_bounds__(256) void k_corr_mfma(const uint32_t *__restrict__ 
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         const float *Srow = Sl + (64 * wave + jl) * SS;
-        for (int st = 0; st < KS; ++st) {
-            const int k = 4 * st + kq;  // this lane's k for A (pair jl) and B (lag jl)
-            const bool kin = k < 2 * Wn;
-            float av[4];
+        auto split = [](float x, __bf16 &hi, __bf16 &lo) {
+            hi = (__bf16)x;
+            lo = (__bf16)(x - (float)hi);
+        };
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt) av[rt] = kin ? Srow[16 * rt * SS + k] : 0.f;
-            const int w = k >> 1;
-            const bool edge = w == 0 || w == N / 2;
-            const float cw = edge ? 1.f / (float)N : 2.f / (float)N;
+        for (int st = 0; st < KS; ++st) {
+            const int k0 = 32 * st + 8 * kq;  // this lane's first k
+            bf16x8_t ah[4], al[4];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = k0 + e;
+                    __bf16 h, l;
+                    split(k < 2 * Wn ? Srow[16 * rt * SS + k] : 0.f, h, l);
+                    ah[rt][e] = h;
+                    al[rt][e] = l;
+                }
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                const float2 e = tw[(w * (16 * ct + jl)) & (N - 1)];  // (cos, -sin)
-                const float bv = !kin ? 0.f : (k & 1) ? (edge ? 0.f : e.y * cw) : e.x * cw;
+                bf16x8_t bh, bl;
 #pragma unroll
-                for (int rt = 0; rt < 4; ++rt)
-                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt], bv, acc[rt][ct], 0, 0, 0);
+                for (int q = 0; q < 4; ++q) {  // k = k0 + 2q (real), k0 + 2q + 1 (imaginary)
+                    const int w = (k0 >> 1) + q;
+                    float re = 0.f, im = 0.f;
+                    if (2 * w < 2 * Wn) {
+                        const bool edge = w == 0 || w == N / 2;
+                        const float cw = edge ? 1.f / (float)N : 2.f / (float)N;
+                        const float2 e = tw[(w * (16 * ct + jl)) & (N - 1)];  // (cos, -sin)
+                        re = e.x * cw;
+                        im = edge ? 0.f : e.y * cw;
+                    }
+                    __bf16 h, l;
+                    split(re, h, l);
+                    bh[2 * q] = h;
+                    bl[2 * q] = l;
+                    split(im, h, l);
+                    bh[2 * q + 1] = h;
+                    bl[2 * q + 1] = l;
+                }
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bh, acc[rt][ct], 0, 0, 0);
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rt], bl, acc[rt][ct], 0, 0, 0);
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rt], bh, acc[rt][ct], 0, 0, 0);
+                }
             }
         }
 #pragma unroll
