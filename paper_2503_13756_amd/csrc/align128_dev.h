@@ -489,7 +489,8 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
 // The same alignment with one pair per wave: the transforms and the spectral
 // dot as in align128_pair, the eight lane groups' partial sums added through
 // the wave's LDS, lags l and l + 64 per lane, the top K lags by a butterfly
-// over the lanes, and the FP32 rescore from image rows staged 16 at a time.
+// over the lanes, and the FP32 rescore from image rows copied to LDS eight
+// at a time, double-buffered.
 // No block barrier: the waves of a block run independent pairs.  xb: the
 // wave's kA128WaveElems float2 of LDS; tw: the angle table in LDS.
 constexpr int kA128WaveElems = 8 * 8 * kA128Stride;
@@ -634,7 +635,7 @@ __device__ void align128_wave(const A128Job &job, float2 *xb, const float2 *tw) 
     }
 
     // --- FP32 rescore of the candidates: direct residual sum, lane columns
-    // k = 2 lane, 2 lane + 1, rows staged 16 at a time
+    // k = 2 lane, 2 lane + 1
     float2 cs[kMaxTopK];
     float sh0[kMaxTopK], sh1[kMaxTopK], part[kMaxTopK];
     const int k0 = 2 * lane;
