@@ -72,7 +72,8 @@ typedef enum { SW_LEVELS_MIDPOINT = 0, SW_LEVELS_LEFT = 1 } sw_levels;
    max-sliced objective, rotation only (extended alignment results: the
    largest per-angle W2^2 instead of the mean, M(l) = max_k (1/Q) sum_j
    (U[j][k] - V[j][(k+l) mod n])^2; the shift is reported as 0).  The
-   max-sliced mode takes n_angles = 64 or 128; its top_k lags (from an FP32
+   max-sliced mode takes n_angles a multiple of 16 up to 128 (16, 32, 48,
+   64, 96, 128); its top_k lags (from an FP32
    matrix-core estimate of every lag) are rescored as direct residuals, and
    the curve holds the estimate. */
 typedef enum { SW_MODE_ROT_TRANS = 0, SW_MODE_ROT_ONLY = 1, SW_MODE_MAX_SLICED = 2 } sw_mode;

@@ -9,8 +9,9 @@
 // are then rescored as direct residual sums (no cancellation), and the
 // smallest rescored value wins (ties to the smaller lag).
 //
-// One 4-wave block per pair.  Wave w owns the row blocks a = w, w + 4 of the
-// 16 x 16 tiles of C and all column blocks; V streams through LDS in chunks
+// One 4-wave block per pair, n a multiple of 16 up to 128.  Wave w owns the
+// row blocks a = w, w + 4 (those below n / 16) of the 16 x 16 tiles of C and
+// all column blocks; V streams through LDS in chunks
 // of 64 rows (row stride n + 16 floats, so the four rows of a B fragment fall
 // in distinct banks), U comes straight from global memory (the reference
 // tables are L2-resident).
@@ -22,7 +23,8 @@ typedef float f32x4m __attribute__((ext_vector_type(4)));
 
 template <int NN>
 __global__ __launch_bounds__(256) void k_align_msw(PairArgs a, Geo g) {
-    constexpr int NB = NN / 16, RA = NB >= 4 ? NB / 4 : 1, KC = 64, VS = NN + 16;
+    static_assert(NN % 16 == 0 && NN <= 128, "n a multiple of 16 up to 128");
+    constexpr int NB = NN / 16, RA = (NB + 3) / 4, KC = 64, VS = NN + 16;
     __shared__ float vs[KC * VS];
     __shared__ float uu[NN], vv[NN];
     __shared__ unsigned Dbits[NN];
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(256) void k_align_msw(PairArgs a, Geo g) {
 #pragma unroll
                 for (int s = 0; s < KC / 4; ++s) {
                     const int j = j0 + 4 * s + lk;
-                    afr[ra][s] = j < Q ? U[(int64_t)j * NN + 16 * ab + li] : 0.f;
+                    afr[ra][s] = j < Q && ab < NB ? U[(int64_t)j * NN + 16 * ab + li] : 0.f;
                 }
             }
 #pragma unroll
@@ -121,13 +123,15 @@ __global__ __launch_bounds__(256) void k_align_msw(PairArgs a, Geo g) {
 #pragma unroll
         for (int ra = 0; ra < RA; ++ra) {
             const int ab = wave + 4 * ra;
+            if (ab >= NB) continue;  // wave-uniform
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int k = 16 * ab + 4 * lk + e, kp = 16 * b + li;
                     const float v = fmaxf((uu[k] + vv[kp] - 2.f * acc[ra][b][e]) * invQ, 0.f);
-                    atomicMax(&Dbits[(kp - k + NN) & (NN - 1)], __float_as_uint(v));
+                    const int lag = kp >= k ? kp - k : kp - k + NN;
+                    atomicMax(&Dbits[lag], __float_as_uint(v));
                 }
             }
         }
@@ -163,16 +167,18 @@ __global__ __launch_bounds__(256) void k_align_msw(PairArgs a, Geo g) {
     }
     __syncthreads();
     // rescore: direct FP32 column residuals at every candidate, max over k
+    // (threads past TPC n idle)
     constexpr int TPC = 256 / NN;  // threads per column
     const int k = t % NN, part = t / NN;
     for (int c = 0; c < K; ++c) {
         const int l = cand[c];
-        const float *Vc = V + ((k + l) & (NN - 1));
+        const float *Vc = V + (k + l < NN ? k + l : k + l - NN);
         float s = 0.f;
-        for (int j = part; j < Q; j += TPC) {
-            const float d = U[(int64_t)j * NN + k] - Vc[(int64_t)j * NN];
-            s = fmaf(d, d, s);
-        }
+        if (part < TPC)
+            for (int j = part; j < Q; j += TPC) {
+                const float d = U[(int64_t)j * NN + k] - Vc[(int64_t)j * NN];
+                s = fmaf(d, d, s);
+            }
         colred[t] = s;
         __syncthreads();
         if (t < NN) {
@@ -182,7 +188,7 @@ __global__ __launch_bounds__(256) void k_align_msw(PairArgs a, Geo g) {
         }
         __syncthreads();
         if (wave == 0) {
-            float m = fmaxf(colred[lane], NN > 64 ? colred[lane + 64] : 0.f);
+            float m = fmaxf(lane < NN ? colred[lane] : 0.f, lane + 64 < NN ? colred[lane + 64] : 0.f);
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
             if (lane == 0) cval[c] = m * invQ;
@@ -205,17 +211,25 @@ __global__ __launch_bounds__(256) void k_align_msw(PairArgs a, Geo g) {
     }
 }
 
-bool msw_supported(Geo g) { return g.n == 64 || g.n == 128; }
+bool msw_supported(Geo g) { return g.n % 16 == 0 && g.n <= 128; }
+
+template <int NN>
+static void launch_msw_t(const PairArgs &a, Geo g, int64_t P, hipStream_t s) {
+    hipLaunchKernelGGL((k_align_msw<NN>), dim3((unsigned)P), dim3(256), 0, s, a, g);
+}
 
 hipError_t launch_align_msw(const PairArgs &a, Geo g, hipStream_t s) {
     const int64_t P = a.pairs ? a.n_pairs : a.n_ref * a.n_img;
     if (P <= 0) return hipSuccess;
-    if (g.n == 64)
-        hipLaunchKernelGGL((k_align_msw<64>), dim3((unsigned)P), dim3(256), 0, s, a, g);
-    else if (g.n == 128)
-        hipLaunchKernelGGL((k_align_msw<128>), dim3((unsigned)P), dim3(256), 0, s, a, g);
-    else
-        return hipErrorInvalidValue;
+    switch (g.n) {  // the admissible n (factors 2 and 3) that are multiples of 16 up to 128
+    case 16: launch_msw_t<16>(a, g, P, s); break;
+    case 32: launch_msw_t<32>(a, g, P, s); break;
+    case 48: launch_msw_t<48>(a, g, P, s); break;
+    case 64: launch_msw_t<64>(a, g, P, s); break;
+    case 96: launch_msw_t<96>(a, g, P, s); break;
+    case 128: launch_msw_t<128>(a, g, P, s); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

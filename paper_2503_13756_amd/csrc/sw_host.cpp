@@ -1131,7 +1131,8 @@ static sw_status align_batch_impl(void *ctx, const sw_batch *b, sw_result *out, 
         b->mode != SW_MODE_MAX_SLICED)
         return fail(SW_E_INVALID, "mode = %d is not a sw_mode value", b->mode);
     if (b->mode == SW_MODE_MAX_SLICED && !sw::msw_supported(geo))
-        return fail(SW_E_UNSUPPORTED, "max-sliced alignment needs n_angles = 64 or 128, got %d",
+        return fail(SW_E_UNSUPPORTED,
+                    "max-sliced alignment needs n_angles a multiple of 16 up to 128, got %d",
                     geo.n);
     if (b->prec != SW_PREC_FP32 && b->prec != SW_PREC_BF16_SPLIT)
         return fail(SW_E_INVALID, "prec = %d is not a sw_precision value", b->prec);

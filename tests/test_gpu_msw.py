@@ -48,7 +48,8 @@ def curve_tol(rq, iq):
     return 1e-5 * e / Q
 
 
-@pytest.mark.parametrize("L,n,Q", [(64, 64, 64), (128, 128, 128), (96, 128, 96), (48, 64, 40)])
+@pytest.mark.parametrize("L,n,Q", [(32, 16, 16), (40, 32, 24), (48, 48, 48), (64, 64, 64),
+                                   (96, 96, 96), (128, 128, 128), (96, 128, 96), (48, 64, 40)])
 @pytest.mark.parametrize("top_k", [1, 4])
 def test_msw_parity_on_oracle_tables(api, ctx, oracle, L, n, Q, top_k):
     """Alignment stage alone on the oracle's tables rounded to FP32: the lag
@@ -69,7 +70,7 @@ def test_msw_parity_on_oracle_tables(api, ctx, oracle, L, n, Q, top_k):
     assert np.abs(c - o["curve"]).max() < curve_tol(rq32, iq32)
 
 
-@pytest.mark.parametrize("L,n,Q", [(64, 64, 64), (128, 128, 128)])
+@pytest.mark.parametrize("L,n,Q", [(64, 64, 64), (128, 128, 128), (96, 96, 96), (39, 48, 48)])
 def test_msw_end_to_end_and_pair_list(api, ctx, oracle, L, n, Q):
     """Images -> GPU tables -> max-sliced alignment against the oracle from the
     same images, on a pair list with a self pair and an out-of-range index."""
@@ -90,7 +91,8 @@ def test_msw_end_to_end_and_pair_list(api, ctx, oracle, L, n, Q):
 
 def test_msw_quarter_turns_and_status(api, ctx):
     """90-degree rotations give l = m n/4 and distance 0; zero and non-finite
-    images keep their status; other n are refused."""
+    images keep their status; n that are not multiples of 16 up to 128 are
+    refused."""
     from paper_2503_13756_amd._abi import SwError
 
     L = n = Q = 64
@@ -106,6 +108,7 @@ def test_msw_quarter_turns_and_status(api, ctx):
     assert list(g["status"]) == [0, 0, 0, 1, 2]
     assert sorted(int(x) % (n // 4) for x in g["rot_index"][:3]) == [0, 0, 0]
     assert np.all(np.abs(g["sw2sq"][:3]) < 1e-9)
-    q96, a96 = api.tables(ctx, dev(stack[:1]), 96, 96)
-    with pytest.raises(SwError):
-        api.align_batch(ctx, q96, a96, q96, a96, L, mode=MSW)
+    for nn in (24, 192):
+        qx, ax = api.tables(ctx, dev(stack[:1]), nn, 32)
+        with pytest.raises(SwError):
+            api.align_batch(ctx, qx, ax, qx, ax, L, mode=MSW)
