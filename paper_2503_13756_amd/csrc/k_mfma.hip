@@ -264,7 +264,7 @@ __device__ __forceinline__ float wave_sum_f(float v) {
     return (r0 + r1) + (r2 + r3);
 }
 
-// Rescore: grid (ceil(n_img / 8), ceil(n_ref / TR)), 512 threads; wave w owns
+// Rescore: grid (ceil(n_img / (NT / 64)), ceil(n_ref / TR)), NT threads; wave w owns
 // image g0 + w and walks the references r0 .. r1 - 1.  Lane layout: chunk
 // p = lane % CPR of four columns (CPR = N / 4 chunks per row) in rows
 // jr + RPS m (jr = lane / CPR, RPS = 64 / CPR), so the image's table is
@@ -275,18 +275,18 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // elements at a fixed offset per row step.  Lane c < top_k carries candidate
 // c (its lag, translation and objective); the next reference's table and
 // candidates are fetched into registers while this one is summed.
-template <int N, int KMAX>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rescore_tiles(
+template <int N, int KMAX, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rescore_tiles(
     const float *__restrict__ ref_qt, const double *__restrict__ ref_aux, int64_t n_ref,
     const float *__restrict__ img_qt, const double *__restrict__ img_aux, int64_t n_img, int TR,
     int mode, int top_k, int L, const int16_t *__restrict__ cand, const double2 *__restrict__ tw64,
     Result *__restrict__ out) {
     constexpr int Q = N, CPR = N / 4, RPS = 64 / CPR, STEPS = Q / RPS;
-    constexpr int COPY = Q * N, NCH = Q * N / 4, CH = (NCH + 511) / 512;
+    constexpr int COPY = Q * N, NCH = Q * N / 4, CH = (NCH + NT - 1) / NT;
     static_assert(KMAX <= 64 && STEPS * RPS == Q, "rescore layout");
     extern __shared__ __align__(16) float lds[];  // [4][Q][N]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t g = (int64_t)blockIdx.x * 8 + wave;
+    const int64_t g = (int64_t)blockIdx.x * (NT / 64) + wave;
     const bool live = g < n_img;  // wave-uniform
     const int64_t gc = live ? g : n_img - 1;
     const int64_t r0 = (int64_t)blockIdx.y * TR;
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         const float4 *U = (const float4 *)(ref_qt + r * (int64_t)COPY);
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            const int c = t + 512 * i;
+            const int c = t + NT * i;
             if (c < NCH) {
                 ucur[i] = U[c];
                 if constexpr (!kRor) {
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
         __syncthreads();  // every wave is done with the previous table
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
-            const int c = t + 512 * i;
+            const int c = t + NT * i;
             if (c < NCH) {
                 const float4 u = ucur[i];
                 float4 v;
@@ -431,6 +431,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 
 bool mfma_path_supported(Geo g) { return g.Q == g.n && (g.n == 32 || g.n == 64); }
 
+// Threads of a rescore block: one image per wave against each staged
+// reference table, so 16 images share each staging of the four rotated
+// copies (64 KiB of LDS at n = 64, one block per CU either way); 2,000 x
+// 2,000 at L = 64: 5.35 ms with 512 threads, 5.27 ms with 1024.
+constexpr int kRescoreThreads = 1024;
+
 template <int N>
 static hipError_t launch_mfma_t(const MfmaArgs &a, Geo g, const AngleTable &t, hipStream_t s) {
     constexpr int KMAX = 4;
@@ -449,19 +455,20 @@ static hipError_t launch_mfma_t(const MfmaArgs &a, Geo g, const AngleTable &t, h
                        a.img_aux, t.d32, a.cand, (int)slice);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // blocks of eight images x TR references; TR chosen so that the grid
+    // blocks of NT / 64 images x TR references; TR chosen so that the grid
     // fills the resident slots in as few, as full, rounds as possible
+    constexpr int NT = kRescoreThreads, IPB = NT / 64;
     static const int slots = [] {
-        (void)hipFuncSetAttribute((const void *)k_rescore_tiles<N, KMAX>,
+        (void)hipFuncSetAttribute((const void *)k_rescore_tiles<N, KMAX, NT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 4 * N * N * 4);
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_rescore_tiles<N, KMAX>,
-                                                        512, sizeof(float) * 4 * N * N);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, (const void *)k_rescore_tiles<N, KMAX, NT>, NT, sizeof(float) * 4 * N * N);
         return (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
     }();
-    const int64_t gx = (a.n_img + 7) / 8;
+    const int64_t gx = (a.n_img + IPB - 1) / IPB;
     int64_t best_gy = 1;
     double best_eff = -1.0;
     for (int64_t gy = 1; gy <= a.n_ref && (gy == 1 || gx * gy <= 4 * (int64_t)slots); ++gy) {
@@ -476,7 +483,7 @@ static hipError_t launch_mfma_t(const MfmaArgs &a, Geo g, const AngleTable &t, h
     const int TR = (int)((a.n_ref + best_gy - 1) / best_gy);
     const int gy = (int)((a.n_ref + TR - 1) / TR);
     const size_t lds2 = sizeof(float) * 4 * N * N;
-    hipLaunchKernelGGL((k_rescore_tiles<N, KMAX>), dim3((unsigned)gx, (unsigned)gy), dim3(512), lds2, s, a.ref_qt,
+    hipLaunchKernelGGL((k_rescore_tiles<N, KMAX, NT>), dim3((unsigned)gx, (unsigned)gy), dim3(NT), lds2, s, a.ref_qt,
                        a.ref_aux, a.n_ref, a.img_qt, a.img_aux, a.n_img, TR, a.mode, a.top_k, g.L,
                        a.cand, t.d64, a.out);
     return hipGetLastError();
