@@ -205,7 +205,9 @@ sw_status sw_tables_rf(void *ctx, const float *img, int64_t N, const sw_geom *g 
    mass up to the clipped lobes).  The slices are evaluated by a type-2
    NUFFT (grid oversampled by 2, exponential-of-semicircle kernel of width
    7: relative error about 1e-6 before FP32 rounding), two slices per FP32
-   inverse FFT.  L must be a power of two.  Uses the context scratch.
+   inverse FFT.  L must be even with prime factors 2 and 3 only (8, 12, 16,
+   18, 24, ..., 96, ..., 192, 256; mixed-radix transforms of lengths L and
+   2L).  Uses the context scratch.
    img: [N][L][L] float32, pmf: [N][n][L] float32.  An image holding a
    non-finite value yields an all-NaN projection. */
 sw_status sw_project_fourier(void *ctx, const float *img, int64_t N, const sw_geom *g /*host*/,

@@ -86,7 +86,7 @@ def _angles(theta, n):
 
 def project_fourier(ctx: Context, imgs: torch.Tensor, n: int, stream=None, out=None, theta=None):
     """sw_project_fourier: [N, L, L] float32 -> [N, n, L] float32 projections
-    by the Fourier slice theorem (L a power of two); with theta (n radians,
+    by the Fourier slice theorem (L even, prime factors 2 and 3); with theta (n radians,
     host) sw_project_fourier_at at those directions."""
     _need(imgs, torch.float32, "imgs")
     N, L = imgs.shape[0], imgs.shape[-1]

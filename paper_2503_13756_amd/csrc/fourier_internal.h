@@ -5,7 +5,8 @@
 
 namespace sw {
 
-// Fourier-slice projector (k_fourier.hip): L a power of two, oversampled
+// Fourier-slice projector (k_fourier.hip): L even with factors 2 and 3
+// (lgL, lgNf: log2 of L and Nf for powers of two, else -1), oversampled
 // grid Nf = 2L, H = Nf/2 + 1 stored spectrum columns.  Tables (device,
 // context-owned): corr[j] = 1 / phihat((j - L/2) / Nf) for the interpolation
 // kernel phi, twf[k] = exp(-2 pi i k / Nf) (k < Nf), twl[k] =

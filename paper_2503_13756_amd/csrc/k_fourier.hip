@@ -22,8 +22,11 @@
 //     transform of one pixel cell; the coefficients of two slices are packed
 //     into one complex L-point inverse FFT (both results are real), scaled by
 //     h/2, clipped at zero and written with their theta + pi mirror.
-// The FFTs are Stockham transforms (radix 4, one radix-2 step for odd
-// powers of two) in LDS over a batch of sequences.
+// The FFTs are Stockham transforms in LDS over a batch of sequences: for L a
+// power of two radix 4 with one radix-2 step for odd powers, with shift and
+// mask indexing; for other L (factors 2 and 3) the mixed-radix transforms of
+// fft_dev.h, the inverse as conj(FFT(conj x)).
+#include "fft_dev.h"
 #include "fourier_internal.h"
 
 namespace sw {
@@ -31,10 +34,6 @@ namespace sw {
 namespace {
 
 constexpr int kFftFloats2 = 2048;  // float2 per FFT work buffer
-
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
 
 __device__ __forceinline__ bool in_disk_f(int L, int i, int j) {
     const int a = 2 * j - L + 1, b = 2 * i - L + 1, r = L - 2;
@@ -129,11 +128,11 @@ __device__ __forceinline__ float2 slice_point(const float2 *__restrict__ B, int 
     const float wx[kFourierW] = {e1.x, e1.y, e1.z, e1.w, e2.x, e2.y, e2.z};
     const float wy[kFourierW] = {e3.x, e3.y, e3.z, e3.w, e4.x, e4.y, e4.z};
     const float2 *col = B + (vw & 0xffff);
-    const int msk = Nf - 1;
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int a = 0; a < kFourierW; ++a) {
-        const float2 *row = col + ((u0 + a) & msk) * Hx;
+        const int u = u0 + a < Nf ? u0 + a : u0 + a - Nf;  // u0 < Nf, a < kFourierW <= Nf
+        const float2 *row = col + u * Hx;
         float2 ra = make_float2(0.f, 0.f);
 #pragma unroll
         for (int c = 0; c < kFourierW; ++c) {
@@ -148,7 +147,22 @@ __device__ __forceinline__ float2 slice_point(const float2 *__restrict__ B, int 
     return cmul(acc, make_float2(e0.z, e0.w));
 }
 
-template <int NT>
+// Multiples and quotients by a transform length: shifts for powers of two,
+// else plain arithmetic.
+template <bool POW2>
+struct Len {
+    int n, lg;
+    __device__ __forceinline__ int mul(int x) const {
+        if constexpr (POW2) return x << lg;
+        else return x * n;
+    }
+    __device__ __forceinline__ int div(int x) const {
+        if constexpr (POW2) return x >> lg;
+        else return x / n;
+    }
+};
+
+template <int NT, bool POW2>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fourier(const float *__restrict__ img, int64_t N,
                                                 FourierShape S, FourierTabs T,
                                                 float2 *__restrict__ scratch, float *__restrict__ pmf) {
@@ -171,8 +185,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     }
     float2 *R = scratch + (size_t)blockIdx.x * fourier_slot_elems(L, Nf);  // [L][H]
     float2 *B = R + (size_t)L * H;  // [Nf][Hx], column v at v + kFourierPad
-    const int GR = kFftFloats2 >> lgNf;  // transforms of length Nf per round
-    const int GS = kFftFloats2 >> lgL;   // transforms of length L per round (two slices each)
+    const Len<POW2> LF{Nf, lgNf}, LH{Nf >> 1, lgNf - 1}, LL{L, lgL};
+    const int GR = kFftFloats2 / Nf;  // transforms of length Nf per round
+    const int GS = kFftFloats2 / L;   // transforms of length L per round (two slices each)
+    // forward transforms of cnt sequences of length len (twiddles tw); the
+    // input must be complete in LDS, the result is visible to the block
+    auto fft = [&](float2 *a, float2 *b, int cnt, int len, int lg, const float2 *tw) -> float2 * {
+        if constexpr (POW2) {
+            return fft_batch<NT>(a, b, lg, cnt, tw, false);
+        } else {
+            __syncthreads();
+            return fft_rows<NT>(a, b, cnt, len, tw);
+        }
+    };
     for (int64_t g = blockIdx.x; g < N; g += gridDim.x) {
         const float *F = img + g * (int64_t)L * L;
         __syncthreads();  // previous image done with sbad and the buffers
@@ -182,8 +207,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         for (int p0 = 0; p0 < M; p0 += GR) {
             const int cnt = min(GR, M - p0);
             __syncthreads();
-            for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT) {
-                const int f = idx >> lgNf, q = idx & (Nf - 1);
+            for (int idx = threadIdx.x; idx < LF.mul(cnt); idx += NT) {
+                const int f = LF.div(idx), q = idx - LF.mul(f);
                 const int j = (q < (Nf >> 1) ? q : q - Nf) + M;
                 float2 z = make_float2(0.f, 0.f);
                 if (j >= 0 && j < L) {
@@ -196,17 +221,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                 }
                 fa[idx] = z;
             }
-            const float2 *X = fft_batch<NT>(fa, fb, lgNf, cnt, twf, false);
+            const float2 *X = fft(fa, fb, cnt, Nf, lgNf, twf);
             auto unpack = [&](int f, int v) {
-                const float2 zv = X[(f << lgNf) + v], zc = X[(f << lgNf) + ((Nf - v) & (Nf - 1))];
+                const float2 zv = X[LF.mul(f) + v], zc = X[LF.mul(f) + (v == 0 ? 0 : Nf - v)];
                 const int i = 2 * (p0 + f);
                 // Z = X_i + i X_{i+1}: X_i[v] = (Z[v] + conj Z[-v]) / 2,
                 // X_{i+1}[v] = (Z[v] - conj Z[-v]) / (2 i)
                 R[(size_t)i * H + v] = make_float2(0.5f * (zv.x + zc.x), 0.5f * (zv.y - zc.y));
                 R[(size_t)(i + 1) * H + v] = make_float2(0.5f * (zv.y + zc.y), -0.5f * (zv.x - zc.x));
             };
-            for (int idx = threadIdx.x; idx < (cnt << (lgNf - 1)); idx += NT)
-                unpack(idx >> (lgNf - 1), idx & ((Nf >> 1) - 1));
+            for (int idx = threadIdx.x; idx < LH.mul(cnt); idx += NT) {
+                const int f = LH.div(idx);
+                unpack(f, idx - LH.mul(f));
+            }
             for (int f = threadIdx.x; f < cnt; f += NT) unpack(f, Nf >> 1);  // v = Nf/2
         }
         if (bad) sbad = 1;
@@ -220,23 +247,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
             const bool p2 = (1 << lgc) == cnt;
             auto load = [&](int q, int f) {
                 const int i = (q < (Nf >> 1) ? q : q - Nf) + M;
-                fa[(f << lgNf) + q] =
+                fa[LF.mul(f) + q] =
                     (i >= 0 && i < L) ? R[(size_t)i * H + v0 + f] : make_float2(0.f, 0.f);
             };
             if (p2) {
-                for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT)
+                for (int idx = threadIdx.x; idx < LF.mul(cnt); idx += NT)
                     load(idx >> lgc, idx & (cnt - 1));
             } else {
-                for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT)
+                for (int idx = threadIdx.x; idx < LF.mul(cnt); idx += NT)
                     load(idx / cnt, idx % cnt);
             }
-            const float2 *X = fft_batch<NT>(fa, fb, lgNf, cnt, twf, false);
-            auto store = [&](int u, int f) { B[(size_t)u * Hx + kFourierPad + v0 + f] = X[(f << lgNf) + u]; };
+            const float2 *X = fft(fa, fb, cnt, Nf, lgNf, twf);
+            auto store = [&](int u, int f) { B[(size_t)u * Hx + kFourierPad + v0 + f] = X[LF.mul(f) + u]; };
             if (p2) {
-                for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT)
+                for (int idx = threadIdx.x; idx < LF.mul(cnt); idx += NT)
                     store(idx >> lgc, idx & (cnt - 1));
             } else {
-                for (int idx = threadIdx.x; idx < (cnt << lgNf); idx += NT) store(idx / cnt, idx % cnt);
+                for (int idx = threadIdx.x; idx < LF.mul(cnt); idx += NT) store(idx / cnt, idx % cnt);
             }
         }
         __syncthreads();  // B written
@@ -246,7 +273,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
             const int u = idx / (2 * kFourierPad - 1), c = idx - u * (2 * kFourierPad - 1);
             const int v = c < kFourierPad ? c - kFourierPad : (Nf >> 1) + 1 + (c - kFourierPad);
             const int vs = v < 0 ? -v : Nf - v;
-            float2 z = B[(size_t)((Nf - u) & (Nf - 1)) * Hx + kFourierPad + vs];
+            float2 z = B[(size_t)(u == 0 ? 0 : Nf - u) * Hx + kFourierPad + vs];
             z.y = -z.y;
             B[(size_t)u * Hx + kFourierPad + v] = z;
         }
@@ -262,8 +289,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
             for (int idx = threadIdx.x; idx < ns * (M + 1); idx += NT)
                 Y[idx] = slice_point(B, Nf, Hx, T.targets + 5 * ((size_t)m0 * (M + 1) + idx));
             __syncthreads();
-            for (int idx = threadIdx.x; idx < ((ns >> 1) << lgL); idx += NT) {
-                const int f = idx >> lgL, t = idx & (L - 1);
+            for (int idx = threadIdx.x; idx < LL.mul(ns >> 1); idx += NT) {
+                const int f = LL.div(idx), t = idx - LL.mul(f);
                 const int k = t < M ? t : t - L;
                 const float2 *Y1 = Y + (2 * f) * (M + 1), *Y2 = Y1 + (M + 1);
                 float2 c1 = k >= 0 ? Y1[k] : Y1[-k], c2 = k >= 0 ? Y2[k] : Y2[-k];
@@ -276,12 +303,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                     z1.y = 0.f;
                     z2.y = 0.f;
                 }
-                fa[idx] = make_float2(z1.x - z2.y, z1.y + z2.x);  // z1 + i z2
+                float2 zz = make_float2(z1.x - z2.y, z1.y + z2.x);  // z1 + i z2
+                if constexpr (!POW2) zz.y = -zz.y;  // inverse as conj(FFT(conj))
+                fa[idx] = zz;
             }
-            const float2 *X = fft_batch<NT>(fa, fb, lgL, ns >> 1, twl, true);
-            for (int idx = threadIdx.x; idx < ((ns >> 1) << lgL); idx += NT) {
-                const int f = idx >> lgL, b = idx & (L - 1);
-                const float2 z = X[idx];
+            const float2 *X;
+            if constexpr (POW2) X = fft_batch<NT>(fa, fb, lgL, ns >> 1, twl, true);
+            else X = fft(fa, fb, ns >> 1, L, lgL, twl);
+            for (int idx = threadIdx.x; idx < LL.mul(ns >> 1); idx += NT) {
+                const int f = LL.div(idx), b = idx - LL.mul(f);
+                float2 z = X[idx];
+                if constexpr (!POW2) z.y = -z.y;
                 const int m1 = m0 + 2 * f, m2 = m1 + 1;
                 const float qnan = __int_as_float(0x7fc00000);
                 const float p1 = isbad ? qnan : fmaxf(0.5f * h * z.x, 0.f);
@@ -312,17 +344,26 @@ constexpr int kFourierNT = 512;
 
 static void fourier_attr() {
     static const hipError_t attr =
-        hipFuncSetAttribute((const void *)k_fourier<kFourierNT>,
+        hipFuncSetAttribute((const void *)k_fourier<kFourierNT, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    static const hipError_t attr2 =
+        hipFuncSetAttribute((const void *)k_fourier<kFourierNT, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     (void)attr;
+    (void)attr2;
 }
+
+static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 int fourier_blocks_per_cu(int L, int Nf) {
     fourier_attr();
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fourier<kFourierNT>, kFourierNT,
-                                                     fourier_lds_bytes(L, Nf)) != hipSuccess)
-        return 1;
+    const hipError_t e =
+        is_pow2(L) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fourier<kFourierNT, true>,
+                                                                  kFourierNT, fourier_lds_bytes(L, Nf))
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fourier<kFourierNT, false>,
+                                                                  kFourierNT, fourier_lds_bytes(L, Nf));
+    if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
@@ -333,8 +374,12 @@ hipError_t launch_fourier(const float *img, int64_t N, const FourierShape &S, co
     const size_t lds = fourier_lds_bytes(S.L, S.Nf);
     fourier_attr();
     const int grid = (int)(N < slots ? N : slots);
-    hipLaunchKernelGGL((k_fourier<NT>), dim3(grid), dim3(NT), lds, s, img, N, S, T,
-                       (float2 *)scratch, pmf);
+    if (is_pow2(S.L))
+        hipLaunchKernelGGL((k_fourier<NT, true>), dim3(grid), dim3(NT), lds, s, img, N, S, T,
+                           (float2 *)scratch, pmf);
+    else
+        hipLaunchKernelGGL((k_fourier<NT, false>), dim3(grid), dim3(NT), lds, s, img, N, S, T,
+                           (float2 *)scratch, pmf);
     return hipGetLastError();
 }
 

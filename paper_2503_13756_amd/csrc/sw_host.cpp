@@ -338,7 +338,7 @@ static sw_status get_ramp_table(Ctx *ctx, int L, const float **out) {
     return SW_OK;
 }
 
-// Tables of the Fourier-slice projector for L (a power of two), laid out as
+// Tables of the Fourier-slice projector for L (even, factors 2 and 3), laid out as
 // described beside sw::FourierTabs in one device buffer.  The interpolation
 // kernel is the exponential of semicircle phi(z) = exp(beta (sqrt(1 -
 // (2z/W)^2) - 1)), |z| < W/2, on the grid oversampled by 2; its Fourier
@@ -974,18 +974,22 @@ sw_status sw_tables_rf(void *ctx, const float *img, int64_t N, const sw_geom *g,
     return SW_OK;
 }
 
-// Geometry and scratch of the Fourier-slice projector: L a power of two.
+// Geometry and scratch of the Fourier-slice projector: L even with prime
+// factors 2 and 3 only (the transforms of lengths L and 2L are mixed-radix
+// 4/3/2; powers of two take the shift-indexed kernel).
 static sw_status fourier_setup(Ctx *c, const sw::Geo &geo, int64_t N, const double *theta,
                                sw::FourierShape *S, sw::FourierTabs *T, int *slots,
                                const sw::AngleTable **dirs) {
-    const int lg = log2_exact(geo.L);
-    if (lg < 0)
-        return fail(SW_E_INVALID, "the Fourier-slice projector needs L a power of two (L = %d)",
+    if (geo.L % 2 != 0 || !only_2_3(geo.L))
+        return fail(SW_E_INVALID,
+                    "the Fourier-slice projector needs L even with prime factors 2 and 3 only "
+                    "(L = %d)",
                     geo.L);
+    const int lg = log2_exact(geo.L);  // -1 unless a power of two
     S->L = geo.L;
     S->n = geo.n;
     S->Nf = 2 * geo.L;
-    S->lgNf = lg + 1;
+    S->lgNf = lg < 0 ? -1 : lg + 1;
     S->lgL = lg;
     S->H = geo.L + 1;
     S->mirror = theta ? 0 : 1;

@@ -14,7 +14,10 @@ pytestmark = pytest.mark.gpu
 # L-point FFT (observed below 1e-6): 5e-6 of the image's largest projection value
 TOL_PROJ = 5e-6
 
-FGEOMS = [(8, 8, 8), (16, 16, 16), (32, 24, 16), (64, 64, 64), (128, 128, 128), (256, 64, 32)]
+# powers of two (shift-indexed transforms) and other even L with factors 2
+# and 3 (mixed-radix transforms of lengths L and 2L)
+FGEOMS = [(8, 8, 8), (16, 16, 16), (32, 24, 16), (64, 64, 64), (128, 128, 128), (256, 64, 32),
+          (12, 16, 8), (18, 16, 16), (24, 24, 24), (48, 48, 48), (96, 96, 96), (192, 48, 24)]
 
 
 @pytest.fixture(scope="module")
@@ -117,16 +120,18 @@ def test_fourier_mass_half_turn_and_edge_cases(api, ctx):
 
 
 def test_fourier_rejects_other_sizes(api, ctx):
-    """L must be a power of two: other sizes are refused with an error, no
-    launch."""
-    imgs = synth.uniform_images(3, 24, 2)
-    with pytest.raises(RuntimeError, match="power of two"):
-        api.project_fourier(ctx, dev(imgs), 24)
+    """L must be even with prime factors 2 and 3: other sizes (odd, or with a
+    factor 5) are refused with an error, no launch."""
+    for L in (27, 40):
+        imgs = synth.uniform_images(3, L, 2)
+        with pytest.raises(RuntimeError, match="factors 2 and 3"):
+            api.project_fourier(ctx, dev(imgs), 24)
 
 
 @pytest.mark.parametrize("L,n,Q,kind", [(32, 32, 32, "clean"), (64, 64, 64, "clean"),
                                         (128, 128, 128, "clean"), (64, 64, 64, "raw"),
-                                        (128, 128, 128, "raw")])
+                                        (128, 128, 128, "raw"), (96, 96, 96, "clean"),
+                                        (48, 48, 48, "raw")])
 def test_fourier_tables_and_alignment(api, ctx, oracle, L, n, Q, kind):
     """Images -> Fourier-slice tables -> alignment on the GPU against the
     oracle from the same images: tables, rotation (tie-aware), shift and
@@ -145,7 +150,7 @@ def test_fourier_tables_and_alignment(api, ctx, oracle, L, n, Q, kind):
 
 
 # ---------------------------------------------------------------- explicit angles, Monte-Carlo SW2
-@pytest.mark.parametrize("L,n", [(16, 16), (64, 48), (128, 128)])
+@pytest.mark.parametrize("L,n", [(16, 16), (64, 48), (128, 128), (96, 64)])
 def test_fourier_at_random_angles_parity(api, ctx, oracle, L, n):
     """Slices at sorted random directions (each computed on its own, no
     half-turn mirror) against the oracle's exact DFT at the same angles."""
