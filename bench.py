@@ -47,8 +47,9 @@ KERNEL_SOURCES = {
     "k_tables2": ["k_tables.hip", "proj2_dev.h", "proj_dev.h", "quant_dev.h", "sw_internal.h"],
     "k_project": ["k_project.hip", "proj_dev.h", "sw_internal.h"],
     "k_quantile": ["k_quantile.hip", "quant_dev.h", "sw_internal.h"],
-    "k_align128w": ["k_align128.hip", "align128_dev.h", "align_dev.h", "sw_internal.h"],
-    "k_spectrum": ["k_align.hip", "align_dev.h", "sw_internal.h"],
+    "k_align128w": ["k_align128.hip", "align128_dev.h", "align_dev.h", "fft_dev.h",
+                    "sw_internal.h"],
+    "k_spectrum": ["k_align.hip", "align_dev.h", "fft_dev.h", "sw_internal.h"],
     "k_corr_mfma": ["k_mfma.hip", "sw_internal.h"],
     "k_rescore_tiles": ["k_mfma.hip", "sw_internal.h"],
 }
