@@ -121,6 +121,7 @@ __device__ float2 *fft_batch(float2 *a, float2 *b, int lg, int cnt, const float2
 // transform); the kW x-weights; the kW y-weights.  Taps are rows
 // (u0 + a) mod Nf, columns v0 - kFourierPad + c; with conj the kernel was
 // evaluated at the mirrored point and the sum is conjugated.
+template <bool POW2>
 __device__ __forceinline__ float2 slice_point(const float2 *__restrict__ B, int Nf, int Hx,
                                               const float4 *__restrict__ e) {
     const float4 e0 = e[0], e1 = e[1], e2 = e[2], e3 = e[3], e4 = e[4];
@@ -131,7 +132,9 @@ __device__ __forceinline__ float2 slice_point(const float2 *__restrict__ B, int 
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int a = 0; a < kFourierW; ++a) {
-        const int u = u0 + a < Nf ? u0 + a : u0 + a - Nf;  // u0 < Nf, a < kFourierW <= Nf
+        int u;  // (u0 + a) mod Nf: u0 < Nf, a < kFourierW <= Nf
+        if constexpr (POW2) u = (u0 + a) & (Nf - 1);
+        else u = u0 + a < Nf ? u0 + a : u0 + a - Nf;
         const float2 *row = col + u * Hx;
         float2 ra = make_float2(0.f, 0.f);
 #pragma unroll
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         for (int m0 = 0; m0 < nsl; m0 += 2 * GS) {
             const int ns = min(2 * GS, nsl - m0);  // even: n is a multiple of 8
             for (int idx = threadIdx.x; idx < ns * (M + 1); idx += NT)
-                Y[idx] = slice_point(B, Nf, Hx, T.targets + 5 * ((size_t)m0 * (M + 1) + idx));
+                Y[idx] = slice_point<POW2>(B, Nf, Hx, T.targets + 5 * ((size_t)m0 * (M + 1) + idx));
             __syncthreads();
             for (int idx = threadIdx.x; idx < LL.mul(ns >> 1); idx += NT) {
                 const int f = LL.div(idx), t = idx - LL.mul(f);
