@@ -47,8 +47,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
 // stay in registers until the strips are done; then each image in turn
 // writes its PMF table into the region and inverts it.  Results are bitwise
 // those of k_tables.  Only for geometries with one task group of at most six
-// tasks per wave.  QM: the column inversion compiled (quant_mode_for(L)); the
-// second image's projections are live across the first image's phase.
+// tasks per wave.  QM: the column inversion compiled (quant_mode_for(L)).
+// With five or six tasks per wave the second image's projections would not
+// fit the registers beside the first image's quantile phase: they wait in
+// the second image's output table (which the host guarantees holds them,
+// kParkFloats) and come back before its own phase.
+template <int NT, int TPW>
+constexpr int kParkFloats = TPW >= 5 ? TPW * 4 * NT : 0;
+
 template <int NT, int TPW, int QM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_tables2(
     const float *__restrict__ img, int64_t N, TablesShape T, const float2 *__restrict__ d32,
@@ -66,12 +72,28 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     const float *F[2] = {img + g0 * (int64_t)L * L, img + (g0 + nimg - 1) * (int64_t)L * L};
     float acc[2][TPW][4];
     int bad[2];
-    project_images2<NT, TPW, 2>(F, nimg, P, d32, region, 0, acc, bad);
+    // the slot table sits in the column-sum area until the quantile phase
+    project_images2<NT, TPW, 2>(F, nimg, P, d32, region, (float4 *)colS, 0, acc, bad);
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float *park = qt + (g0 + 1) * (int64_t)Q * n + threadIdx.x;
+    if (kParkFloats<NT, TPW> > 0 && nimg == 2) {
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) park[(4 * t + v) * NT] = acc[1][t][v];
+    }
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
         if (g < nimg) {  // block-uniform
+            if (kParkFloats<NT, TPW> > 0 && g == 1) {
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int t = 0; t < TPW; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[1][t][v] = park[(4 * t + v) * NT];
+            }
             __syncthreads();  // strips, or the previous image's PMF, no longer read
+                              // (and every parked value is back)
             if (!bad[g])
                 emit_outputs<TPW>(P, 0, wave, NW, lane, acc[g],
                                   [&](int k, int b, float v) { region[k * L + b] = v; });
@@ -238,11 +260,14 @@ hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t
     T.P.trow = pp.trow;
     if (lds != 0 && lds <= 79 * 1024) {
         const int w = tasks_per_wave(T.P.ntasks, 512);
-        if (per_block == 2 && T.region_floats * 4 >= 2 * kImg2Bytes) {
+        if (per_block == 2 && T.region_floats * 4 >= 2 * kImg2Bytes && s4_supported(g.L)) {
+            const int64_t table = (int64_t)g.Q * g.n;
             if (w <= 2) return launch_tables2_t<512, 2>(img, N, T, lds, t, qt, aux, s);
             if (w <= 4) return launch_tables2_t<512, 4>(img, N, T, lds, t, qt, aux, s);
-            if (w <= 5) return launch_tables2_t<512, 5>(img, N, T, lds, t, qt, aux, s);
-            if (w <= 6) return launch_tables2_t<512, 6>(img, N, T, lds, t, qt, aux, s);
+            if (w <= 5 && table >= kParkFloats<512, 5>)
+                return launch_tables2_t<512, 5>(img, N, T, lds, t, qt, aux, s);
+            if (w <= 6 && table >= kParkFloats<512, 6>)
+                return launch_tables2_t<512, 6>(img, N, T, lds, t, qt, aux, s);
         }
         if (w <= 2) return launch_tables_t<512, 2>(img, N, T, lds, t, qt, aux, s);
         if (w <= 4) return launch_tables_t<512, 4>(img, N, T, lds, t, qt, aux, s);

@@ -10,11 +10,11 @@
 //
 // Strip layout (per image, R strip rows of P positions, 16 bytes each):
 // position p = j + 2 of strip row r (image row i = i0 + r) holds the four
-// values the four angles read at column j,
-//   kind 0: F[i][j]          (theta)
-//   kind 1: F[j][i]          (pi/2 - theta: the transposed image)
-//   kind 2: F[i][L-1-j]      (pi - theta: the mirrored row)
-//   kind 3: F[L-1-j][i]      (pi/2 + theta: the mirrored transposed image)
+// values the four angles read at column j, in the order
+//   F[i][j]          (theta)
+//   F[i][L-1-j]      (pi - theta: the mirrored row)
+//   F[j][i]          (pi/2 - theta: the transposed image)
+//   F[L-1-j][i]      (pi/2 + theta: the mirrored transposed image)
 // each clipped at 0 and masked to the disk, zero for j outside [0, L).  The
 // three pixels of a line in one row are positions j2, j2 + 1, j2 + 2
 // (j2 = j0 + 2, j0 the first column of the hat), so one address serves all
@@ -23,6 +23,13 @@
 // formed in the order of proj_dev.h (w0 term first), and a row's line
 // position depends only on its image row, so the projections are bitwise
 // those of the one-image kernels.
+//
+// Staging goes by mirrored pairs: a pixel and its mirror image in the row
+// (F[i][j], F[i][L-1-j]) fill the first half of positions j + 2 and
+// L + 1 - j (in swapped order), and the column pair (F[j][i], F[L-1-j][i])
+// the second half of the same positions, so each loaded pair is two 8-byte
+// LDS writes; both pixels of a pair lie at the same distance from the centre,
+// so one disk test serves both.
 #pragma once
 #include "proj_dev.h"
 
@@ -33,98 +40,217 @@ constexpr int kImg2Bytes = 32768;  // strips of the second image: half the 64 Ki
 // Positions per strip row: j = -2 .. L + 2, odd so that consecutive rows
 // start in different banks.
 __host__ __device__ inline int s4_positions(int L) { return (L + 5) | 1; }
-// Strip rows per image that fit kImg2Bytes.
+// Column pairs per row: j < ceil(L / 2) (an odd L's middle column pairs with
+// itself).
+__host__ __device__ inline int s4_pairs(int L) { return (L + 1) >> 1; }
+// Strip rows per image: as many as fit kImg2Bytes, at most twice the rows one
+// pass of NT threads covers (so that two passes stage any strip).  With this
+// bound two passes also cover the column pairs for every L <= 1024
+// (ceil(L/2) <= NT for NT = 512).
+template <int NT = 512>
 __host__ __device__ inline int s4_rows(int L) {
-    const int r = kImg2Bytes / (16 * s4_positions(L));
-    return r < L ? r : L;
+    int r = kImg2Bytes / (16 * s4_positions(L));
+    if (r > L) r = L;
+    const int cap = 2 * (NT / s4_pairs(L));
+    return r < cap ? r : cap;
 }
+// Whether the two-image staging covers L with 512-thread blocks.
+__host__ __device__ inline bool s4_supported(int L) { return L >= 2 && s4_pairs(L) <= 512; }
 
-// Staging entries per kind a thread handles per strip (at most R L of them
-// per kind, R L <= kImg2Bytes / 16).
-template <int NT>
-constexpr int s4_groups() {
-    return (kImg2Bytes / 16 + NT - 1) / NT;
-}
-
-template <int NT, int IMG>
+// Loaded strip entries of a thread: [image][row pairs | column pairs][pass]
+// [pixel, mirrored pixel].
+template <int IMG>
 struct Strip4Regs {
-    float x[IMG][2][s4_groups<NT>()];
+    float x[IMG][2][2][2];
 };
 
-// Entry e of a strip of `w` entries per line: line index q = e / w and
-// offset o = e - q w (exact in FP32 for these sizes).
-__device__ __forceinline__ void s4_entry(int e, int w, float invw, int &q, int &o) {
-    q = (int)fmaf((float)e, invw, 0.5f * invw);
+// Quotient and remainder of e by w through a multiply-high with
+// mg = floor((2^32 - 1) / w) + 1: exact while e w < 2^32 (e < 512, w <= 1024
+// here).  mg is uniform, so each division is one VALU operation with a scalar
+// operand.
+__device__ __forceinline__ void s4_divmod(int e, int w, unsigned mg, int &q, int &o) {
+    q = (int)__umulhi((unsigned)e, mg);
     o = e - __mul24(q, w);
 }
 
-// Issue the loads of strip rows [i0, i0 + rows) of `nimg` images into
-// registers.  Kind 0 walks the strip rows (j fastest), kind 1 the image rows
-// j of the transposed strip (r fastest: F[j][i0 .. i0 + rows) is contiguous).
-// Every image is read through a buffer resource covering exactly that image.
+// Per-block constants of the staging: pairs per row H, strip rows R, and the
+// rows a pass covers for each entry kind (rp strip rows of pairs, jp image
+// rows of column runs).
+struct S4Geo {
+    int H, R, rp, jp;
+    unsigned mH, mR;  // multipliers of s4_divmod for H and R
+};
+template <int NT>
+__device__ __forceinline__ S4Geo s4_geo(int L) {
+    S4Geo G;
+    G.H = s4_pairs(L);
+    G.R = s4_rows<NT>(L);
+    G.rp = NT / G.H;
+    G.jp = NT / G.R;
+    G.mH = 0xffffffffu / (unsigned)G.H + 1u;
+    G.mR = 0xffffffffu / (unsigned)G.R + 1u;
+    // uniform: keep them in scalar registers
+    G.rp = __builtin_amdgcn_readfirstlane(G.rp);
+    G.jp = __builtin_amdgcn_readfirstlane(G.jp);
+    G.mH = __builtin_amdgcn_readfirstlane(G.mH);
+    G.mR = __builtin_amdgcn_readfirstlane(G.mR);
+    return G;
+}
+
+// The thread's entries: row pairs (j0, L-1-j0) of strip rows r0 + k rp, and
+// column runs: column i0 + rr0 of image rows jj0 + k jp and L-1-(jj0 + k jp),
+// k < 2.  Threads past a full pass (r0 >= rp, jj0 >= jp) have no entries.
+struct S4Map {
+    int j0, r0, rr0, jj0;
+};
+// Recomputed at each use (an opaque copy of the thread index keeps the
+// compiler from holding the map, loop-invariant, across the accumulation).
+__device__ __forceinline__ S4Map s4_map(const S4Geo &G) {
+    S4Map m;
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    s4_divmod(t, G.H, G.mH, m.r0, m.j0);
+    s4_divmod(t, G.R, G.mR, m.jj0, m.rr0);
+    return m;
+}
+
+// Issue the loads of strip rows [i0, i0 + R) of `nimg` images into
+// registers.  Row pairs read along the strip rows, column runs along image
+// rows (F[jj][i0 .. i0 + R) is contiguous), both coalesced.  Every image is
+// read through a buffer resource covering exactly that image: entries past
+// the image (or with a negative offset) load 0 under the hardware range
+// check, entries past the strip load in range; the store drops both.
 template <int NT, int IMG>
 __device__ __forceinline__ void s4_load(const float *const (&F)[IMG], int nimg, int L, int i0,
-                                        int rows, Strip4Regs<NT, IMG> &X) {
-    constexpr int G = s4_groups<NT>();
-    const int total = rows * L;
-    const float invL = 1.f / (float)L, invR = 1.f / (float)rows;
+                                        const S4Geo &G, Strip4Regs<IMG> &X) {
+    const S4Map m = s4_map(G);
+    int o[2][2][2];
+    const int dm = L - 1 - 2 * m.j0;           // F[i][L-1-j0] - F[i][j0]
+    const int c = i0 + m.rr0, cm = (L - 1) * L + 2 * c;  // F[L-1-jj][c] = cm - F[jj][c]
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        o[0][k][0] = __mul24(i0 + m.r0 + k * G.rp, L) + m.j0;
+        o[0][k][1] = o[0][k][0] + dm;
+        o[1][k][0] = __mul24(m.jj0 + k * G.jp, L) + c;
+        o[1][k][1] = cm - o[1][k][0];
+    }
 #pragma unroll
     for (int g = 0; g < IMG; ++g) {
         if (g >= nimg) break;  // block-uniform
         const __amdgpu_buffer_rsrc_t img =
             __builtin_amdgcn_make_buffer_rsrc((void *)F[g], (short)0, 4 * L * L, 0x00020000);
 #pragma unroll
-        for (int it = 0; it < G; ++it) {
-            const int e = threadIdx.x + it * NT;
-            int r, j, jj, rr;
-            s4_entry(e, L, invL, r, j);
-            s4_entry(e, rows, invR, jj, rr);
-            // entries past the strip read in range and are dropped at the store
-            const int o0 = e < total ? __mul24(i0 + r, L) + j : 0;
-            const int o1 = e < total ? __mul24(jj, L) + i0 + rr : 0;
-            X.x[g][0][it] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, 4 * o0, 0, 0));
-            X.x[g][1][it] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(img, 4 * o1, 0, 0));
-        }
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+                    X.x[g][h][k][v] = __uint_as_float(
+                        __builtin_amdgcn_raw_buffer_load_b32(img, 4 * o[h][k][v], 0, 0));
     }
 }
 
-// Write the loaded strip: every value to its own position and to the
-// mirrored one (kinds 0/2 from the rows, 1/3 from the transposed rows).  A
-// non-finite pixel (inside the disk or not) sets bad[g].
+// Write the loaded strip (rows [i0, i0 + rows)): clip at 0, mask to the disk
+// x^2 + y^2 <= (1 - h)^2, and put each pair into its two positions.  A
+// non-finite pixel (inside the disk or not) sets bad[g]; every pixel of the
+// image passes through the row pairs once.
 template <int NT, int IMG>
-__device__ __forceinline__ void s4_store(int nimg, int L, int i0, int rows,
-                                         const Strip4Regs<NT, IMG> &X, float *lds, int (&bad)[IMG]) {
-    constexpr int G = s4_groups<NT>();
-    const int total = rows * L, P4 = 4 * s4_positions(L);
-    const int rr2 = (L - 2) * (L - 2);
-    const float invL = 1.f / (float)L, invR = 1.f / (float)rows;
+__device__ __forceinline__ void s4_store(int nimg, int L, int i0, int rows, const S4Geo &G,
+                                         const Strip4Regs<IMG> &X, float *lds, int (&bad)[IMG]) {
+    typedef float f32x2v __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) f32x2v LdsF2;
+    const S4Map m = s4_map(G);
+    const int P16 = 16 * s4_positions(L), rr2 = (L - 2) * (L - 2);
+    const int lb = (int)(uintptr_t)(const __attribute__((address_space(3))) float *)lds;
+    float nf[IMG];
 #pragma unroll
-    for (int g = 0; g < IMG; ++g) {
-        if (g >= nimg) break;
-        float *S = lds + g * (kImg2Bytes / 4);
-        float nf = 0.f;  // becomes NaN once a non-finite value is read
+    for (int g = 0; g < IMG; ++g) nf[g] = 0.f;  // becomes NaN once a non-finite value is read
+    {  // row pairs: positions j0 + 2 and L + 1 - j0 of strip row r0 + k rp, bytes 0..7
+        const int a = 2 * m.j0 - L + 1, a2 = __mul24(a, a);
+        const int p0 = lb + __mul24(m.r0, P16) + 16 * (m.j0 + 2);
+        const int p1 = p0 + 16 * (L - 1 - 2 * m.j0);
 #pragma unroll
-        for (int it = 0; it < G; ++it) {
-            const int e = threadIdx.x + it * NT;
-            if (e < total) {
-                int r, j, jj, rr;
-                s4_entry(e, L, invL, r, j);
-                s4_entry(e, rows, invR, jj, rr);
-                const float x0 = X.x[g][0][it], x1 = X.x[g][1][it];
-                nf = fmaf(x0, 0.f, nf);
-                // pixel (i0 + r, j) and pixel (jj, i0 + rr): x^2 + y^2 <= (1 - h)^2
-                const int a0 = 2 * j - L + 1, b0 = 2 * (i0 + r) - L + 1;
-                const int a1 = 2 * (i0 + rr) - L + 1, b1 = 2 * jj - L + 1;
-                const float v0 = __mul24(a0, a0) + __mul24(b0, b0) <= rr2 ? fmaxf(x0, 0.f) : 0.f;
-                const float v1 = __mul24(a1, a1) + __mul24(b1, b1) <= rr2 ? fmaxf(x1, 0.f) : 0.f;
-                float *row0 = S + __mul24(r, P4), *row1 = S + __mul24(rr, P4);
-                row0[4 * (j + 2)] = v0;
-                row0[4 * (L + 1 - j) + 2] = v0;
-                row1[4 * (jj + 2) + 1] = v1;
-                row1[4 * (L + 1 - jj) + 3] = v1;
+        for (int k = 0; k < 2; ++k) {
+            const int r = m.r0 + k * G.rp;
+            if (m.r0 < G.rp && r < rows) {
+                const int b = 2 * (i0 + r) - L + 1;
+                const bool in = __mul24(b, b) + a2 <= rr2;
+                const int dk = k * G.rp * P16;
+#pragma unroll
+                for (int g = 0; g < IMG; ++g) {
+                    if (g >= nimg) break;
+                    const float x = X.x[g][0][k][0], y = X.x[g][0][k][1];
+                    nf[g] = fmaf(y, 0.f, fmaf(x, 0.f, nf[g]));
+                    const float u = in ? fmaxf(x, 0.f) : 0.f, v = in ? fmaxf(y, 0.f) : 0.f;
+                    *(LdsF2 *)(uintptr_t)(p0 + dk + g * kImg2Bytes) = f32x2v{u, v};
+                    *(LdsF2 *)(uintptr_t)(p1 + dk + g * kImg2Bytes) = f32x2v{v, u};
+                }
             }
         }
-        if (nf != 0.f) bad[g] = 1;
+    }
+    {  // column runs: positions jj + 2 and L + 1 - jj of strip row rr0, bytes 8..15
+        const int a = 2 * (i0 + m.rr0) - L + 1, a2 = __mul24(a, a);
+        const int p0 = lb + __mul24(m.rr0, P16) + 16 * (m.jj0 + 2) + 8;
+        const int p1 = lb + __mul24(m.rr0, P16) + 16 * (L + 1 - m.jj0) + 8;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int jj = m.jj0 + k * G.jp;
+            if (m.jj0 < G.jp && m.rr0 < rows && jj < G.H) {
+                const int b = 2 * jj - L + 1;
+                const bool in = __mul24(b, b) + a2 <= rr2;
+                const int dk = 16 * k * G.jp;
+#pragma unroll
+                for (int g = 0; g < IMG; ++g) {
+                    if (g >= nimg) break;
+                    const float x = X.x[g][1][k][0], y = X.x[g][1][k][1];
+                    const float u = in ? fmaxf(x, 0.f) : 0.f, v = in ? fmaxf(y, 0.f) : 0.f;
+                    *(LdsF2 *)(uintptr_t)(p0 + dk + g * kImg2Bytes) = f32x2v{u, v};
+                    *(LdsF2 *)(uintptr_t)(p1 - dk + g * kImg2Bytes) = f32x2v{v, u};
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < IMG; ++g)
+        if (g < nimg && nf[g] != 0.f) bad[g] = 1;
+}
+
+// A lane's task here keeps only its row offsets and the LDS address of its
+// slot's constants (c = cos theta, r = tan theta, k1 = 2 - 1/c, k2 = 2 - 3c,
+// the values of make_task), read once per task and strip: the accumulators of
+// two images leave no registers for five constants per task.
+struct LaneTask2 {
+    int ka;           // byte address of the slot's float4 in the table
+    float A3, A3n;
+    int rlo, rhi;     // wave-uniform
+};
+
+__device__ __forceinline__ LaneTask2 make_task2(const ProjShape &P, const float2 *dtab, int task,
+                                                int lane, int kbase) {
+    const LaneTask t = make_task(P, dtab, task, lane);
+    const int item = task_item(P, task, lane);
+    LaneTask2 u;
+    u.A3 = t.A3;
+    u.A3n = t.A3n;
+    u.rlo = t.rlo;
+    u.rhi = t.rhi;
+    u.ka = kbase + 16 * (item >= 0 ? item / P.L : P.slots);
+    return u;
+}
+
+// The table: one float4 per slot plus the constants of an empty lane.
+template <int NT>
+__device__ __forceinline__ void fill_slot_table(const ProjShape &P, const float2 *dtab,
+                                                float4 *tab) {
+    for (int k = threadIdx.x; k <= P.slots; k += NT) {
+        float c = 1.f, r = 0.f, k1 = 1.f;
+        if (k < P.slots) {
+            const float2 d = dtab[k];
+            c = d.x;
+            r = -d.y / c;
+            k1 = (float)(2.0 - 1.0 / (double)c);
+        }
+        tab[k] = make_float4(c, r, k1, fmaf(-3.f, c, 2.f));
     }
 }
 
@@ -132,10 +258,10 @@ __device__ __forceinline__ void s4_store(int nimg, int L, int i0, int rows,
 // second image reads its zero strips).  Rows pair from even image rows as in
 // accumulate_strip.
 template <int TPW, int IMG>
-__device__ __forceinline__ void s4_accumulate(const LaneTask (&tasks)[TPW], int L,
+__device__ __forceinline__ void s4_accumulate(const LaneTask2 (&tasks)[TPW], int L,
                                               const float *lds, int i0, int rows,
                                               float (&acc)[IMG][TPW][4], int my_tasks) {
-    const float hi3 = (float)L + 2.f;
+    const float hi3 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)L + 2.f)));
     const int P16 = 16 * s4_positions(L);
     const int lbase = (int)(uintptr_t)(const __attribute__((address_space(3))) float *)lds;
     int s16;
@@ -143,8 +269,9 @@ __device__ __forceinline__ void s4_accumulate(const LaneTask (&tasks)[TPW], int 
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
         if (t < my_tasks) {  // wave-uniform
-            const LaneTask tk = tasks[t];
-            const float k2 = 2.f - 3.f * tk.c;
+            const LaneTask2 tk = tasks[t];
+            const f32x4v K = *(const LdsF4 *)(uintptr_t)tk.ka;
+            const float c = K.x, tr = K.y, k1 = K.z, k2 = K.w;
             float s[IMG][4];
 #pragma unroll
             for (int g = 0; g < IMG; ++g)
@@ -155,9 +282,9 @@ __device__ __forceinline__ void s4_accumulate(const LaneTask (&tasks)[TPW], int 
                 um = __builtin_amdgcn_fmed3f(um, 0.5f, hi3);
                 const float fr = __builtin_amdgcn_fractf(um);
                 const int j2 = (int)um;
-                const float w0 = fmaf(-tk.c, fr, tk.c);
-                const float w1 = fmaf(-tk.c, fabsf(tk.k1 - fr), 1.f);
-                const float w2 = __builtin_amdgcn_fmed3f(fmaf(tk.c, fr, k2), 0.f, 1.f);
+                const float w0 = fmaf(-c, fr, c);
+                const float w1 = fmaf(-c, fabsf(k1 - fr), 1.f);
+                const float w2 = __builtin_amdgcn_fmed3f(fmaf(c, fr, k2), 0.f, 1.f);
                 const int pa = __mul24(j2, s16) + rbase;
 #pragma unroll
                 for (int g = 0; g < IMG; ++g) {
@@ -165,23 +292,23 @@ __device__ __forceinline__ void s4_accumulate(const LaneTask (&tasks)[TPW], int 
                     const f32x4v K1 = *(const LdsF4 *)(uintptr_t)(pa + g * kImg2Bytes + 16);
                     const f32x4v K2 = *(const LdsF4 *)(uintptr_t)(pa + g * kImg2Bytes + 32);
                     s[g][0] = fmaf(w2, K2.x, fmaf(w1, K1.x, fmaf(w0, K0.x, s[g][0])));
-                    s[g][1] = fmaf(w2, K2.y, fmaf(w1, K1.y, fmaf(w0, K0.y, s[g][1])));
-                    s[g][2] = fmaf(w2, K2.z, fmaf(w1, K1.z, fmaf(w0, K0.z, s[g][2])));
+                    s[g][1] = fmaf(w2, K2.z, fmaf(w1, K1.z, fmaf(w0, K0.z, s[g][1])));
+                    s[g][2] = fmaf(w2, K2.y, fmaf(w1, K1.y, fmaf(w0, K0.y, s[g][2])));
                     s[g][3] = fmaf(w2, K2.w, fmaf(w1, K1.w, fmaf(w0, K0.w, s[g][3])));
                 }
             };
             int rr = ra;
             if (rr < rb && ((i0 + rr) & 1)) {  // odd first row (wave-uniform)
-                row(fmaf((float)(i0 + rr - 1), tk.r, tk.A3n), lbase + rr * P16);
+                row(fmaf((float)(i0 + rr - 1), tr, tk.A3n), lbase + rr * P16);
                 ++rr;
             }
             float fi = (float)(i0 + rr);  // even row index, exact in FP32
             for (; rr + 1 < rb; rr += 2, fi += 2.f) {
                 const int rbase = lbase + rr * P16;
-                row(fmaf(fi, tk.r, tk.A3), rbase);
-                row(fmaf(fi, tk.r, tk.A3n), rbase + P16);
+                row(fmaf(fi, tr, tk.A3), rbase);
+                row(fmaf(fi, tr, tk.A3n), rbase + P16);
             }
-            if (rr < rb) row(fmaf(fi, tk.r, tk.A3), lbase + rr * P16);
+            if (rr < rb) row(fmaf(fi, tr, tk.A3), lbase + rr * P16);
 #pragma unroll
             for (int g = 0; g < IMG; ++g)
 #pragma unroll
@@ -192,15 +319,18 @@ __device__ __forceinline__ void s4_accumulate(const LaneTask (&tasks)[TPW], int 
 
 // Projection of `nimg` <= IMG images for the task group starting at task
 // tg0 (tasks tg0 + wave + t NW, t < TPW) into the accumulators; lds holds IMG
-// strip buffers of kImg2Bytes.  bad[g] is set when image g holds a
+// strip buffers of kImg2Bytes, ktab (P.slots + 1 entries, 16-byte aligned)
+// the slot constants.  bad[g] is set when image g holds a
 // non-finite value.
 template <int NT, int TPW, int IMG>
 __device__ void project_images2(const float *const (&F)[IMG], int nimg, const ProjShape &P,
-                                const float2 *__restrict__ dtab, float *lds, int tg0,
+                                const float2 *__restrict__ dtab, float *lds, float4 *ktab, int tg0,
                                 float (&acc)[IMG][TPW][4], int (&bad)[IMG]) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int L = P.L, R = s4_rows(L);
+    const int L = P.L;
+    const S4Geo G = s4_geo<NT>(L);
+    const int R = G.R;
 #pragma unroll
     for (int g = 0; g < IMG; ++g) {
         bad[g] = 0;
@@ -209,21 +339,23 @@ __device__ void project_images2(const float *const (&F)[IMG], int nimg, const Pr
     }
     const int mine = P.ntasks - tg0 - wave;
     const int my_tasks = mine > 0 ? min(TPW, (mine + NW - 1) / NW) : 0;
-    LaneTask tasks[TPW];
+    const int kbase = (int)(uintptr_t)(__attribute__((address_space(3))) float4 *)ktab;
+    LaneTask2 tasks[TPW];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) tasks[t] = make_task(P, dtab, tg0 + wave + t * NW, lane);
+    for (int t = 0; t < TPW; ++t) tasks[t] = make_task2(P, dtab, tg0 + wave + t * NW, lane, kbase);
     // the padding positions (and a missing image's strips) stay zero
-    __syncthreads();  // the caller may have used the region
+    __syncthreads();  // the caller may have used the region and the table
+    fill_slot_table<NT>(P, dtab, ktab);
     for (int q = threadIdx.x; q < IMG * kImg2Bytes / 16; q += NT)
         *(float4 *)(lds + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
-    Strip4Regs<NT, IMG> xs;
-    s4_load<NT, IMG>(F, nimg, L, 0, min(R, L), xs);
+    Strip4Regs<IMG> xs;
+    s4_load<NT, IMG>(F, nimg, L, 0, G, xs);
     for (int i0 = 0; i0 < L; i0 += R) {
         const int rows = min(R, L - i0);
         __syncthreads();
-        s4_store<NT, IMG>(nimg, L, i0, rows, xs, lds, bad);
+        s4_store<NT, IMG>(nimg, L, i0, rows, G, xs, lds, bad);
         __syncthreads();
-        if (i0 + R < L) s4_load<NT, IMG>(F, nimg, L, i0 + R, min(R, L - i0 - R), xs);
+        if (i0 + R < L) s4_load<NT, IMG>(F, nimg, L, i0 + R, G, xs);
         s4_accumulate<TPW, IMG>(tasks, L, lds, i0, rows, acc, my_tasks);
     }
 #pragma unroll

@@ -287,7 +287,7 @@ __device__ __forceinline__ void accumulate_strip(const ProjShape &P, const LaneT
             // and j0 stays in [-2, L]: a line clamped there has its whole hat
             // on columns <= 0 or >= L - 1, outside the disk, and so does the
             // clamped position.
-            const float k2 = 2.f - 3.f * tk.c;
+            const float k2 = fmaf(-3.f, tk.c, 2.f);
             float s0 = acc[t][0], s1 = acc[t][1], s2 = acc[t][2], s3 = acc[t][3];
             // only the rows of this strip that the task's lines cross
             const int ra = max(tk.rlo - i0, 0), rb = min(tk.rhi - i0 + 1, rows);
