@@ -26,8 +26,15 @@ struct QuantShape {
 
 // v moved across lanes by a DPP control (row_mask selects the 16-lane rows
 // that receive; lanes without a valid source, and rows not selected, get 0).
+// With every row selected the bound control supplies the zeros, so no
+// zeroed destination has to be set up first.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_d(double v) {
+    if (ROWS == 0xf) {
+        const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+        const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+        return __hiloint2double(hi, lo);
+    }
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
     return __hiloint2double(hi, lo);
@@ -98,11 +105,20 @@ __device__ __forceinline__ int levels_at_or_below(double c, int Q, double zshift
     return min(max(j, 0), Q);
 }
 
-// h / den for den > 0: hardware reciprocal and two Newton steps (FP64).
-__device__ __forceinline__ double div_by(double h, double den) {
-    double r = __builtin_amdgcn_rcp(den);
-    r = fma(r, fma(-den, r, 1.0), r);
-    r = fma(r, fma(-den, r, 1.0), r);
+// 1 / m for m > 0: hardware reciprocal and two Newton steps (FP64).
+__device__ __forceinline__ double recip_d(double m) {
+    double r = __builtin_amdgcn_rcp(m);
+    r = fma(r, fma(-m, r, 1.0), r);
+    r = fma(r, fma(-m, r, 1.0), r);
+    return r;
+}
+
+// h / den in FP32 for den > 0 (the interpolation runs in FP32): the FP64 CDF
+// step rounded to FP32, its hardware reciprocal refined by one Newton step.
+__device__ __forceinline__ float slope_f(float h, double den) {
+    const float d = (float)den;
+    float r = __builtin_amdgcn_rcpf(d);
+    r = fmaf(r, fmaf(-d, r, 1.f), r);
     return h * r;
 }
 
@@ -116,14 +132,16 @@ template <int M, bool HALF, typename ColFn>
 __device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut, int ldt, int kl,
                                   int hl, int half, double *su, double *sq) {
     constexpr int G = HALF ? 32 : 64;
+    // the lane's M bins read at once (bins past the column read the last
+    // bin and are dropped), then summed
+    float xs[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) xs[t] = col(min(hl * M + t, L - 1));
     double v[M];
     double run = 0.0;
 #pragma unroll
     for (int t = 0; t < M; ++t) {
-        const int b = hl * M + t;
-        double x = 0.0;
-        if (b < L) x = (double)col(b);
-        run += x;
+        run += hl * M + t < L ? (double)xs[t] : 0.0;
         v[t] = run;  // lane-local inclusive sums
     }
     const double excl = group_inclusive_scan_d<HALF>(run) - run;
@@ -151,17 +169,14 @@ __device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut
             s2 += (double)uf * (double)uf;
         }
     } else {
-        const double invm = 1.0 / mass;
+        const double invm = recip_d(mass);
         // C at the right edge of bin b = hl M + t; exactly 1 at the last bin
         auto cdf = [&](int t) {
             return hl * M + t == L - 1 ? 1.0 : (excl + v[t]) * invm;
         };
         // C at the left edge of this lane's first bin: the previous lane's
         // last right edge (0 on the first lane of the group)
-        const double cm = cdf(M - 1);
-        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(cm), 0x138, 0xf, 0xf, false);
-        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(cm), 0x138, 0xf, 0xf, false);
-        double cl = __hiloint2double(hi, lo);  // wave_shr:1
+        double cl = dpp_d<0x138, 0xf>(cdf(M - 1));  // wave_shr:1
         if (hl == 0) cl = 0.0;  // with halves, lane 32 got lane 31's edge
         int jl = hl == 0 ? 0 : levels_at_or_below(cl, Q, zshift);
 #pragma unroll
@@ -172,11 +187,11 @@ __device__ double invert_column_m(ColFn col, int L, int Q, int levels, float *Ut
                 const int jr = levels_at_or_below(cr, Q, zshift);
                 const double tl = fma((double)b, h, -1.0), tr = tl + h;
                 const double den = cr - cl;
-                const double slope = den > 0.0 ? div_by(h, den) : 0.0;
                 // the offset z - cl inside the bin in FP64 (advanced by 1/Q
-                // per level), the interpolation and the clamp to the bin in
-                // FP32 (the result's precision)
-                const float tlf = (float)tl, trf = (float)tr, slf = (float)slope;
+                // per level), the slope, the interpolation and the clamp to
+                // the bin in FP32 (the result's precision)
+                const float tlf = (float)tl, trf = (float)tr;
+                const float slf = den > 0.0 ? slope_f((float)h, den) : 0.f;
                 double zc = fma((double)jl, invQ, z0) - cl;
                 for (int j = jl; j < jr; ++j, zc += invQ) {
                     const float uf = __builtin_amdgcn_fmed3f(fmaf((float)zc, slf, tlf), tlf, trf);
