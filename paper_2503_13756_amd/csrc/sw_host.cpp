@@ -209,8 +209,11 @@ static sw_status noalloc_device(int device, NoAllocDevice **out) {
 // the line crosses row i; a small margin keeps the range conservative under
 // FP32 rounding).  Units of 8 consecutive bins of one slot take the union of
 // their items' ranges, units are ordered by the centre of their range, and
-// each run of eight forms a task.  Rows outside a task's range only ever add
-// zeros, so skipping them leaves every sum unchanged.
+// each run of eight forms a task; a local search then swaps units between
+// tasks while that does not lengthen the two tasks' ranges together (fixed
+// seed: the plan is a function of (L, n)).  Rows outside a task's range only
+// ever add zeros, so skipping them leaves every sum unchanged, whatever the
+// plan.
 static void build_plan(int L, int n, std::vector<int> &perm, std::vector<int2> &trow) {
     std::vector<double> c, s;
     angle_values(n, c, s);
@@ -250,6 +253,41 @@ static void build_plan(int L, int n, std::vector<int> &perm, std::vector<int2> &
         const int kx = x.lo <= x.hi ? x.lo + x.hi : -1, ky = y.lo <= y.hi ? y.lo + y.hi : -1;
         return kx < ky;
     });
+    // local search: task t holds units[8 t .. 8 t + 7]; a swap is kept when
+    // the two tasks' range lengths do not grow in sum
+    const int nu = (int)units.size();
+    auto span = [&](int t) {
+        int lo = L, hi = -1;
+        for (int q = 8 * t; q < std::min(nu, 8 * t + 8); ++q)
+            if (units[q].lo <= units[q].hi) {
+                lo = std::min(lo, units[q].lo);
+                hi = std::max(hi, units[q].hi);
+            }
+        return hi >= lo ? hi - lo + 1 : 0;
+    };
+    if (ntasks > 1) {
+        std::vector<int> len(ntasks);
+        for (int t = 0; t < ntasks; ++t) len[t] = span(t);
+        uint64_t st = 0x9e3779b97f4a7c15ull;
+        auto next = [&](int m) {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            return (int)((st >> 33) % (uint64_t)m);
+        };
+        const long iters = 200000 + 50L * nu;
+        for (long it = 0; it < iters; ++it) {
+            const int qa = next(nu), qb = next(nu);
+            const int ta = qa / 8, tb = qb / 8;
+            if (ta == tb) continue;
+            std::swap(units[qa], units[qb]);
+            const int la = span(ta), lb = span(tb);
+            if (la + lb <= len[ta] + len[tb]) {
+                len[ta] = la;
+                len[tb] = lb;
+            } else {
+                std::swap(units[qa], units[qb]);
+            }
+        }
+    }
     perm.assign((size_t)ntasks * 64, -1);
     trow.assign(ntasks, make_int2(1, 0));
     for (size_t q = 0; q < units.size(); ++q) {
