@@ -8,6 +8,7 @@
 #include "align128_dev.h"
 #include "align_dev.h"
 #include "mix_internal.h"
+#include "proj2_dev.h"
 #include "proj_dev.h"
 #include "quant_dev.h"
 
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
         P.n = it.n;
         P.S = strip_stride(it.L);
         P.RS = strip_row_floats(it.L);
-        P.R = it.R;
+        P.R = it.R;  // rows of the four-kind strips (plan_mixed clamps it)
         P.slots = it.n / 8 + 1;
         P.items = P.slots * it.L;
         P.ntasks = proj_ntasks(it.L, it.n);
@@ -77,8 +78,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
         float *pmf = it.fused ? region : scratch + (int64_t)blockIdx.x * slot_floats;
         const float *F = it.img + gi * (int64_t)L * L;
         int bad = 0;
-        project_image<NT, TPW>(F, P, it.d32, region, bad,
-                               [&](int k, int b, float v) { pmf[k * L + b] = v; });
+        // the slot table sits in the column-sum area until the quantile phase
+        project_image4<NT, TPW>(F, P, it.d32, region, (float4 *)colS, P.R, bad,
+                                [&](int k, int b, float v) { pmf[k * L + b] = v; });
         if (bad)
             for (int t = threadIdx.x; t < n * L; t += NT) pmf[t] = __int_as_float(0x7fc00000);
         __threadfence_block();
@@ -213,8 +215,8 @@ MixLaunch plan_mixed(MixItem *items, int nitems, MixKnobs knobs) {
     size_t align_lds = 0;
     for (int i = 0; i < nitems; ++i) {
         MixItem &it = items[i];
-        int R = it.R > 0 ? it.R : strip_rows_max(it.L);
-        if (R > strip_rows_max(it.L)) R = strip_rows_max(it.L);
+        int R = it.R > 0 ? it.R : strip4_rows_max(it.L);
+        if (R > strip4_rows_max(it.L)) R = strip4_rows_max(it.L);
         if (R > it.L) R = it.L;
         if (R < 1) R = 1;
         if (R > NTT) R = NTT;

@@ -73,7 +73,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     float acc[2][TPW][4];
     int bad[2];
     // the slot table sits in the column-sum area until the quantile phase
-    project_images2<NT, TPW, 2>(F, nimg, P, d32, region, (float4 *)colS, 0, acc, bad);
+    project_images2<NT, TPW, 2>(F, nimg, P, d32, region, (float4 *)colS, s4_rows<NT>(L), 0, acc,
+                                bad);
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *park = qt + (g0 + 1) * (int64_t)Q * n + threadIdx.x;
     if (kParkFloats<NT, TPW> > 0 && nimg == 2) {

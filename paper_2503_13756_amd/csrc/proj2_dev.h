@@ -43,52 +43,56 @@ __host__ __device__ inline int s4_positions(int L) { return (L + 5) | 1; }
 // Column pairs per row: j < ceil(L / 2) (an odd L's middle column pairs with
 // itself).
 __host__ __device__ inline int s4_pairs(int L) { return (L + 1) >> 1; }
-// Strip rows per image: as many as fit kImg2Bytes, at most twice the rows one
-// pass of NT threads covers (so that two passes stage any strip).  With this
-// bound two passes also cover the column pairs for every L <= 1024
-// (ceil(L/2) <= NT for NT = 512).
-template <int NT = 512>
-__host__ __device__ inline int s4_rows(int L) {
-    int r = kImg2Bytes / (16 * s4_positions(L));
+// Strip rows per image: as many as fit `bytes`, at most KP times the rows one
+// pass of NT threads covers (so that KP passes stage any strip).  With this
+// bound KP passes also cover the column pairs for every L <= 1024 (ceil(L/2)
+// <= NT for NT = 512).
+template <int NT = 512, int KP = 2>
+__host__ __device__ inline int s4_rows(int L, int bytes = kImg2Bytes) {
+    int r = bytes / (16 * s4_positions(L));
     if (r > L) r = L;
-    const int cap = 2 * (NT / s4_pairs(L));
+    const int cap = KP * (NT / s4_pairs(L));
     return r < cap ? r : cap;
 }
-// Whether the two-image staging covers L with 512-thread blocks.
+// Whether the staging covers L with 512-thread blocks.
 __host__ __device__ inline bool s4_supported(int L) { return L >= 2 && s4_pairs(L) <= 512; }
+// The one-image form: four passes, strips in the whole 64 KiB region
+// (strip4_rows_max(L) = s4_rows<512, 4>(L, 65536)).
+constexpr int kImg1Passes = 4;
 
 // Loaded strip entries of a thread: [image][row pairs | column pairs][pass]
 // [pixel, mirrored pixel].
-template <int IMG>
+template <int IMG, int KP>
 struct Strip4Regs {
-    float x[IMG][2][2][2];
+    float x[IMG][2][KP][2];
 };
 
 // Quotient and remainder of e by w through a multiply-high with
 // mg = floor((2^32 - 1) / w) + 1: exact while e w < 2^32 (e < 512, w <= 1024
 // here).  mg is uniform, so each division is one VALU operation with a scalar
-// operand.
+// operand.  For w = 1 the multiplier (2^32) does not fit: mg = 0 there and the
+// quotient is e itself.
 __device__ __forceinline__ void s4_divmod(int e, int w, unsigned mg, int &q, int &o) {
-    q = (int)__umulhi((unsigned)e, mg);
+    q = (int)__umulhi((unsigned)e, mg) + (w == 1 ? e : 0);
     o = e - __mul24(q, w);
 }
 
-// Per-block constants of the staging: pairs per row H, strip rows R, and the
-// rows a pass covers for each entry kind (rp strip rows of pairs, jp image
-// rows of column runs).
+// Per-block constants of the staging: pairs per row H, strip rows R (at most
+// s4_rows for the pass count), and the rows a pass covers for each entry kind
+// (rp strip rows of pairs, jp image rows of column runs).
 struct S4Geo {
     int H, R, rp, jp;
     unsigned mH, mR;  // multipliers of s4_divmod for H and R
 };
 template <int NT>
-__device__ __forceinline__ S4Geo s4_geo(int L) {
+__device__ __forceinline__ S4Geo s4_geo(int L, int R) {
     S4Geo G;
     G.H = s4_pairs(L);
-    G.R = s4_rows<NT>(L);
+    G.R = R;
     G.rp = NT / G.H;
     G.jp = NT / G.R;
-    G.mH = 0xffffffffu / (unsigned)G.H + 1u;
-    G.mR = 0xffffffffu / (unsigned)G.R + 1u;
+    G.mH = G.H > 1 ? 0xffffffffu / (unsigned)G.H + 1u : 0u;
+    G.mR = G.R > 1 ? 0xffffffffu / (unsigned)G.R + 1u : 0u;
     // uniform: keep them in scalar registers
     G.rp = __builtin_amdgcn_readfirstlane(G.rp);
     G.jp = __builtin_amdgcn_readfirstlane(G.jp);
@@ -99,7 +103,7 @@ __device__ __forceinline__ S4Geo s4_geo(int L) {
 
 // The thread's entries: row pairs (j0, L-1-j0) of strip rows r0 + k rp, and
 // column runs: column i0 + rr0 of image rows jj0 + k jp and L-1-(jj0 + k jp),
-// k < 2.  Threads past a full pass (r0 >= rp, jj0 >= jp) have no entries.
+// k < KP.  Threads past a full pass (r0 >= rp, jj0 >= jp) have no entries.
 struct S4Map {
     int j0, r0, rr0, jj0;
 };
@@ -120,15 +124,15 @@ __device__ __forceinline__ S4Map s4_map(const S4Geo &G) {
 // read through a buffer resource covering exactly that image: entries past
 // the image (or with a negative offset) load 0 under the hardware range
 // check, entries past the strip load in range; the store drops both.
-template <int NT, int IMG>
+template <int NT, int IMG, int KP>
 __device__ __forceinline__ void s4_load(const float *const (&F)[IMG], int nimg, int L, int i0,
-                                        const S4Geo &G, Strip4Regs<IMG> &X) {
+                                        const S4Geo &G, Strip4Regs<IMG, KP> &X) {
     const S4Map m = s4_map(G);
-    int o[2][2][2];
+    int o[2][KP][2];
     const int dm = L - 1 - 2 * m.j0;           // F[i][L-1-j0] - F[i][j0]
     const int c = i0 + m.rr0, cm = (L - 1) * L + 2 * c;  // F[L-1-jj][c] = cm - F[jj][c]
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < KP; ++k) {
         o[0][k][0] = __mul24(i0 + m.r0 + k * G.rp, L) + m.j0;
         o[0][k][1] = o[0][k][0] + dm;
         o[1][k][0] = __mul24(m.jj0 + k * G.jp, L) + c;
@@ -142,7 +146,7 @@ __device__ __forceinline__ void s4_load(const float *const (&F)[IMG], int nimg, 
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < KP; ++k)
 #pragma unroll
                 for (int v = 0; v < 2; ++v)
                     X.x[g][h][k][v] = __uint_as_float(
@@ -154,9 +158,10 @@ __device__ __forceinline__ void s4_load(const float *const (&F)[IMG], int nimg, 
 // x^2 + y^2 <= (1 - h)^2, and put each pair into its two positions.  A
 // non-finite pixel (inside the disk or not) sets bad[g]; every pixel of the
 // image passes through the row pairs once.
-template <int NT, int IMG>
+template <int NT, int IMG, int KP>
 __device__ __forceinline__ void s4_store(int nimg, int L, int i0, int rows, const S4Geo &G,
-                                         const Strip4Regs<IMG> &X, float *lds, int (&bad)[IMG]) {
+                                         const Strip4Regs<IMG, KP> &X, float *lds,
+                                         int (&bad)[IMG]) {
     typedef float f32x2v __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) f32x2v LdsF2;
     const S4Map m = s4_map(G);
@@ -170,7 +175,7 @@ __device__ __forceinline__ void s4_store(int nimg, int L, int i0, int rows, cons
         const int p0 = lb + __mul24(m.r0, P16) + 16 * (m.j0 + 2);
         const int p1 = p0 + 16 * (L - 1 - 2 * m.j0);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < KP; ++k) {
             const int r = m.r0 + k * G.rp;
             if (m.r0 < G.rp && r < rows) {
                 const int b = 2 * (i0 + r) - L + 1;
@@ -193,7 +198,7 @@ __device__ __forceinline__ void s4_store(int nimg, int L, int i0, int rows, cons
         const int p0 = lb + __mul24(m.rr0, P16) + 16 * (m.jj0 + 2) + 8;
         const int p1 = lb + __mul24(m.rr0, P16) + 16 * (L + 1 - m.jj0) + 8;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < KP; ++k) {
             const int jj = m.jj0 + k * G.jp;
             if (m.jj0 < G.jp && m.rr0 < rows && jj < G.H) {
                 const int b = 2 * jj - L + 1;
@@ -319,18 +324,17 @@ __device__ __forceinline__ void s4_accumulate(const LaneTask2 (&tasks)[TPW], int
 
 // Projection of `nimg` <= IMG images for the task group starting at task
 // tg0 (tasks tg0 + wave + t NW, t < TPW) into the accumulators; lds holds IMG
-// strip buffers of kImg2Bytes, ktab (P.slots + 1 entries, 16-byte aligned)
-// the slot constants.  bad[g] is set when image g holds a
-// non-finite value.
-template <int NT, int TPW, int IMG>
+// strip buffers kImg2Bytes apart, of R rows (R <= s4_rows<NT, KP>), ktab
+// (P.slots + 1 entries, 16-byte aligned) the slot constants.  bad[g] is set
+// when image g holds a non-finite value.
+template <int NT, int TPW, int IMG, int KP = 2>
 __device__ void project_images2(const float *const (&F)[IMG], int nimg, const ProjShape &P,
-                                const float2 *__restrict__ dtab, float *lds, float4 *ktab, int tg0,
-                                float (&acc)[IMG][TPW][4], int (&bad)[IMG]) {
+                                const float2 *__restrict__ dtab, float *lds, float4 *ktab, int R,
+                                int tg0, float (&acc)[IMG][TPW][4], int (&bad)[IMG]) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int L = P.L;
-    const S4Geo G = s4_geo<NT>(L);
-    const int R = G.R;
+    const S4Geo G = s4_geo<NT>(L, R);
 #pragma unroll
     for (int g = 0; g < IMG; ++g) {
         bad[g] = 0;
@@ -346,9 +350,12 @@ __device__ void project_images2(const float *const (&F)[IMG], int nimg, const Pr
     // the padding positions (and a missing image's strips) stay zero
     __syncthreads();  // the caller may have used the region and the table
     fill_slot_table<NT>(P, dtab, ktab);
-    for (int q = threadIdx.x; q < IMG * kImg2Bytes / 16; q += NT)
-        *(float4 *)(lds + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
-    Strip4Regs<IMG> xs;
+    const int used = R * s4_positions(L);  // 16-byte chunks of an image's strips
+#pragma unroll
+    for (int g = 0; g < IMG; ++g)
+        for (int q = threadIdx.x; q < used; q += NT)
+            *(float4 *)(lds + g * (kImg2Bytes / 4) + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
+    Strip4Regs<IMG, KP> xs;
     s4_load<NT, IMG>(F, nimg, L, 0, G, xs);
     for (int i0 = 0; i0 < L; i0 += R) {
         const int rows = min(R, L - i0);
@@ -360,6 +367,29 @@ __device__ void project_images2(const float *const (&F)[IMG], int nimg, const Pr
     }
 #pragma unroll
     for (int g = 0; g < IMG; ++g) bad[g] = __syncthreads_or(bad[g]);
+}
+
+// One image per block in the four-kind strips, any number of task groups
+// (each group stages the strips again): strips of R <= strip4_rows_max(L) rows in
+// the 64 KiB region at lds, the slot table at ktab; results handed to emit,
+// which must not write to the strips or the table.  bad_out: the image holds
+// a non-finite value (then nothing is emitted).  Bitwise the sums of
+// project_image.
+template <int NT, int TPW, typename Emit>
+__device__ void project_image4(const float *__restrict__ F, const ProjShape &P,
+                               const float2 *__restrict__ dtab, float *lds, float4 *ktab, int R,
+                               int &bad_out, Emit emit) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float *const Fa[1] = {F};
+    bad_out = 0;
+    for (int tg0 = 0; tg0 < P.ntasks; tg0 += NW * TPW) {
+        float acc[1][TPW][4];
+        int bad[1];
+        project_images2<NT, TPW, 1, kImg1Passes>(Fa, 1, P, dtab, lds, ktab, R, tg0, acc, bad);
+        if (!bad[0]) emit_outputs<TPW>(P, tg0, wave, NW, lane, acc[0], emit);
+        bad_out |= bad[0];
+    }
 }
 
 }  // namespace sw

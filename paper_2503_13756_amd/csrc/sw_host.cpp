@@ -1408,7 +1408,7 @@ sw_status sw_autotune(void *ctx, const int32_t *Ls, int32_t nL, int64_t n_images
         // coordinate descent: strip rows, then tasks per wave of the tables
         // kernel, then blocks per compute unit of the per-pair alignment
         sw::MixKnobs kn;
-        const int Rmax = std::min(L, sw::strip_rows_max(L));
+        const int Rmax = sw::strip4_rows_max(L);
         int bR = 0;
         float bms = 1e30f;
         const int cands[] = {2, 4, 6, 8, 12, 16, 24, 32, 0};  // 0: the largest that fits

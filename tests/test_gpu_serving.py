@@ -105,9 +105,10 @@ def test_autotune_table_roundtrip(api, ctx, tmp_path):
 
 
 def strip_rows_max(L):
-    """Largest strip height of the projection at side L (8192 floats per
-    strip kind, rows of 4 ((L + 4) | 1) floats)."""
-    return min(L, 8192 // (4 * ((L + 4) | 1)))
+    """Largest strip height of the mixed launches' projection at side L: rows
+    of (L + 5) | 1 sixteen-byte positions in 64 KiB, at most four staging
+    passes of 512 threads over the ceil(L / 2) column pairs."""
+    return min(L, 65536 // (16 * ((L + 5) | 1)), 4 * (512 // ((L + 1) // 2)))
 
 
 def test_tiles_never_change_results(api, ctx, tmp_path):
