@@ -1,5 +1,6 @@
 // Kernel and launcher of the stand-alone line projection (images -> PMF
 // tables); the device routines are in proj_dev.h.
+#include "proj2_dev.h"
 #include "proj_dev.h"
 
 namespace sw {
@@ -14,8 +15,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
     const float *F = img + g * (int64_t)P.L * P.L;
     float *out = pmf + g * (int64_t)P.n * P.L;
     int bad = 0;
-    project_image<NT, TPW>(F, P, dtab, lds, bad,
-                           [&](int k, int b, float v) { out[k * P.L + b] = v; });
+    if constexpr (NT == 512) {  // four-kind strips, the slot table after them
+        // (an opaque offset: a constant one trips the compiler's LDS cast)
+        int off = kStripFloats;
+        asm volatile("" : "+s"(off));
+        project_image4<NT, TPW>(F, P, dtab, lds, (float4 *)(lds + off), strip4_rows_max(P.L), bad,
+                                [&](int k, int b, float v) { out[k * P.L + b] = v; });
+    } else
+        project_image<NT, TPW>(F, P, dtab, lds, bad,
+                               [&](int k, int b, float v) { out[k * P.L + b] = v; });
     if (bad) {
         // an image with a non-finite value gets an all-NaN projection
         __syncthreads();
@@ -44,7 +52,7 @@ __global__ __launch_bounds__(NT) void k_project_split(const float *__restrict__ 
 template <int NT, int TPW>
 static hipError_t launch_project_t(const float *img, int64_t N, const ProjShape &P,
                                    const float2 *dtab, float *pmf, hipStream_t s) {
-    const size_t lds = sizeof(float) * kStripFloats;
+    const size_t lds = sizeof(float) * kStripFloats + sizeof(float4) * (P.slots + 1);
     static const hipError_t attr = hipFuncSetAttribute(
         (const void *)k_project<NT, TPW>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     (void)attr;

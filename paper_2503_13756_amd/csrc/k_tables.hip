@@ -33,8 +33,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
     float *Ut = (float *)(colS + 2 * n);
     const float *F = img + g * (int64_t)L * L;
     int bad = 0;
-    project_image<NT, TPW>(F, P, d32, region, bad,
-                           [&](int k, int b, float v) { region[k * L + b] = v; });
+    if constexpr (NT == 512)  // four-kind strips; the slot table in the column-sum area
+        project_image4<NT, TPW>(F, P, d32, region, (float4 *)colS, strip4_rows_max(L), bad,
+                                [&](int k, int b, float v) { region[k * L + b] = v; });
+    else
+        project_image<NT, TPW>(F, P, d32, region, bad,
+                               [&](int k, int b, float v) { region[k * L + b] = v; });
     if (bad)
         for (int t = threadIdx.x; t < n * L; t += NT) region[t] = __int_as_float(0x7fc00000);
     __syncthreads();
@@ -137,9 +141,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
     const float *F = img + g * (int64_t)L * L;
     int bad = 0;
     // columns ldp = L + 4 floats apart: the filter's 16 columns x 4 bins of
-    // one fragment read fall in distinct banks
-    project_image<NT, TPW>(F, P, d32, region, bad,
-                           [&](int k, int b, float v) { region[k * ldp + b] = v; });
+    // one fragment read fall in distinct banks; four-kind strips, the slot
+    // table in the column-sum area
+    project_image4<NT, TPW>(F, P, d32, region, (float4 *)colS, strip4_rows_max(L), bad,
+                            [&](int k, int b, float v) { region[k * ldp + b] = v; });
     if (bad)
         for (int t = threadIdx.x; t < n * ldp; t += NT) region[t] = __int_as_float(0x7fc00000);
     for (int i = threadIdx.x; i < HX; i += NT) hs[i] = hx[i];
