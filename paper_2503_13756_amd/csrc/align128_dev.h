@@ -119,20 +119,33 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 constexpr int kA128Stride = 18;  // complex per lane row of the transpose buffer (16 + pad)
 constexpr int kA128VRow = 132;   // floats per staged table row (128 + pad)
+// The per-wave layout: the two rows of a packed pair contiguous (as in the
+// table, so that one 1 KiB memory-to-LDS copy stages a pair), pairs 264
+// floats apart (the 8 groups' reads still fall in distinct banks).
+constexpr int kA128PairStride = 264;
+
+struct A128NoHook {
+    __device__ void operator()() const {}
+};
 
 // Spectrum of the packed row of lane group `grp`, whose two table rows are
-// staged at varea + 2 grp kA128VRow (rows kA128VRow floats apart): lane l8
+// staged at varea + 2 grp kA128VRow (rows kA128VRow floats apart), or with
+// PAIRED at varea + grp kA128PairStride (rows 128 floats apart): lane l8
 // ends with Z[2 l8 + tau + 16 s] in u_tau[s].  buf: the group's 8 x
 // kA128Stride transpose buffer (it may overlap the staged rows: they are read
-// first).  Wave-synchronous.
+// first).  after(): called once the wave's last LDS read of the staged rows
+// and the buffer is done (the wave may refill them).  Wave-synchronous.
+template <bool PAIRED = false, typename After = A128NoHook>
 __device__ __forceinline__ void a128_row_spectrum(const float *varea, float2 *buf,
                                                   const float2 *tw, int grp, int l8,
-                                                  float2 (&u0)[8], float2 (&u1)[8]) {
+                                                  float2 (&u0)[8], float2 (&u1)[8],
+                                                  After after = After()) {
     constexpr int n = 128;
+    constexpr int kRow2 = PAIRED ? 128 : kA128VRow;
     float2 x[16];
-    const float *zr = varea + 2 * grp * kA128VRow + l8;
+    const float *zr = varea + (PAIRED ? grp * kA128PairStride : 2 * grp * kA128VRow) + l8;
 #pragma unroll
-    for (int m = 0; m < 16; ++m) x[m] = make_float2(zr[8 * m], zr[kA128VRow + 8 * m]);
+    for (int m = 0; m < 16; ++m) x[m] = make_float2(zr[8 * m], zr[kRow2 + 8 * m]);
     wave_lds_sync();
     dft16(x);
     // l8 t < n: the twiddle addresses are formed here from an opaque copy of
@@ -153,6 +166,7 @@ __device__ __forceinline__ void a128_row_spectrum(const float *varea, float2 *bu
         u1[l] = make_float2(q.z, q.w);
     }
     wave_lds_sync();
+    after();
     dft8(u0);
     dft8(u1);
 }
@@ -523,32 +537,37 @@ __device__ void align128_wave(const A128Job &job, float2 *xb, const float2 *tw) 
     float *varea = (float *)xb;
     float2 *buf = xb + grp * 8 * kA128Stride;
 
-    // 16 table rows [r0, r0 + 16) of V into varea (rows kA128VRow apart,
-    // coalesced 16-byte loads; rows past Q read as zero)
-    // (lane: row lane / 32 + 2 i, 16-byte column lane mod 32 for i < 8, so
-    // that every address is one per-lane base plus a constant)
-    const int srow = lane >> 5, sc4 = 4 * (lane & 31);
-    float *sdst = varea + srow * kA128VRow + sc4;
+    // 8 packed pairs of table rows [r0, r0 + 16) of V into varea by
+    // memory-to-LDS copies, one 1 KiB copy per pair (the pair's two rows are
+    // contiguous in the table and in varea, pairs kA128PairStride apart).
+    // Pairs past Q copy the last pair again: their transforms are computed
+    // and never used.  The next stage's copies are issued as soon as the
+    // current rows and the transpose buffer have been read, so that they fly
+    // during the last transforms and the spectral dot.
     auto stage = [&](int r0) {
-        const float *src = V + (int64_t)(r0 + srow) * n + sc4;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (r0 + srow + 2 * i < Q) v = *(const float4 *)(src + 2 * i * n);
-            *(float4 *)(sdst + 2 * i * kA128VRow) = v;
+            const int r = min(r0 + 2 * i, Q - 2);  // Q is even
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(V + (int64_t)r * n + 4 * lane),
+                (__attribute__((address_space(3))) void *)(varea + i * kA128PairStride), 16, 0,
+                0);
         }
-        wave_lds_sync();
     };
 
     // --- angle FFTs of the packed rows and the spectral dot
     float2 acc[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = make_float2(0.f, 0.f);
+    stage(0);
     for (int pbase = 0; pbase < P2; pbase += 8) {
-        stage(2 * pbase);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this stage's copies have landed
+        wave_lds_sync();
         const int p = pbase + grp;
         float2 u0[8], u1[8];
-        a128_row_spectrum(varea, buf, tw, grp, l8, u0, u1);
+        a128_row_spectrum<true>(varea, buf, tw, grp, l8, u0, u1, [&]() {
+            if (pbase + 8 < P2) stage(2 * (pbase + 8));
+        });
         if (p < P2) a128_dot(acc, u0, u1, job.G, job.GX, p, l8, job.bf16);
     }
 
