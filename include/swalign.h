@@ -134,6 +134,21 @@ sw_status sw_ctx_destroy(void *ctx);
 const char *sw_last_error(void);
 const char *sw_version(void);
 
+/* The work plan of the line projection (Sec. 2.2/2.3, step 1) for side L and
+   n angles, as every projection launch of (L, n) uses it: host memory only,
+   no context and no device work (for inspection and tests).  Items are
+   (slot angle m <= n/8, bin b) pairs, item = m L + b; a task is 64 lanes,
+   eight units of 8 consecutive bins of one slot.  perm[t 64 + l] = the item
+   of lane l of task t, or -1; [row_lo[t], row_hi[t]] = the image rows task t
+   reads (every row where one of its items' lines has a pixel of non-zero
+   weight inside the disk; row_lo > row_hi for a task with none).  *ntasks is
+   set first; the arrays (cap_tasks tasks; NULL with cap_tasks = 0 to query
+   the count) are filled when cap_tasks >= *ntasks, else SW_E_INVALID.  The
+   plan does not change results: rows outside a task's range add only zeros. */
+sw_status sw_projection_plan(int32_t L, int32_t n, int32_t cap_tasks, int32_t *perm /*host*/,
+                             int32_t *row_lo /*host*/, int32_t *row_hi /*host*/,
+                             int32_t *ntasks /*host*/);
+
 /* Step 1, line projection (Sec. 2.2 Radon transform, Sec. 2.3 columns of U).
    pmf[g][k][b] = sum over masked pixels of max(F,0) * max(0, 1 - |p.d_k - c_b|/h)
    with d_k = (cos theta_k, -sin theta_k) and c_b the centre of bin b: each

@@ -83,6 +83,7 @@ SIGNATURES = [
     ("sw_ctx_destroy", I32, [P]),
     ("sw_last_error", ctypes.c_char_p, []),
     ("sw_version", ctypes.c_char_p, []),
+    ("sw_projection_plan", I32, [I32, I32, I32, P, P, P, ctypes.POINTER(ctypes.c_int32)]),
     ("sw_project", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P]),
     ("sw_quantiles", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),
     ("sw_tables", I32, [P, P, I64, ctypes.POINTER(sw_geom), P, P, P]),

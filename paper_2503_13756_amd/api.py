@@ -65,6 +65,23 @@ def geom(L, n, Q, levels=_abi.LEVELS_MIDPOINT):
     return sw_geom(int(L), int(n), int(Q), int(levels))
 
 
+def projection_plan(L: int, n: int):
+    """sw_projection_plan (host only, no context): the projection work plan
+    of (L, n) as numpy arrays: perm [ntasks, 64] (item = slot * L + bin, or
+    -1) and rows [ntasks, 2] (first and last image row each task reads)."""
+    import numpy as np
+
+    lib = _abi.load()
+    nt = ctypes.c_int32(0)
+    check(lib.sw_projection_plan(int(L), int(n), 0, None, None, None, ctypes.byref(nt)))
+    perm = np.empty((nt.value, 64), np.int32)
+    lo = np.empty(nt.value, np.int32)
+    hi = np.empty(nt.value, np.int32)
+    check(lib.sw_projection_plan(int(L), int(n), nt.value, perm.ctypes.data, lo.ctypes.data,
+                                 hi.ctypes.data, ctypes.byref(nt)))
+    return perm, np.stack([lo, hi], axis=1)
+
+
 def project(ctx: Context, imgs: torch.Tensor, n: int, stream=None, out=None):
     """sw_project: [N, L, L] float32 -> [N, n, L] float32 projections."""
     _need(imgs, torch.float32, "imgs")

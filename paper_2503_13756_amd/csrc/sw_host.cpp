@@ -742,6 +742,29 @@ const char *sw_last_error(void) { return g_err.c_str(); }
 
 const char *sw_version(void) { return "swalign 0.1 (gfx950)"; }
 
+sw_status sw_projection_plan(int32_t L, int32_t n, int32_t cap_tasks, int32_t *perm,
+                             int32_t *row_lo, int32_t *row_hi, int32_t *ntasks) {
+    if (!ntasks) return fail(SW_E_INVALID, "ntasks out-pointer is NULL");
+    if (L < 8 || L > sw::kMaxL) return fail(SW_E_INVALID, "L = %d outside [8, %d]", L, sw::kMaxL);
+    if (n < 8 || n > sw::kMaxN || n % 8 != 0)
+        return fail(SW_E_INVALID, "n = %d is not a multiple of 8 in [8, %d]", n, sw::kMaxN);
+    const int nt = sw::proj_ntasks(L, n);
+    *ntasks = nt;
+    if (cap_tasks == 0 && !perm && !row_lo && !row_hi) return SW_OK;
+    if (cap_tasks < nt || !perm || !row_lo || !row_hi)
+        return fail(SW_E_INVALID, "the plan of (L = %d, n = %d) has %d tasks (cap %d)", L, n, nt,
+                    cap_tasks);
+    std::vector<int> pv;
+    std::vector<int2> tr;
+    build_plan(L, n, pv, tr);
+    for (size_t i = 0; i < pv.size(); ++i) perm[i] = pv[i];
+    for (int t = 0; t < nt; ++t) {
+        row_lo[t] = tr[t].x;
+        row_hi[t] = tr[t].y;
+    }
+    return SW_OK;
+}
+
 sw_status sw_ctx_create(void **ctx, int device, const char *tune_json) {
     (void)tune_json;
     if (!ctx) return fail(SW_E_INVALID, "ctx out-pointer is NULL");
