@@ -45,7 +45,7 @@ MFMA_FILE = os.path.join(PROFILES, "mfma_k_corr_mfma_all_pairs_2000.txt")
 STATS_FILE = os.path.join(PROFILES, "kernels_all_legs_stats.txt")
 KERNEL_SOURCES = {
     "k_tables2": ["k_tables.hip", "proj2_dev.h", "proj_dev.h", "quant_dev.h", "sw_internal.h"],
-    "k_project": ["k_project.hip", "proj_dev.h", "sw_internal.h"],
+    "k_project": ["k_project.hip", "proj2_dev.h", "proj_dev.h", "sw_internal.h"],
     "k_quantile": ["k_quantile.hip", "quant_dev.h", "sw_internal.h"],
     "k_align128w": ["k_align128.hip", "align128_dev.h", "align_dev.h", "fft_dev.h",
                     "sw_internal.h"],
