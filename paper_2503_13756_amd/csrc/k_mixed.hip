@@ -43,7 +43,7 @@ __device__ __forceinline__ int64_t next_work(unsigned long long *counter, int64_
 // alone on an otherwise idle device.  `scratch` holds one PMF slot of
 // slot_floats per block, used by images whose PMF table does not fit in LDS.
 template <int NT, int TPW>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWaves<NT, TPW>, NT <= 256 ? 2 : 4))) void k_tables_mixed(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_tables_mixed(
     const MixGroup *__restrict__ G0, const MixGroup *__restrict__ G1, unsigned long long *counter,
     float *scratch, int64_t slot_floats, int region_floats, int /*lmax*/, int nmax) {
     constexpr int NW = NT / 64;
@@ -252,7 +252,8 @@ MixLaunch plan_mixed(MixItem *items, int nitems, MixKnobs knobs) {
     }
     // tables kernel instance: both handle any item (more task groups with
     // fewer tasks per wave); the knob overrides the smallest-that-fits rule
-    if (knobs.tpw == kMixTablesTasksSmall || knobs.tpw == TPW) {
+    if (knobs.tpw == kMixTablesTasksSmall || knobs.tpw == TPW ||
+        knobs.tpw == kMixTablesTasksLarge) {
         // the region must still hold the fused PMFs: fused needs one group
         bool ok = true;
         for (int i = 0; i < nitems; ++i)
@@ -279,6 +280,10 @@ void prepare_mixed() {
         (const void *)k_tables_mixed<NTT, kMixTablesTasksSmall>,
         hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     (void)a0;
+    static const hipError_t a4 = hipFuncSetAttribute(
+        (const void *)k_tables_mixed<NTT, kMixTablesTasksLarge>,
+        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)a4;
     static const hipError_t a2 = hipFuncSetAttribute(
         (const void *)k_refspec_mixed<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     static const hipError_t a3 = hipFuncSetAttribute(
@@ -298,6 +303,10 @@ hipError_t launch_mixed(const MixGroup *d_refs, const MixGroup *d_imgs, const Mi
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters, 4);
     if (m.tpw == kMixTablesTasksSmall)
         hipLaunchKernelGGL((k_tables_mixed<NTT, kMixTablesTasksSmall>), dim3((unsigned)grid),
+                           dim3(NTT), m.tables_lds, s, d_refs, d_imgs, counters + 0, scratch,
+                           m.slot_floats, m.region_floats, m.lmax, m.nmax);
+    else if (m.tpw == kMixTablesTasksLarge)
+        hipLaunchKernelGGL((k_tables_mixed<NTT, kMixTablesTasksLarge>), dim3((unsigned)grid),
                            dim3(NTT), m.tables_lds, s, d_refs, d_imgs, counters + 0, scratch,
                            m.slot_floats, m.region_floats, m.lmax, m.nmax);
     else

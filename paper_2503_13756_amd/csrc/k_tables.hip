@@ -1,9 +1,11 @@
-// Fused projection + CDF/quantile stage: one block turns one image into its
-// quantile table without the projection leaving the chip.  The projection
-// accumulates in registers across LDS image strips (proj_dev.h); after the
-// last strip the block writes the PMF table into the same LDS region and
-// inverts its columns there (quant_dev.h).  Results are identical in form to
-// the stand-alone projection followed by the stand-alone quantile stage.
+// Fused projection + CDF/quantile stage: one block turns one image (two, in
+// k_tables2) into its quantile table without the projection leaving the
+// chip.  The projection accumulates in registers across LDS image strips
+// (the four-kind strips of proj2_dev.h for 512-thread blocks, the
+// sliding-window strips of proj_dev.h for 256 threads); after the last strip
+// the block writes the PMF table into the same LDS region and inverts its
+// columns there (quant_dev.h).  Results are bitwise those of the stand-alone
+// projection followed by the stand-alone quantile stage.
 #include "proj2_dev.h"
 #include "proj_dev.h"
 #include "quant_dev.h"

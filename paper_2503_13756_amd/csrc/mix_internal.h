@@ -8,8 +8,11 @@ namespace sw {
 constexpr int kMaxMix = 64;
 // block size and tasks per wave of the persistent tables kernel; launches
 // whose every item projects in one task group of five tasks per wave take
-// that smaller instance (fewer registers, no spills)
-constexpr int kMixTablesThreads = 512, kMixTablesTasks = 6, kMixTablesTasksSmall = 5;
+// that smaller instance (fewer registers, no spills); the nine-task instance
+// (a knob of the autotuner) restages an image for fewer task groups at large
+// L (two instead of three at L = n = 256) at three waves per SIMD
+constexpr int kMixTablesThreads = 512, kMixTablesTasks = 6, kMixTablesTasksSmall = 5,
+              kMixTablesTasksLarge = 9;
 
 // One stack of images of one geometry aligned against one reference.
 struct MixItem {
@@ -53,7 +56,7 @@ struct MixLaunch {
 };
 // Launch knobs of the autotuner (0: the default); none changes a result.
 struct MixKnobs {
-    int tpw = 0;        // kMixTablesTasksSmall or kMixTablesTasks
+    int tpw = 0;        // kMixTablesTasksSmall, kMixTablesTasks or kMixTablesTasksLarge
     int align_bpc = 0;  // 1 .. 8
 };
 // Fills the per-item tile fields (R clamped, TC, fused) and the launch sizes;

@@ -22,7 +22,10 @@
 // R columns transposed (layout in sw_internal.h: four shifted copies of each,
 // so that every four-pixel window is one aligned 16-byte LDS read), so that
 // all four variants read along LDS rows.  Accumulators live in registers
-// across strips.
+// across strips.  This sliding-window form serves the 256- and 1024-thread
+// and split kernels; the 512-thread kernels use the four-kind strips of
+// proj2_dev.h (same sums, bitwise), which also reuse the task plan, the line
+// weights and the emit step defined here.
 #pragma once
 #include "sw_internal.h"
 

@@ -1446,7 +1446,7 @@ sw_status sw_autotune(void *ctx, const int32_t *Ls, int32_t nL, int64_t n_images
             }
         }
         int btpw = 0;
-        for (int tpw : {sw::kMixTablesTasksSmall, sw::kMixTablesTasks}) {
+        for (int tpw : {sw::kMixTablesTasksSmall, sw::kMixTablesTasks, sw::kMixTablesTasksLarge}) {
             if (e != hipSuccess) break;
             sw::MixKnobs k2 = kn;
             k2.tpw = tpw;

@@ -123,7 +123,7 @@ def test_tiles_never_change_results(api, ctx, tmp_path):
     cases = [(L, R, 0, 0) for L in (64, 96, 128, 256) for R in range(1, strip_rows_max(L) + 1)]
     # the other knobs: tables tasks per wave and alignment blocks per CU
     # (the launch takes them from its L with the most projection work: 256)
-    cases += [(256, 0, tpw, bpc) for tpw in (5, 6) for bpc in (1, 2, 4, 6, 8)]
+    cases += [(256, 0, tpw, bpc) for tpw in (5, 6, 9) for bpc in (1, 2, 4, 6, 8)]
     for L, R, tpw, bpc in cases:
         path = tmp_path / f"t{L}_{R}_{tpw}_{bpc}.json"
         extra = (f', "tpw": {tpw}' if tpw else "") + (f', "align_bpc": {bpc}' if bpc else "")
