@@ -63,7 +63,14 @@ def raw_stack(L, N, seed):
     ref, imgs = synth.make_raw_stack(seed, L, N)
     keep = synth.disk_keep(L)
     # every image has negative pixels inside the disk and positive ones
-    # outside it (at L >= 64 about a third of the disk is negative)
+    # outside it (at L >= 64 about a third of the disk is negative; the few
+    # disk pixels of the smallest sides may all be positive, then the
+    # smallest one is made negative)
+    inside = imgs[:, keep]
+    for g in np.nonzero(~(inside < 0).any(axis=1))[0]:
+        k = int(np.argmin(inside[g]))
+        inside[g, k] = -abs(inside[g, k]) - 1.0
+    imgs[:, keep] = inside
     assert np.all((imgs[:, keep] < 0).any(axis=1))
     assert np.all((imgs[:, ~keep] > 0).all(axis=1))
     return ref, imgs
@@ -77,7 +84,7 @@ def inputs(kind, L, N, seed):
 # with a radix-3 angle count, L = 127 takes the n = 128 register-FFT path
 # (176, 144, 144) and (120, 256, 64): seven and eight tasks per wave of a
 # 512-thread block (the one-image kernels beyond the two-image one)
-GEOMS = [(16, 16, 16), (39, 48, 48), (40, 24, 20), (64, 64, 64), (96, 96, 96),
+GEOMS = [(8, 8, 8), (16, 16, 16), (39, 48, 48), (40, 24, 20), (64, 64, 64), (96, 96, 96),
          (127, 128, 128), (128, 128, 128), (64, 128, 48), (176, 144, 144), (120, 256, 64),
          (192, 192, 192), (256, 256, 256)]
 
