@@ -44,15 +44,17 @@ __host__ __device__ inline int s4_positions(int L) { return (L + 5) | 1; }
 // itself).
 __host__ __device__ inline int s4_pairs(int L) { return (L + 1) >> 1; }
 // Strip rows per image: as many as fit `bytes`, at most KP times the rows one
-// pass of NT threads covers (so that KP passes stage any strip).  With this
-// bound KP passes also cover the column pairs for every L <= 1024 (ceil(L/2)
-// <= NT for NT = 512).
+// pass of NT threads covers (so that KP passes stage the row pairs of any
+// strip), and at most NT / ceil(H / KP) (so that KP passes of NT / R image
+// rows stage the H column pairs); any smaller R satisfies both.
 template <int NT = 512, int KP = 2>
 __host__ __device__ inline int s4_rows(int L, int bytes = kImg2Bytes) {
     int r = bytes / (16 * s4_positions(L));
     if (r > L) r = L;
-    const int cap = KP * (NT / s4_pairs(L));
-    return r < cap ? r : cap;
+    const int H = s4_pairs(L);
+    const int cap = KP * (NT / H), cap1 = NT / ((H + KP - 1) / KP);
+    if (r > cap) r = cap;
+    return r < cap1 ? r : cap1;
 }
 // Whether the staging covers L with 512-thread blocks.
 __host__ __device__ inline bool s4_supported(int L) { return L >= 2 && s4_pairs(L) <= 512; }

@@ -28,14 +28,17 @@ __host__ __device__ inline int strip_stride(int L) { return (L + kStripPad + 1) 
 __host__ __device__ inline int strip_row_floats(int L) { return 4 * strip_stride(L); }
 __host__ __device__ inline int strip_rows_max(int L) { return kKindFloats / strip_row_floats(L); }
 // Rows of the four-kind strips of one image (the persistent mixed tables
-// kernel): (L + 5) | 1 positions of 16 bytes per row in the 64 KiB region, at
-// most four staging passes of 512 threads over the ceil(L / 2) column pairs.
+// kernel): (L + 5) | 1 positions of 16 bytes per row in the 64 KiB region,
+// staged in at most four passes of 512 threads both over the strip's rows of
+// ceil(L / 2) column pairs (R <= 4 (512 / H)) and over the H image rows of
+// its column runs (R <= 512 / ceil(H / 4)).
 __host__ __device__ inline int strip4_rows_max(int L) {
     const int P = (L + 5) | 1, H = (L + 1) >> 1;
     int r = 65536 / (16 * P);
     if (r > L) r = L;
-    const int cap = 4 * (512 / H);
-    return r < cap ? r : cap;
+    const int cap = 4 * (512 / H), cap1 = 512 / ((H + 3) / 4);
+    if (r > cap) r = cap;
+    return r < cap1 ? r : cap1;
 }
 
 // Projection work order of one geometry (L, n).  The projection's work

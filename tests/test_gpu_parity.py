@@ -83,10 +83,12 @@ def inputs(kind, L, N, seed):
 # odd sides too: L = 39 is the digits' size in the paper's timings (Table 4)
 # with a radix-3 angle count, L = 127 takes the n = 128 register-FFT path
 # (176, 144, 144) and (120, 256, 64): seven and eight tasks per wave of a
-# 512-thread block (the one-image kernels beyond the two-image one)
-GEOMS = [(8, 8, 8), (16, 16, 16), (39, 48, 48), (40, 24, 20), (64, 64, 64), (96, 96, 96),
-         (127, 128, 128), (128, 128, 128), (64, 128, 48), (176, 144, 144), (120, 256, 64),
-         (192, 192, 192), (256, 256, 256)]
+# 512-thread block (the one-image kernels beyond the two-image one); at
+# L = 65 and 82 the one-image strips' height is set by the staging of the
+# column runs, not by the LDS
+GEOMS = [(8, 8, 8), (16, 16, 16), (39, 48, 48), (40, 24, 20), (64, 64, 64), (65, 48, 48),
+         (82, 72, 72), (96, 96, 96), (127, 128, 128), (128, 128, 128), (64, 128, 48),
+         (176, 144, 144), (120, 256, 64), (192, 192, 192), (256, 256, 256)]
 
 
 @pytest.mark.parametrize("kind", ["clean", "raw"])

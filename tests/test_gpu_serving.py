@@ -108,7 +108,8 @@ def strip_rows_max(L):
     """Largest strip height of the mixed launches' projection at side L: rows
     of (L + 5) | 1 sixteen-byte positions in 64 KiB, at most four staging
     passes of 512 threads over the ceil(L / 2) column pairs."""
-    return min(L, 65536 // (16 * ((L + 5) | 1)), 4 * (512 // ((L + 1) // 2)))
+    H = (L + 1) // 2
+    return min(L, 65536 // (16 * ((L + 5) | 1)), 4 * (512 // H), 512 // -(-H // 4))
 
 
 def test_tiles_never_change_results(api, ctx, tmp_path):
