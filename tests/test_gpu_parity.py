@@ -106,6 +106,43 @@ def test_project_parity(api, ctxs, oracle, L, n, Q, policy, kind):
     assert err.max() < 1e-5, err
 
 
+def test_every_side_projects_and_tables(api, ctxs, oracle):
+    """Every side L = 8 .. 256 (odd and even: the strip heights, staging
+    passes and column pairs of the four-kind strips change with L), raw
+    inputs, n = Q = 8: the one-image projection and the two-image tables (an
+    odd count leaves a block with one image) against the oracle."""
+    worst_p = worst_q = 0.0
+    for L in range(8, 257):
+        _, imgs = raw_stack(L, 3, 4000 + L)
+        x = dev(imgs)
+        P0, _ = oracle.project(imgs, 8)
+        pmf = api.project(ctxs["perimage"], x, 8).cpu().numpy()
+        ep = (np.abs(pmf - P0).max(axis=(1, 2)) / P0.max(axis=(1, 2))).max()
+        assert ep < 1e-5, (L, ep)
+        # the fused tables against the oracle's quantiles of the GPU's own FP32
+        # projections (the fused and staged projections are bitwise equal)
+        q0, _ = oracle.quantiles(pmf.astype(np.float64), 8, 0)
+        q1, _ = api.tables(ctxs["perimage"], x, 8, 8)
+        eq = np.abs(q1.cpu().numpy() - q0).max()
+        assert eq < 2e-6, (L, eq)
+        # the one-image fused kernel gives bitwise the same tables
+        q2, _ = api.tables(ctxs["one"], x, 8, 8)
+        assert np.array_equal(q2.cpu().numpy(), q1.cpu().numpy()), L
+        worst_p, worst_q = max(worst_p, ep), max(worst_q, eq)
+    print(f"worst relative projection error {worst_p:.2e}, quantile error {worst_q:.2e}")
+    # the persistent mixed kernel (stacks of every third side, 20 per launch)
+    Ls = list(range(8, 257, 3))
+    for c0 in range(0, len(Ls), 20):
+        stacks, want = [], []
+        for L in Ls[c0:c0 + 20]:
+            ref, imgs = raw_stack(L, 3, 5000 + L)
+            stacks.append((dev(ref), dev(imgs)))
+            want.append(api.tables(ctxs["one"], dev(imgs), 8, 8)[0].cpu().numpy())
+        got = api.align_stacks(ctxs["perimage"], stacks, n=8, Q=8)
+        for L, g, w in zip(Ls[c0:c0 + 20], got, want):
+            assert np.array_equal(g["qt"].cpu().numpy(), w), L
+
+
 @pytest.mark.parametrize("policy", ["perimage", "split"])
 @pytest.mark.parametrize("L,n,Q", GEOMS)
 @pytest.mark.parametrize("levels", [0, 1])
