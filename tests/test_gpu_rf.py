@@ -9,7 +9,7 @@ from tests import parity
 
 pytestmark = pytest.mark.gpu
 
-RF_GEOMS = [(16, 16, 16), (39, 48, 24), (40, 24, 20), (64, 64, 64), (96, 96, 96),
+RF_GEOMS = [(16, 16, 16), (39, 48, 24), (40, 24, 20), (64, 64, 64), (65, 48, 48), (96, 96, 96),
             (128, 128, 128), (256, 64, 32)]
 
 
