@@ -61,7 +61,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
 template <int NT, int TPW>
 constexpr int kParkFloats = TPW >= 5 ? TPW * 4 * NT : 0;
 
-template <int NT, int TPW, int QM>
+template <int NT, int TPW, int QM, int IB>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_tables2(
     const float *__restrict__ img, int64_t N, TablesShape T, const float2 *__restrict__ d32,
     const double2 *__restrict__ d64, float *__restrict__ qt, double *__restrict__ aux) {
@@ -79,8 +79,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     float acc[2][TPW][4];
     int bad[2];
     // the slot table sits in the column-sum area until the quantile phase
-    project_images2<NT, TPW, 2>(F, nimg, P, d32, region, (float4 *)colS, s4_rows<NT>(L), 0, acc,
-                                bad);
+    project_images2<NT, TPW, 2, 2, IB>(F, nimg, P, d32, region, (float4 *)colS,
+                                       s4_rows<NT>(L, IB), 0, acc, bad);
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *park = qt + (g0 + 1) * (int64_t)Q * n + threadIdx.x;
     if (kParkFloats<NT, TPW> > 0 && nimg == 2) {
@@ -201,15 +201,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
     }
 }
 
-// Bytes of LDS the fused kernel needs for a geometry (0 when it cannot run).
-size_t tables_lds_bytes(Geo g, int nt, TablesShape *out) {
+// Bytes of LDS the fused kernel needs for a geometry (0 when it cannot run),
+// with a strip region of at least min_region floats.
+size_t tables_lds_bytes(Geo g, int nt, TablesShape *out, int min_region = 0) {
     TablesShape T;
     T.P = proj_shape(g.L, g.n);
     T.Q = g.Q;
     T.levels = g.levels;
     // all tasks in one group: the PMF table is written over the strip buffers
     if (tasks_per_wave(T.P.ntasks, nt) > (nt >= 512 ? 9 : 20)) return 0;
-    int region = kStripFloats;
+    int region = kStripFloats > min_region ? kStripFloats : min_region;
     if (region < g.n * g.L) region = g.n * g.L;
     region = (region + 1) & ~1;
     T.region_floats = region;
@@ -236,24 +237,40 @@ static hipError_t launch_tables_t(const float *img, int64_t N, const TablesShape
     return hipGetLastError();
 }
 
-template <int NT, int TPW, int QM>
+template <int NT, int TPW, int QM, int IB>
 static hipError_t launch_tables2_q(const float *img, int64_t N, const TablesShape &T, size_t lds,
                                    const AngleTable &t, float *qt, double *aux, hipStream_t s) {
-    static const hipError_t attr = hipFuncSetAttribute((const void *)k_tables2<NT, TPW, QM>,
+    static const hipError_t attr = hipFuncSetAttribute((const void *)k_tables2<NT, TPW, QM, IB>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                                        152 * 1024);
     (void)attr;
-    hipLaunchKernelGGL((k_tables2<NT, TPW, QM>), dim3((unsigned)((N + 1) / 2)), dim3(NT), lds, s,
-                       img, N, T, t.d32, t.d64, qt, aux);
+    hipLaunchKernelGGL((k_tables2<NT, TPW, QM, IB>), dim3((unsigned)((N + 1) / 2)), dim3(NT), lds,
+                       s, img, N, T, t.d32, t.d64, qt, aux);
     return hipGetLastError();
 }
 
-template <int NT, int TPW>
+template <int NT, int TPW, int IB>
 static hipError_t launch_tables2_t(const float *img, int64_t N, const TablesShape &T, size_t lds,
                                    const AngleTable &t, float *qt, double *aux, hipStream_t s) {
     if (quant_mode_for(T.P.L) == kQuantHalf)
-        return launch_tables2_q<NT, TPW, kQuantHalf>(img, N, T, lds, t, qt, aux, s);
-    return launch_tables2_q<NT, TPW, kQuantWave>(img, N, T, lds, t, qt, aux, s);
+        return launch_tables2_q<NT, TPW, kQuantHalf, IB>(img, N, T, lds, t, qt, aux, s);
+    return launch_tables2_q<NT, TPW, kQuantWave, IB>(img, N, T, lds, t, qt, aux, s);
+}
+
+// The two-image kernel for w tasks per wave with image strips IB bytes apart
+// (the region holds both), if an instance fits; hipErrorNotSupported if not.
+template <int IB>
+static hipError_t launch_tables2_w(const float *img, int64_t N, Geo g, const TablesShape &T,
+                                   size_t lds, int w, const AngleTable &t, float *qt, double *aux,
+                                   hipStream_t s) {
+    const int64_t table = (int64_t)g.Q * g.n;
+    if (w <= 2) return launch_tables2_t<512, 2, IB>(img, N, T, lds, t, qt, aux, s);
+    if (w <= 4) return launch_tables2_t<512, 4, IB>(img, N, T, lds, t, qt, aux, s);
+    if (w <= 5 && table >= kParkFloats<512, 5>)
+        return launch_tables2_t<512, 5, IB>(img, N, T, lds, t, qt, aux, s);
+    if (w <= 6 && table >= kParkFloats<512, 6>)
+        return launch_tables2_t<512, 6, IB>(img, N, T, lds, t, qt, aux, s);
+    return hipErrorNotSupported;
 }
 
 hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t,
@@ -268,14 +285,23 @@ hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t
     T.P.trow = pp.trow;
     if (lds != 0 && lds <= 79 * 1024) {
         const int w = tasks_per_wave(T.P.ntasks, 512);
-        if (per_block == 2 && T.region_floats * 4 >= 2 * kImg2Bytes && s4_supported(g.L)) {
-            const int64_t table = (int64_t)g.Q * g.n;
-            if (w <= 2) return launch_tables2_t<512, 2>(img, N, T, lds, t, qt, aux, s);
-            if (w <= 4) return launch_tables2_t<512, 4>(img, N, T, lds, t, qt, aux, s);
-            if (w <= 5 && table >= kParkFloats<512, 5>)
-                return launch_tables2_t<512, 5>(img, N, T, lds, t, qt, aux, s);
-            if (w <= 6 && table >= kParkFloats<512, 6>)
-                return launch_tables2_t<512, 6>(img, N, T, lds, t, qt, aux, s);
+        if (per_block == 2 && s4_supported(g.L)) {
+            // two images' strips a little over 32 KiB apart (one more strip
+            // row at L = 128) while the block still fits two per CU and the
+            // quantile phase keeps its column tile
+            TablesShape T2;
+            const size_t lds2 = tables_lds_bytes(g, 512, &T2, 2 * kImg2BytesWide / 4);
+            if (lds2 != 0 && lds2 <= 79 * 1024 && T2.TC >= T.TC) {
+                T2.P.perm = pp.perm;
+                T2.P.trow = pp.trow;
+                const hipError_t e =
+                    launch_tables2_w<kImg2BytesWide>(img, N, g, T2, lds2, w, t, qt, aux, s);
+                if (e != hipErrorNotSupported) return e;
+            }
+            if (T.region_floats * 4 >= 2 * kImg2Bytes) {
+                const hipError_t e = launch_tables2_w<kImg2Bytes>(img, N, g, T, lds, w, t, qt, aux, s);
+                if (e != hipErrorNotSupported) return e;
+            }
         }
         if (w <= 2) return launch_tables_t<512, 2>(img, N, T, lds, t, qt, aux, s);
         if (w <= 4) return launch_tables_t<512, 4>(img, N, T, lds, t, qt, aux, s);

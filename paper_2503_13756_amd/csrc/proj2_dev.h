@@ -35,7 +35,9 @@
 
 namespace sw {
 
-constexpr int kImg2Bytes = 32768;  // strips of the second image: half the 64 KiB region
+// strips of the second image: half the 64 KiB region, or a little more where
+// the block's LDS allows it (k_tables2's IB)
+constexpr int kImg2Bytes = 32768, kImg2BytesWide = 34816;
 
 // Positions per strip row: j = -2 .. L + 2, odd so that consecutive rows
 // start in different banks.
@@ -160,7 +162,7 @@ __device__ __forceinline__ void s4_load(const float *const (&F)[IMG], int nimg, 
 // x^2 + y^2 <= (1 - h)^2, and put each pair into its two positions.  A
 // non-finite pixel (inside the disk or not) sets bad[g]; every pixel of the
 // image passes through the row pairs once.
-template <int NT, int IMG, int KP>
+template <int NT, int IMG, int KP, int IB = kImg2Bytes>
 __device__ __forceinline__ void s4_store(int nimg, int L, int i0, int rows, const S4Geo &G,
                                          const Strip4Regs<IMG, KP> &X, float *lds,
                                          int (&bad)[IMG]) {
@@ -189,8 +191,8 @@ __device__ __forceinline__ void s4_store(int nimg, int L, int i0, int rows, cons
                     const float x = X.x[g][0][k][0], y = X.x[g][0][k][1];
                     nf[g] = fmaf(y, 0.f, fmaf(x, 0.f, nf[g]));
                     const float u = in ? fmaxf(x, 0.f) : 0.f, v = in ? fmaxf(y, 0.f) : 0.f;
-                    *(LdsF2 *)(uintptr_t)(p0 + dk + g * kImg2Bytes) = f32x2v{u, v};
-                    *(LdsF2 *)(uintptr_t)(p1 + dk + g * kImg2Bytes) = f32x2v{v, u};
+                    *(LdsF2 *)(uintptr_t)(p0 + dk + g * IB) = f32x2v{u, v};
+                    *(LdsF2 *)(uintptr_t)(p1 + dk + g * IB) = f32x2v{v, u};
                 }
             }
         }
@@ -211,8 +213,8 @@ __device__ __forceinline__ void s4_store(int nimg, int L, int i0, int rows, cons
                     if (g >= nimg) break;
                     const float x = X.x[g][1][k][0], y = X.x[g][1][k][1];
                     const float u = in ? fmaxf(x, 0.f) : 0.f, v = in ? fmaxf(y, 0.f) : 0.f;
-                    *(LdsF2 *)(uintptr_t)(p0 + dk + g * kImg2Bytes) = f32x2v{u, v};
-                    *(LdsF2 *)(uintptr_t)(p1 - dk + g * kImg2Bytes) = f32x2v{v, u};
+                    *(LdsF2 *)(uintptr_t)(p0 + dk + g * IB) = f32x2v{u, v};
+                    *(LdsF2 *)(uintptr_t)(p1 - dk + g * IB) = f32x2v{v, u};
                 }
             }
         }
@@ -264,7 +266,7 @@ __device__ __forceinline__ void fill_slot_table(const ProjShape &P, const float2
 // Accumulate one strip for this wave's tasks and `IMG` images (a missing
 // second image reads its zero strips).  Rows pair from even image rows as in
 // accumulate_strip.
-template <int TPW, int IMG>
+template <int TPW, int IMG, int IB = kImg2Bytes>
 __device__ __forceinline__ void s4_accumulate(const LaneTask2 (&tasks)[TPW], int L,
                                               const float *lds, int i0, int rows,
                                               float (&acc)[IMG][TPW][4], int my_tasks) {
@@ -295,9 +297,9 @@ __device__ __forceinline__ void s4_accumulate(const LaneTask2 (&tasks)[TPW], int
                 const int pa = __mul24(j2, s16) + rbase;
 #pragma unroll
                 for (int g = 0; g < IMG; ++g) {
-                    const f32x4v K0 = *(const LdsF4 *)(uintptr_t)(pa + g * kImg2Bytes);
-                    const f32x4v K1 = *(const LdsF4 *)(uintptr_t)(pa + g * kImg2Bytes + 16);
-                    const f32x4v K2 = *(const LdsF4 *)(uintptr_t)(pa + g * kImg2Bytes + 32);
+                    const f32x4v K0 = *(const LdsF4 *)(uintptr_t)(pa + g * IB);
+                    const f32x4v K1 = *(const LdsF4 *)(uintptr_t)(pa + g * IB + 16);
+                    const f32x4v K2 = *(const LdsF4 *)(uintptr_t)(pa + g * IB + 32);
                     s[g][0] = fmaf(w2, K2.x, fmaf(w1, K1.x, fmaf(w0, K0.x, s[g][0])));
                     s[g][1] = fmaf(w2, K2.z, fmaf(w1, K1.z, fmaf(w0, K0.z, s[g][1])));
                     s[g][2] = fmaf(w2, K2.y, fmaf(w1, K1.y, fmaf(w0, K0.y, s[g][2])));
@@ -326,10 +328,10 @@ __device__ __forceinline__ void s4_accumulate(const LaneTask2 (&tasks)[TPW], int
 
 // Projection of `nimg` <= IMG images for the task group starting at task
 // tg0 (tasks tg0 + wave + t NW, t < TPW) into the accumulators; lds holds IMG
-// strip buffers kImg2Bytes apart, of R rows (R <= s4_rows<NT, KP>), ktab
+// strip buffers IB bytes apart, of R rows (R <= s4_rows<NT, KP>(L, IB)), ktab
 // (P.slots + 1 entries, 16-byte aligned) the slot constants.  bad[g] is set
 // when image g holds a non-finite value.
-template <int NT, int TPW, int IMG, int KP = 2>
+template <int NT, int TPW, int IMG, int KP = 2, int IB = kImg2Bytes>
 __device__ void project_images2(const float *const (&F)[IMG], int nimg, const ProjShape &P,
                                 const float2 *__restrict__ dtab, float *lds, float4 *ktab, int R,
                                 int tg0, float (&acc)[IMG][TPW][4], int (&bad)[IMG]) {
@@ -356,16 +358,16 @@ __device__ void project_images2(const float *const (&F)[IMG], int nimg, const Pr
 #pragma unroll
     for (int g = 0; g < IMG; ++g)
         for (int q = threadIdx.x; q < used; q += NT)
-            *(float4 *)(lds + g * (kImg2Bytes / 4) + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
+            *(float4 *)(lds + g * (IB / 4) + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
     Strip4Regs<IMG, KP> xs;
     s4_load<NT, IMG>(F, nimg, L, 0, G, xs);
     for (int i0 = 0; i0 < L; i0 += R) {
         const int rows = min(R, L - i0);
         __syncthreads();
-        s4_store<NT, IMG>(nimg, L, i0, rows, G, xs, lds, bad);
+        s4_store<NT, IMG, KP, IB>(nimg, L, i0, rows, G, xs, lds, bad);
         __syncthreads();
         if (i0 + R < L) s4_load<NT, IMG>(F, nimg, L, i0 + R, G, xs);
-        s4_accumulate<TPW, IMG>(tasks, L, lds, i0, rows, acc, my_tasks);
+        s4_accumulate<TPW, IMG, IB>(tasks, L, lds, i0, rows, acc, my_tasks);
     }
 #pragma unroll
     for (int g = 0; g < IMG; ++g) bad[g] = __syncthreads_or(bad[g]);
