@@ -19,6 +19,8 @@
 // The per-reference coefficients are laid out in the lane order, 16 complex
 // per lane and packed row.
 #pragma once
+#include <type_traits>
+
 #include "align_dev.h"
 
 namespace sw {
@@ -174,10 +176,13 @@ __device__ __forceinline__ void a128_row_spectrum(const float *varea, float2 *bu
 // Spectral dot of packed row p into the lane's 16 slots (slot tau 8 + s holds
 // frequency f = 2 l8 + tau + 16 s; f > 64 accumulates conj(Z) beta into
 // S(128 - f)); lane 0 of the group also adds conj(Z(0)) beta_p(0) and
-// Z(64) alpha_p(64).  bf16: operands rounded to bfloat16 first.
+// Z(64) alpha_p(64).  BF16: operands rounded to bfloat16 first (a compile-time
+// choice: as a run-time flag the compiler computes the roundings on both paths
+// and selects, about half the VALU work of a pass).
+template <bool BF16>
 __device__ __forceinline__ void a128_dot(float2 (&acc)[16], const float2 (&u0)[8],
                                          const float2 (&u1)[8], const float2 *__restrict__ G,
-                                         const float2 *__restrict__ GX, int p, int l8, int bf16) {
+                                         const float2 *__restrict__ GX, int p, int l8) {
     const float4 *gp = (const float4 *)(G + (int64_t)p * kA128Slots + l8 * 16);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -187,7 +192,7 @@ __device__ __forceinline__ void a128_dot(float2 (&acc)[16], const float2 (&u0)[8
             const int slot = 2 * k + h, tau = slot >> 3, s = slot & 7;
             float2 z = tau ? u1[s] : u0[s];
             float2 c = h ? make_float2(gq.z, gq.w) : make_float2(gq.x, gq.y);
-            if (bf16) {
+            if constexpr (BF16) {
                 z = bf16r2(z);
                 c = bf16r2(c);
             }
@@ -200,7 +205,7 @@ __device__ __forceinline__ void a128_dot(float2 (&acc)[16], const float2 (&u0)[8
         // f = 0 also takes conj(Z) beta_p(0); f = 64 also takes Z alpha_p(64)
         float2 z0 = u0[0], z4 = u0[4];
         float2 c0 = GX[2 * p], c4 = GX[2 * p + 1];
-        if (bf16) {
+        if constexpr (BF16) {
             z0 = bf16r2(z0);
             z4 = bf16r2(z4);
             c0 = bf16r2(c0);
@@ -243,7 +248,8 @@ struct A128Job {
     int Q, L, mode, bf16, top_k, status;
 };
 
-template <int NT>
+// BF16 is job.bf16 as a compile-time choice.
+template <int NT, bool BF16>
 __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
     constexpr int n = 128, NW = NT / 64, NG = NW * 8;  // lane groups per block
     float2 *tw = sm.tw, *xb = sm.xb, *S = sm.S;
@@ -272,7 +278,6 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
     const float *U = job.U, *V = job.V;
     const float2 *G = job.G, *GX = job.GX;
     const double *au = job.au, *av = job.av;
-    const int bf16 = job.bf16;
     const double2 *tw64 = job.d64;
     Result *res = job.res;
     float *curve = job.curve;
@@ -303,7 +308,11 @@ __device__ void align128_pair(const A128Job &job, A128Lds<NT> &sm) {
         const int p = pbase + grp;
         float2 u0[8], u1[8];
         a128_row_spectrum(varea, buf, tw, grp, l8, u0, u1);
-        if (p < P2) a128_dot(acc, u0, u1, G, GX, p, l8, bf16);
+        // an opaque copy of l8: the coefficient address is formed per
+        // iteration rather than held (or spilled) across the loop
+        int l8o = l8;
+        asm volatile("" : "+v"(l8o));
+        if (p < P2) a128_dot<BF16>(acc, u0, u1, G, GX, p, l8o);
     }
     // --- partial sums of every lane group to LDS, then S(w) for w = 0..64
 #pragma unroll
@@ -560,16 +569,22 @@ __device__ void align128_wave(const A128Job &job, float2 *xb, const float2 *tw) 
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = make_float2(0.f, 0.f);
     stage(0);
-    for (int pbase = 0; pbase < P2; pbase += 8) {
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this stage's copies have landed
-        wave_lds_sync();
-        const int p = pbase + grp;
-        float2 u0[8], u1[8];
-        a128_row_spectrum<true>(varea, buf, tw, grp, l8, u0, u1, [&]() {
-            if (pbase + 8 < P2) stage(2 * (pbase + 8));
-        });
-        if (p < P2) a128_dot(acc, u0, u1, job.G, job.GX, p, l8, job.bf16);
-    }
+    auto pass = [&](auto bf16) {
+        for (int pbase = 0; pbase < P2; pbase += 8) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this stage's copies have landed
+            wave_lds_sync();
+            const int p = pbase + grp;
+            float2 u0[8], u1[8];
+            a128_row_spectrum<true>(varea, buf, tw, grp, l8, u0, u1, [&]() {
+                if (pbase + 8 < P2) stage(2 * (pbase + 8));
+            });
+            if (p < P2) a128_dot<decltype(bf16)::value>(acc, u0, u1, job.G, job.GX, p, l8);
+        }
+    };
+    if (job.bf16)
+        pass(std::true_type{});
+    else
+        pass(std::false_type{});
 
     // --- the groups' partial sums, then S(w): lane t forms T(t) and
     // T(t + 64), S(w) = T(w) + T(128 - w) for 1 <= w <= 63, S(0) = T(0),

@@ -18,6 +18,7 @@
 // twiddles from the angle table, which equals e^{-2 pi i m / n}); the two
 // real spectra are separated from the packed one by conjugate symmetry.
 #pragma once
+#include <type_traits>
 #include "fft_dev.h"
 
 namespace sw {
@@ -217,26 +218,34 @@ __device__ void align_pair_block(const PairJob &job, Geo g, int mode, int bf16, 
         load_packed<NT>(Z0, V, n, p0, rows);
         __syncthreads();
         const float2 *Z = fft_rows<NT>(Z0, Z1, rows, n, tw);
-        for (int it = threadIdx.x; it < Wn * G; it += NT) {
-            const int w = it / G, gg = it - w * G;
-            float2 s = Sacc[it];
-            for (int pl = gg; pl < rows; pl += G) {
-                float2 xe, xo;
-                unpack(Z, pl, n, w, xe, xo);
-                const float4 uu = *(const float4 *)(Uh + (int64_t)w * Q + 2 * (p0 + pl));
-                float2 ue = make_float2(uu.x, uu.y), uo = make_float2(uu.z, uu.w);
-                if (bf16) {
-                    xe = bf16r2(xe);
-                    xo = bf16r2(xo);
-                    ue = bf16r2(ue);
-                    uo = bf16r2(uo);
+        // the rounding to bf16 as a compile-time choice: as a run-time flag
+        // the compiler rounds on both paths and selects
+        auto dot = [&](auto round) {
+            for (int it = threadIdx.x; it < Wn * G; it += NT) {
+                const int w = it / G, gg = it - w * G;
+                float2 s = Sacc[it];
+                for (int pl = gg; pl < rows; pl += G) {
+                    float2 xe, xo;
+                    unpack(Z, pl, n, w, xe, xo);
+                    const float4 uu = *(const float4 *)(Uh + (int64_t)w * Q + 2 * (p0 + pl));
+                    float2 ue = make_float2(uu.x, uu.y), uo = make_float2(uu.z, uu.w);
+                    if constexpr (decltype(round)::value) {
+                        xe = bf16r2(xe);
+                        xo = bf16r2(xo);
+                        ue = bf16r2(ue);
+                        uo = bf16r2(uo);
+                    }
+                    // conj(ue) * xe + conj(uo) * xo
+                    s.x += ue.x * xe.x + ue.y * xe.y + uo.x * xo.x + uo.y * xo.y;
+                    s.y += ue.x * xe.y - ue.y * xe.x + uo.x * xo.y - uo.y * xo.x;
                 }
-                // conj(ue) * xe + conj(uo) * xo
-                s.x += ue.x * xe.x + ue.y * xe.y + uo.x * xo.x + uo.y * xo.y;
-                s.y += ue.x * xe.y - ue.y * xe.x + uo.x * xo.y - uo.y * xo.x;
+                Sacc[it] = s;
             }
-            Sacc[it] = s;
-        }
+        };
+        if (bf16)
+            dot(std::true_type{});
+        else
+            dot(std::false_type{});
     }
     __syncthreads();
     float2 *S = Z0;  // reuse

@@ -21,7 +21,9 @@ __global__ __launch_bounds__(256) void k_gamma128(const float2 *__restrict__ spe
     else gamx[rp * 2 + (slot - kA128Slots)] = c;
 }
 
-template <int NT>
+// BF16: the launch's a.bf16, one instance each so that either has its own
+// register allocation.
+template <int NT, bool BF16>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_align128(
     PairArgs a, Geo g, const float2 *__restrict__ gam, const float2 *__restrict__ gamx,
     const float2 *__restrict__ tw32, const double2 *__restrict__ tw64) {
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     else if (isnan(job.au[0]) || isnan(job.av[0])) status = 2;
     else if (!(job.au[0] > 0.0) || !(job.av[0] > 0.0)) status = 1;
     job.status = status;
-    align128_pair<NT>(job, sm);
+    align128_pair<NT, BF16>(job, sm);
 }
 
 // One pair per wave (align128_wave): NW waves per block share the angle table.
@@ -125,8 +127,12 @@ hipError_t launch_align128(const PairArgs &a, Geo g, const AngleTable &t, float2
         return hipGetLastError();
     }
     constexpr int NT = 256;  // 4 waves, four blocks per compute unit
-    hipLaunchKernelGGL((k_align128<NT>), dim3((unsigned)P), dim3(NT), 0, s, a, g, gam, gamx, t.d32,
-                       t.d64);
+    if (a.bf16)
+        hipLaunchKernelGGL((k_align128<NT, true>), dim3((unsigned)P), dim3(NT), 0, s, a, g, gam,
+                           gamx, t.d32, t.d64);
+    else
+        hipLaunchKernelGGL((k_align128<NT, false>), dim3((unsigned)P), dim3(NT), 0, s, a, g, gam,
+                           gamx, t.d32, t.d64);
     return hipGetLastError();
 }
 
