@@ -425,6 +425,10 @@ def summarize(argv):
       summarize hbm FETCH_DIR WRITE_DIR "command"  HBM bytes per dispatch of the
           path's kernels, each counter scaled by what it reads for the plain
           512 MiB elementwise kernel of --copy-probe (512 MiB read + written)
+      summarize rdreq PMC_DIR "command"            bytes read from memory per dispatch
+          from the L2's read-request counts by size (128/64/32 B): a check of
+          the FETCH_SIZE calibration (gfx950's FETCH_SIZE counts a 128-byte
+          request as 64 bytes when TCC_BUBBLE stays zero)
       summarize mfma PMC_DIR "command"             MFMA counters of k_corr_mfma
       summarize sq PMC_DIR[,PMC_DIR2] "command"    SQ counters of k_tables2
       summarize stats TRACE_DIR "command"          kernel durations
@@ -477,6 +481,25 @@ def summarize(argv):
                   f"fetch_kib: {fk:.1f}\nwrite_kib: {wk:.1f}\n"
                   f"traffic_bytes: {1024 * (fk * ff + wk * wf):.0f}\n"
                   f"sources_sha256: {sources_sha256(k)}")
+    elif kind == "rdreq":
+        agg = counters(rest[0])
+        sizes = (("TCC_EA0_RDREQ_128B_sum", 128), ("TCC_EA0_RDREQ_64B_sum", 64),
+                 ("TCC_EA0_RDREQ_32B_sum", 32))
+
+        def read_bytes(a):
+            return sum(w * per_dispatch(a, c) for c, w in sizes)
+
+        cp = pick(agg, "neg_kernel")
+        print(f"[copy]\nkernel: {cp[0][:80]}\nbytes_read: {read_bytes(cp[2]):.0f}\n"
+              f"bytes_known: {512 << 20}\nTCC_BUBBLE_sum: {per_dispatch(cp[2], 'TCC_BUBBLE_sum'):.0f}")
+        for k in KERNEL_SOURCES:
+            b = pick(agg, f"sw::{k}<")
+            if not b:
+                continue
+            print(f"[{k}]\nkernel: {b[0][:100]}\ngrid: {b[1]}\ndispatches: {len(b[2]['dispatches'])}")
+            for c, _ in sizes:
+                print(f"{c}: {per_dispatch(b[2], c):.0f}")
+            print(f"bytes_read: {read_bytes(b[2]):.0f}\nsources_sha256: {sources_sha256(k)}")
     elif kind in ("mfma", "sq"):
         aggs = [counters(d) for d in rest[0].split(",")]
         k = "k_corr_mfma" if kind == "mfma" else "k_tables2"
