@@ -12,7 +12,9 @@ output.
   the even run's bitwise.
 * all ordered pairs of 2,000 images at L = n = Q = 64 (BF16 correlation,
   top-4 FP32 rescore): 300 sampled pairs (the four corners among them) against
-  the oracle; every self pair exactly 0 at lag 0."""
+  the oracle; every self pair exactly 0 at lag 0.
+* 50,000 images in uneven stacks (L from 64 to 256, tiles autotuned first):
+  8 images per stack against the oracle, tiled copies bitwise equal."""
 import numpy as np
 import pytest
 
@@ -135,3 +137,37 @@ def test_all_pairs_full_size(api, ctx, oracle):
     sub = {k: v[pairs[:, 0] * N + pairs[:, 1]] for k, v in g.items()}
     rep = parity.check(sub, o, L, parity.TAU_BF16, o["curve"])
     print(rep)
+
+
+def test_uneven_stacks_full_size(api, ctx, oracle, tmp_path):
+    """50,000 images in 21 stacks of L in {64, ..., 256} with their own
+    references, the tiles autotuned first as in the benchmark; each stack holds
+    200 rendered images tiled to its drawn size, so copy k of an image must
+    give bitwise its first copy's record; 8 images of every stack against the
+    oracle."""
+    import torch
+
+    stacks = synth.uneven_stacks(total=50000, cap_per_stack=200)
+    devs = []
+    for L, ref, imgs, size in stacks:
+        x = dev(imgs)
+        reps = (size + len(imgs) - 1) // len(imgs)
+        devs.append((dev(ref), x.repeat(reps, 1, 1)[:size].contiguous()))
+    assert sum(int(d[1].shape[0]) for d in devs) == 50000
+    api.autotune(ctx, sorted({s[0] for s in stacks}), out_json=str(tmp_path / "tiles.json"))
+    outs = api.align_stacks(ctx, devs, prec=1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(14)
+    for (L, ref, imgs, size), o in zip(stacks, outs):
+        rec = o["res"].cpu().numpy()
+        g = api.unpack_results(o["res"])
+        check_all(g, L)
+        m = len(imgs)
+        copies = rec.reshape(-1, 6)[: (size // m) * m].reshape(-1, m, 6)
+        assert np.all(copies == copies[:1]), L
+        tail = rec[(size // m) * m:]
+        assert np.array_equal(tail, rec[: len(tail)]), L
+        S = np.unique(np.concatenate([[0, min(m, size) - 1],
+                                      rng.choice(min(m, size), 6, replace=False)]))
+        orc = oracle.align_images(ref, imgs[S], L, L, want_curve=True)
+        parity.check({k: v[S] for k, v in g.items()}, orc, L, parity.TAU_BF16, orc["curve"])
