@@ -257,20 +257,23 @@ static hipError_t launch_tables2_t(const float *img, int64_t N, const TablesShap
     return launch_tables2_q<NT, TPW, kQuantWave, IB>(img, N, T, lds, t, qt, aux, s);
 }
 
-// The two-image kernel for w tasks per wave with image strips IB bytes apart
-// (the region holds both), if an instance fits; hipErrorNotSupported if not.
+// Launch the two-image kernel for w tasks per wave with image strips IB
+// bytes apart (the region holds both) into *e, if an instance fits; false
+// (nothing launched) if none does.
 template <int IB>
-static hipError_t launch_tables2_w(const float *img, int64_t N, Geo g, const TablesShape &T,
-                                   size_t lds, int w, const AngleTable &t, float *qt, double *aux,
-                                   hipStream_t s) {
+static bool launch_tables2_w(const float *img, int64_t N, Geo g, const TablesShape &T, size_t lds,
+                             int w, const AngleTable &t, float *qt, double *aux, hipStream_t s,
+                             hipError_t *e) {
     const int64_t table = (int64_t)g.Q * g.n;
-    if (w <= 2) return launch_tables2_t<512, 2, IB>(img, N, T, lds, t, qt, aux, s);
-    if (w <= 4) return launch_tables2_t<512, 4, IB>(img, N, T, lds, t, qt, aux, s);
-    if (w <= 5 && table >= kParkFloats<512, 5>)
-        return launch_tables2_t<512, 5, IB>(img, N, T, lds, t, qt, aux, s);
-    if (w <= 6 && table >= kParkFloats<512, 6>)
-        return launch_tables2_t<512, 6, IB>(img, N, T, lds, t, qt, aux, s);
-    return hipErrorNotSupported;
+    if (w <= 2) *e = launch_tables2_t<512, 2, IB>(img, N, T, lds, t, qt, aux, s);
+    else if (w <= 4) *e = launch_tables2_t<512, 4, IB>(img, N, T, lds, t, qt, aux, s);
+    else if (w <= 5 && table >= kParkFloats<512, 5>)
+        *e = launch_tables2_t<512, 5, IB>(img, N, T, lds, t, qt, aux, s);
+    else if (w <= 6 && table >= kParkFloats<512, 6>)
+        *e = launch_tables2_t<512, 6, IB>(img, N, T, lds, t, qt, aux, s);
+    else
+        return false;
+    return true;
 }
 
 hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t,
@@ -291,17 +294,16 @@ hipError_t launch_tables(const float *img, int64_t N, Geo g, const AngleTable &t
             // quantile phase keeps its column tile
             TablesShape T2;
             const size_t lds2 = tables_lds_bytes(g, 512, &T2, 2 * kImg2BytesWide / 4);
+            hipError_t e = hipSuccess;
             if (lds2 != 0 && lds2 <= 79 * 1024 && T2.TC >= T.TC) {
                 T2.P.perm = pp.perm;
                 T2.P.trow = pp.trow;
-                const hipError_t e =
-                    launch_tables2_w<kImg2BytesWide>(img, N, g, T2, lds2, w, t, qt, aux, s);
-                if (e != hipErrorNotSupported) return e;
+                if (launch_tables2_w<kImg2BytesWide>(img, N, g, T2, lds2, w, t, qt, aux, s, &e))
+                    return e;
             }
-            if (T.region_floats * 4 >= 2 * kImg2Bytes) {
-                const hipError_t e = launch_tables2_w<kImg2Bytes>(img, N, g, T, lds, w, t, qt, aux, s);
-                if (e != hipErrorNotSupported) return e;
-            }
+            if (T.region_floats * 4 >= 2 * kImg2Bytes &&
+                launch_tables2_w<kImg2Bytes>(img, N, g, T, lds, w, t, qt, aux, s, &e))
+                return e;
         }
         if (w <= 2) return launch_tables_t<512, 2>(img, N, T, lds, t, qt, aux, s);
         if (w <= 4) return launch_tables_t<512, 4>(img, N, T, lds, t, qt, aux, s);
