@@ -114,43 +114,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
 }
 
-// Fused ramp-filtered tables (ramp-filtered SW of Sec. 2.3): the projection
-// as above, written into LDS with a padded column stride, the ramp filter in
-// place on the matrix cores (ramp_dev.h; waves take tiles of 16 columns),
-// then the positive and the negative part of every column inverted into the
-// stacked [2Q][n] table, and aux = { smallest part mass (NaN for a NaN
-// value), E and a of the stacked table }.  Same results as sw_project,
-// sw_ramp and sw_quantiles_rf in sequence.
-template <int NT, int TPW, int NS>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWaves<NT, TPW>, NT <= 256 ? 2 : 4))) void k_tables_rf(
-    const float *__restrict__ img, int64_t N, TablesShape T, const float2 *__restrict__ d32,
-    const double2 *__restrict__ d64, const float *__restrict__ hx, float *__restrict__ qt,
-    double *__restrict__ aux) {
-    constexpr int NW = NT / 64, LP = 4 * NS, HX = 2 * LP - 1;
-    extern __shared__ __align__(16) double ldsd[];
+// The ramp-filtered tail of one image whose projections sit in `region`
+// (columns L + 4 floats apart): the ramp filter in place on the matrix cores
+// (waves take tiles of 16 columns), the positive and the negative part of
+// every column inverted into the stacked [2Q][n] table U, and aux (nullable)
+// = { smallest part mass (NaN for a NaN value), E and a of the stacked
+// table }.  hs: the filter taps in LDS.
+template <int NT, int NS>
+__device__ void rf_image_tail(const TablesShape &T, float *region, const float *hs,
+                              const double2 *__restrict__ d64, float *Ut, double *colS, float *U,
+                              double *A) {
+    constexpr int NW = NT / 64;
     __shared__ double partA[2][4];
     __shared__ double wmin[NW];
     __shared__ int wnan[NW];
-    const int64_t g = blockIdx.x;
-    if (g >= N) return;
     const ProjShape &P = T.P;
     const int L = P.L, n = P.n, Q = T.Q, ldp = L + 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float *region = (float *)ldsd;
-    double *colS = ldsd + T.region_floats / 2;
-    float *Ut = (float *)(colS + 2 * n);
-    float *hs = Ut + Q * (T.TC + 1);
-    const float *F = img + g * (int64_t)L * L;
-    int bad = 0;
-    // columns ldp = L + 4 floats apart: the filter's 16 columns x 4 bins of
-    // one fragment read fall in distinct banks; four-kind strips, the slot
-    // table in the column-sum area
-    project_image4<NT, TPW>(F, P, d32, region, (float4 *)colS, strip4_rows_max(L), bad,
-                            [&](int k, int b, float v) { region[k * ldp + b] = v; });
-    if (bad)
-        for (int t = threadIdx.x; t < n * ldp; t += NT) region[t] = __int_as_float(0x7fc00000);
-    for (int i = threadIdx.x; i < HX; i += NT) hs[i] = hx[i];
-    __syncthreads();
     for (int tile = wave; tile < (n + 15) / 16; tile += NW) {
         const int c0 = 16 * tile;
         ramp_tile<NS>(
@@ -160,7 +140,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
             });
     }
     __syncthreads();
-    float *U = qt + g * (int64_t)2 * Q * n;
     quantile_phase<NT>([&](int k, int b) { return fmaxf(region[k * ldp + b], 0.f); }, L, n, Q,
                        T.levels, T.TC, d64, Ut, colS, U, partA[0]);
     quantile_phase<NT>([&](int k, int b) { return fmaxf(-region[k * ldp + b], 0.f); }, L, n, Q,
@@ -186,18 +165,117 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWave
         wnan[wave] = nan;
     }
     __syncthreads();
-    if (threadIdx.x == 0 && aux) {
+    if (threadIdx.x == 0 && A) {
         double m = wmin[0];
         int nb = wnan[0];
         for (int w = 1; w < NW; ++w) {
             m = fmin(m, wmin[w]);
             nb |= wnan[w];
         }
-        double *A = aux + 4 * g;
         A[0] = nb ? __longlong_as_double(0x7ff8000000000000LL) : m;
         A[1] = partA[0][1] + partA[1][1];
         A[2] = 0.5 * (partA[0][2] + partA[1][2]);
         A[3] = 0.5 * (partA[0][3] + partA[1][3]);
+    }
+}
+
+// Fused ramp-filtered tables (ramp-filtered SW of Sec. 2.3): the projection
+// as above, written into LDS with a padded column stride, the ramp filter in
+// place on the matrix cores (ramp_dev.h; waves take tiles of 16 columns),
+// then the positive and the negative part of every column inverted into the
+// stacked [2Q][n] table, and aux = { smallest part mass (NaN for a NaN
+// value), E and a of the stacked table }.  Same results as sw_project,
+// sw_ramp and sw_quantiles_rf in sequence.
+template <int NT, int TPW, int NS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kProjMinWaves<NT, TPW>, NT <= 256 ? 2 : 4))) void k_tables_rf(
+    const float *__restrict__ img, int64_t N, TablesShape T, const float2 *__restrict__ d32,
+    const double2 *__restrict__ d64, const float *__restrict__ hx, float *__restrict__ qt,
+    double *__restrict__ aux) {
+    constexpr int LP = 4 * NS, HX = 2 * LP - 1;
+    extern __shared__ __align__(16) double ldsd[];
+    const int64_t g = blockIdx.x;
+    if (g >= N) return;
+    const ProjShape &P = T.P;
+    const int L = P.L, n = P.n, Q = T.Q, ldp = L + 4;
+    float *region = (float *)ldsd;
+    double *colS = ldsd + T.region_floats / 2;
+    float *Ut = (float *)(colS + 2 * n);
+    float *hs = Ut + Q * (T.TC + 1);
+    const float *F = img + g * (int64_t)L * L;
+    int bad = 0;
+    // columns ldp = L + 4 floats apart: the filter's 16 columns x 4 bins of
+    // one fragment read fall in distinct banks; four-kind strips, the slot
+    // table in the column-sum area
+    project_image4<NT, TPW>(F, P, d32, region, (float4 *)colS, strip4_rows_max(L), bad,
+                            [&](int k, int b, float v) { region[k * ldp + b] = v; });
+    if (bad)
+        for (int t = threadIdx.x; t < n * ldp; t += NT) region[t] = __int_as_float(0x7fc00000);
+    for (int i = threadIdx.x; i < HX; i += NT) hs[i] = hx[i];
+    __syncthreads();
+    rf_image_tail<NT, NS>(T, region, hs, d64, Ut, colS, qt + g * (int64_t)2 * Q * n,
+                          aux ? aux + 4 * g : nullptr);
+}
+
+// The same for two images per block (as k_tables2): the two images'
+// projections from the same strips and weights (strips kImg2Bytes apart),
+// held in registers (the second image's parked in its own output table,
+// 2Qn floats, during the first image's tail), then image by image written
+// into the region with the padded column stride, filtered and inverted.
+// Bitwise the results of k_tables_rf.
+template <int NT, int TPW, int NS>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_tables2_rf(
+    const float *__restrict__ img, int64_t N, TablesShape T, const float2 *__restrict__ d32,
+    const double2 *__restrict__ d64, const float *__restrict__ hx, float *__restrict__ qt,
+    double *__restrict__ aux) {
+    constexpr int NW = NT / 64, LP = 4 * NS, HX = 2 * LP - 1;
+    extern __shared__ __align__(16) double ldsd[];
+    const int64_t g0 = 2 * (int64_t)blockIdx.x;
+    if (g0 >= N) return;
+    const int nimg = N - g0 >= 2 ? 2 : 1;
+    const ProjShape &P = T.P;
+    const int L = P.L, n = P.n, Q = T.Q, ldp = L + 4;
+    float *region = (float *)ldsd;
+    double *colS = ldsd + T.region_floats / 2;
+    float *Ut = (float *)(colS + 2 * n);
+    float *hs = Ut + Q * (T.TC + 1);
+    const float *F[2] = {img + g0 * (int64_t)L * L, img + (g0 + nimg - 1) * (int64_t)L * L};
+    float acc[2][TPW][4];
+    int bad[2];
+    // the filter taps sit past the quantile tile, out of the strips' way
+    for (int i = threadIdx.x; i < HX; i += NT) hs[i] = hx[i];
+    project_images2<NT, TPW, 2>(F, nimg, P, d32, region, (float4 *)colS, s4_rows<NT>(L), 0, acc,
+                                bad);
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float *park = qt + (g0 + 1) * (int64_t)2 * Q * n + threadIdx.x;
+    if (kParkFloats<NT, TPW> > 0 && nimg == 2) {
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) park[(4 * t + v) * NT] = acc[1][t][v];
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        if (g < nimg) {  // block-uniform
+            if (kParkFloats<NT, TPW> > 0 && g == 1) {
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int t = 0; t < TPW; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[1][t][v] = park[(4 * t + v) * NT];
+            }
+            __syncthreads();  // strips, or the previous image's columns, no longer read
+                              // (and every parked value is back)
+            if (!bad[g])
+                emit_outputs<TPW>(P, 0, wave, NW, lane, acc[g],
+                                  [&](int k, int b, float v) { region[k * ldp + b] = v; });
+            else
+                for (int t = threadIdx.x; t < n * ldp; t += NT)
+                    region[t] = __int_as_float(0x7fc00000);
+            __syncthreads();
+            rf_image_tail<NT, NS>(T, region, hs, d64, Ut, colS,
+                                  qt + (g0 + g) * (int64_t)2 * Q * n,
+                                  aux ? aux + 4 * (g0 + g) : nullptr);
+        }
     }
 }
 
@@ -366,9 +444,41 @@ static hipError_t launch_tables_rf_t(const float *img, int64_t N, const TablesSh
     return hipGetLastError();
 }
 
+template <int NT, int TPW, int NS>
+static hipError_t launch_tables2_rf_t(const float *img, int64_t N, const TablesShape &T,
+                                      size_t lds, const AngleTable &t, const float *hx, float *qt,
+                                      double *aux, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_tables2_rf<NT, TPW, NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        152 * 1024);
+    (void)attr;
+    hipLaunchKernelGGL((k_tables2_rf<NT, TPW, NS>), dim3((unsigned)((N + 1) / 2)), dim3(NT), lds,
+                       s, img, N, T, t.d32, t.d64, hx, qt, aux);
+    return hipGetLastError();
+}
+
+// The two-image ramp-filtered kernel for w tasks per wave into *e, if an
+// instance fits (the second image's accumulators park in its 2Qn-float
+// table); false (nothing launched) if none does.
+template <int NS>
+static bool launch_tables2_rf_w(const float *img, int64_t N, Geo g, const TablesShape &T,
+                                size_t lds, int w, const AngleTable &t, const float *hx, float *qt,
+                                double *aux, hipStream_t s, hipError_t *e) {
+    const int64_t table = 2 * (int64_t)g.Q * g.n;
+    if (w <= 2) *e = launch_tables2_rf_t<512, 2, NS>(img, N, T, lds, t, hx, qt, aux, s);
+    else if (w <= 4) *e = launch_tables2_rf_t<512, 4, NS>(img, N, T, lds, t, hx, qt, aux, s);
+    else if (w <= 5 && table >= kParkFloats<512, 5>)
+        *e = launch_tables2_rf_t<512, 5, NS>(img, N, T, lds, t, hx, qt, aux, s);
+    else if (w <= 6 && table >= kParkFloats<512, 6>)
+        *e = launch_tables2_rf_t<512, 6, NS>(img, N, T, lds, t, hx, qt, aux, s);
+    else
+        return false;
+    return true;
+}
+
 hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable &t,
                             const ProjPlan &pp, const float *hx, float *qt, double *aux,
-                            hipStream_t s) {
+                            hipStream_t s, int per_block) {
     if (N <= 0) return hipSuccess;
     TablesShape T;
     const size_t lds = tables_rf_lds_bytes(g, &T);
@@ -379,6 +489,12 @@ hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable
     T.P.trow = pp.trow;
     const int w = tasks_per_wave(T.P.ntasks, 512);
     const int LP = ramp_padded_length(g.L);
+    if (per_block == 2 && s4_supported(g.L) && T.region_floats * 4 >= 2 * kImg2Bytes) {
+        hipError_t e = hipSuccess;
+        if (LP == 64 ? launch_tables2_rf_w<16>(img, N, g, T, lds, w, t, hx, qt, aux, s, &e)
+                     : launch_tables2_rf_w<32>(img, N, g, T, lds, w, t, hx, qt, aux, s, &e))
+            return e;
+    }
     if (LP == 64) {
         if (w <= 2) return launch_tables_rf_t<512, 2, 16>(img, N, T, lds, t, hx, qt, aux, s);
         if (w <= 4) return launch_tables_rf_t<512, 4, 16>(img, N, T, lds, t, hx, qt, aux, s);

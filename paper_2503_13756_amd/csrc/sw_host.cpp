@@ -1009,7 +1009,8 @@ sw_status sw_tables_rf(void *ctx, const float *img, int64_t N, const sw_geom *g,
     hipStream_t s = (hipStream_t)stream;
     const bool small = c->small(N);
     if (!small && sw::tables_rf_fused_fits(geo)) {
-        hipError_t e = sw::launch_tables_rf(img, N, geo, *t, *pp, hx, qt, aux, s);
+        hipError_t e =
+            sw::launch_tables_rf(img, N, geo, *t, *pp, hx, qt, aux, s, c->tables_per_block);
         return e == hipSuccess ? SW_OK : hip_fail(e, "k_tables_rf launch");
     }
     // projections of a chunk of images in scratch, filtered in place, then

@@ -99,11 +99,12 @@ int ramp_padded_length(int L);
 hipError_t launch_ramp(const float *src, float *dst, int64_t C, int L, const float *hx,
                        hipStream_t s);
 // Fused image -> stacked ramp-filtered tables, for geometries where
-// tables_rf_fused_fits() holds; hx as for launch_ramp.
+// tables_rf_fused_fits() holds; hx as for launch_ramp; per_block as for
+// launch_tables.
 bool tables_rf_fused_fits(Geo g);
 hipError_t launch_tables_rf(const float *img, int64_t N, Geo g, const AngleTable &t,
                             const ProjPlan &pp, const float *hx, float *qt, double *aux,
-                            hipStream_t s);
+                            hipStream_t s, int per_block = 2);
 // sw2sq of the valid results, and the curve, times f.
 hipError_t launch_scale_results(Result *out, int64_t P, float *curve, int n, float f,
                                 hipStream_t s);

@@ -30,6 +30,21 @@ def ctx(api):
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_fused(api, tmp_path_factory):
+    """Contexts that take the fused tables kernels at any batch size: two
+    images per block where the geometry allows it, and one."""
+    out = {}
+    for name, txt in (("two", '{"small_batch": 0}'),
+                      ("one", '{"small_batch": 0, "tables_images_per_block": 1}')):
+        path = tmp_path_factory.mktemp("tune") / f"{name}.json"
+        path.write_text(txt)
+        out[name] = api.Context(0, tune_json=str(path))
+    yield out
+    for c in out.values():
+        c.close()
+
+
 def dev(x):
     import torch
 
@@ -149,20 +164,24 @@ def test_rf_status_and_validation(api, ctx):
 
 @pytest.mark.parametrize("kind", ["clean", "raw"])
 @pytest.mark.parametrize("L,n,Q", [(64, 64, 64), (128, 128, 128), (60, 48, 36), (120, 96, 64)])
-def test_tables_rf_fused_equals_staged(api, ctx, oracle, L, n, Q, kind):
-    """The fused ramp-filtered tables kernel (projection, filter and both
-    inversions in LDS) gives bitwise the tables and aux of sw_project,
-    sw_ramp and sw_quantiles_rf in sequence; on raw inputs its tables also
-    match the oracle's, which clips and masks the images itself."""
+def test_tables_rf_fused_equals_staged(api, ctx, ctx_fused, oracle, L, n, Q, kind):
+    """The fused ramp-filtered tables kernels (projection, filter and both
+    inversions in LDS; two images per block, the odd count leaving the last
+    block one, and one image per block) give bitwise the tables and aux of
+    sw_project, sw_ramp and sw_quantiles_rf in sequence; on raw inputs the
+    tables also match the oracle's, which clips and masks the images itself."""
     if kind == "raw":
-        _, imgs = synth.make_raw_stack(1300 + L, L, 6)
+        _, imgs = synth.make_raw_stack(1300 + L, L, 7)
     else:
-        _, imgs = blob_stack(L, 6, 1300 + L)
+        _, imgs = blob_stack(L, 7, 1300 + L)
     x = dev(imgs)
-    q1, a1 = api.tables(ctx, x, n, Q, ramp=True)
+    q1, a1 = api.tables(ctx_fused["two"], x, n, Q, ramp=True)
     q2, a2 = api.quantiles(ctx, api.ramp(ctx, api.project(ctx, x, n)), Q, ramp=True)
-    assert np.array_equal(q1.cpu().numpy(), q2.cpu().numpy())
-    assert np.array_equal(a1.cpu().numpy(), a2.cpu().numpy())
+    q3, a3 = api.tables(ctx_fused["one"], x, n, Q, ramp=True)
+    q4, a4 = api.tables(ctx, x, n, Q, ramp=True)  # a small batch: the split launches
+    for q, a in ((q2, a2), (q3, a3), (q4, a4)):
+        assert np.array_equal(q1.cpu().numpy(), q.cpu().numpy())
+        assert np.array_equal(a1.cpu().numpy(), a.cpu().numpy())
     if kind == "raw":
         # the projections' FP32 rounding moves the signed parts' quantiles
         # where a part's CDF is nearly flat, so the table check is on the
