@@ -93,7 +93,7 @@ def test_autotune_table_roundtrip(api, ctx, tmp_path):
     assert set(tiles) == {"64", "128"}
     for L, v in tiles.items():
         assert 1 <= v["R"] <= int(L) and v["ms"] > 0
-        assert v.get("tpw", 5) in (5, 6) and v.get("align_bpc", 8) in (2, 4, 6, 8)
+        assert v.get("tpw", 5) in (5, 6, 9) and v.get("align_bpc", 8) in (2, 4, 6, 8)
     c2 = api.Context(0, tune_json=path)
     data = [stack(L, N, 2300 + i) for i, (L, N) in enumerate(SIDES[:3])]
     a = api.align_stacks(c2, [(dev(r), dev(x)) for r, x in data])
