@@ -554,6 +554,11 @@ __device__ void align128_wave(const A128Job &job, float2 *xb, const float2 *tw) 
     // current rows and the transpose buffer have been read, so that they fly
     // during the last transforms and the spectral dot.
     auto stage = [&](int r0) {
+        // the copies write the LDS behind the ds_read path: every read of
+        // the area (the staged rows and the transpose buffers overlap it)
+        // must have returned first, or a copy that lands early overwrites
+        // rows still to be read
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int r = min(r0 + 2 * i, Q - 2);  // Q is even
@@ -690,6 +695,7 @@ __device__ void align128_wave(const A128Job &job, float2 *xb, const float2 *tw) 
     // reference rows it needs are in flight while the current chunk is summed
     float *vb0 = (float *)xb, *vb1 = vb0 + 8 * n;
     auto issue = [&](int r0, float *dst, float2 (&u)[8]) {
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): earlier reads of dst have returned
 #pragma unroll
         for (int q = 0; q < 4; ++q)  // 1 KiB = two rows per copy (Q is even)
             if (r0 + 2 * q < Q)
