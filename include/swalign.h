@@ -115,12 +115,14 @@ typedef struct {
    path to a JSON file with optional keys: "tiles" (the table written by
    sw_autotune), "small_batch": calls on fewer images than this take the
    split launches (several blocks per image; default: the number of compute
-   units), and "align_kernel": "generic", which keeps sw_align_batch on the
-   LDS-FFT pair kernel for n_angles = 128 instead of the register-FFT one
-   (the two agree to FP32 rounding), or "block128", which runs the
-   register-FFT alignment with one pair per block instead of one pair per
-   wave (same arithmetic, sums in another order).  The first two change
-   launch shapes only, never results. */
+   units), "tables_images_per_block": 1 or 2 (default 2), the images one
+   block of the fused sw_tables / sw_tables_rf kernels projects from the same
+   strips where the geometry allows two, and "align_kernel": "generic", which
+   keeps sw_align_batch on the LDS-FFT pair kernel for n_angles = 128 instead
+   of the register-FFT one (the two agree to FP32 rounding), or "block128",
+   which runs the register-FFT alignment with one pair per block instead of
+   one pair per wave (same arithmetic, sums in another order).  The first
+   three change launch shapes only, never results. */
 /* Scratch: the context owns one scratch buffer (grown on demand) that the
    calls needing it share: sw_tables / sw_tables_rf when they take their
    chunked or small-batch path, sw_align_batch (except the max-sliced mode)
