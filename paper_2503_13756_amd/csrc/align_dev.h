@@ -28,14 +28,14 @@ namespace sw {
 // n = 256, so that seven blocks fit on a compute unit instead of two.
 constexpr int kFftElems = 1024;
 
-// bfloat16 round-to-nearest-even of a float, returned as a float
-__device__ __forceinline__ float bf16r(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return x;  // inf / nan unchanged
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xffff0000u);
+// bfloat16 round-to-nearest-even of two floats, returned as floats: one
+// v_cvt_pk_bf16_f32 for the pair (round to nearest even; equal to the bit
+// formula u + 0x7fff + ((u >> 16) & 1), truncated, on every non-NaN float),
+// then the halves shifted back
+__device__ __forceinline__ float2 bf16r2(float2 v) {
+    const __bf16 a = (__bf16)v.x, b = (__bf16)v.y;
+    return make_float2((float)a, (float)b);
 }
-__device__ __forceinline__ float2 bf16r2(float2 v) { return make_float2(bf16r(v.x), bf16r(v.y)); }
 
 // Load complex rows p0 .. p0+rows-1 of a [Q][n] real table: row p packs table
 // rows 2p (real part) and 2p+1 (imaginary part).
