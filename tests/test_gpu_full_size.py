@@ -171,3 +171,27 @@ def test_uneven_stacks_full_size(api, ctx, oracle, tmp_path):
                                       rng.choice(min(m, size), 6, replace=False)]))
         orc = oracle.align_images(ref, imgs[S], L, L, want_curve=True)
         parity.check({k: v[S] for k, v in g.items()}, orc, L, parity.TAU_BF16, orc["curve"])
+
+
+def test_ramp_filtered_full_size(api, ctx, oracle, headline):
+    """The ramp-filtered form of the headline workload (10,000 images, two
+    images per block in the fused ramp-filtered tables kernel): 24 sampled
+    images against the oracle (FP32 and the BF16 form), the sample's fused
+    tables bitwise those of the staged launches, every record valid."""
+    w, x, _, _, _, _ = headline
+    L, n, Q, N = w["L"], w["n"], w["Q"], len(w["imgs"])
+    rq, ra = api.tables(ctx, dev(w["ref"][None]), n, Q, ramp=True)
+    iq, ia = api.tables(ctx, x, n, Q, ramp=True)
+    rng = np.random.default_rng(15)
+    S = np.unique(np.concatenate([[0, 1, N - 2, N - 1], rng.choice(N, 20, replace=False)]))
+    imgs = w["imgs"][S]
+    q5, a5 = api.quantiles(ctx, api.ramp(ctx, api.project(ctx, dev(imgs), n)), Q, ramp=True)
+    assert np.array_equal(q5.cpu().numpy(), iq.cpu().numpy()[S])
+    assert np.array_equal(a5.cpu().numpy(), ia.cpu().numpy()[S])
+    o = oracle.align_images(w["ref"], imgs, n, Q, want_curve=True, ramp=True)
+    for prec in (0, 1):
+        res, _ = api.align_batch(ctx, rq, ra, iq, ia, L, prec=prec, ramp=True)
+        g = api.unpack_results(res)
+        check_all(g, n)
+        rep = parity.check({k: v[S] for k, v in g.items()}, o, L, parity.TAU_RF, o["curve"])
+        print(prec, rep)
