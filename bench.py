@@ -45,7 +45,7 @@ MFMA_FILE = os.path.join(PROFILES, "mfma_k_corr_mfma_all_pairs_2000.txt")
 STATS_FILE = os.path.join(PROFILES, "kernels_all_legs_stats.txt")
 KERNEL_SOURCES = {
     "k_tables2": ["k_tables.hip", "proj2_dev.h", "proj_dev.h", "quant_dev.h", "sw_internal.h"],
-    "k_project": ["k_project.hip", "proj2_dev.h", "proj_dev.h", "sw_internal.h"],
+    "k_project2": ["k_project.hip", "proj2_dev.h", "proj_dev.h", "sw_internal.h"],
     "k_quantile": ["k_quantile.hip", "quant_dev.h", "sw_internal.h"],
     "k_align128w": ["k_align128.hip", "align128_dev.h", "align_dev.h", "fft_dev.h",
                     "sw_internal.h"],
@@ -391,7 +391,7 @@ def stage_rooflines(line, N, L, n, Q):
 
     flops_proj = 4.0 * (n // 2) * M * N
     add("k_tables2", "alu", flops_proj, st["tables_imgs_ms"], "HIP events (images -> tables)")
-    add("k_project", "alu", flops_proj, st["staged_project_ms"], "HIP events (staged projection)")
+    add("k_project2", "alu", flops_proj, st["staged_project_ms"], "HIP events (staged projection)")
     add("k_quantile", "hbm", (4.0 * n * L + 4.0 * Q * n + 32.0) * N, st["staged_quantiles_ms"],
         "HIP events (staged quantiles)")
     add("k_align128w", "hbm", (4.0 * Q * n + 24.0) * N, st["align_ms"],
